@@ -1,0 +1,187 @@
+"""Pins for the oracle's SpMMV, Chebyshev filter, coefficients, SVQB, Rayleigh-Ritz
+and FD loop (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import chebyshev as npcheb
+from scipy import integrate
+
+import oracle as O
+from fd_inputs import int_block, start_block
+
+
+# ----------------------------------------------------------------- SpMMV ----
+@pytest.mark.parametrize("nb", [1, 3, 8, 16])
+def test_spmmv_vs_dense_matmul(nb):
+    A = O.hubbard(7, 3, 3, 1.0, 2.5)
+    X = start_block(A.D, nb, 5)
+    np.testing.assert_allclose(O.spmmv(A, X), A.dense() @ X, rtol=0, atol=1e-12)
+
+
+def test_spmmv_integer_exact():
+    A = O.anderson(6, 1.0, 0.0)
+    X = int_block(A.D, 8, 2)
+    Y = O.spmmv(A, X)
+    Yref = (A.dense().astype(np.int64) @ X.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(Y, Yref)
+
+
+# ---------------------------------------------------------- coefficients ----
+def test_jackson_normalisation_and_first_factor():
+    for n in (2, 10, 100, 800):
+        assert abs(O.jackson(n, 0) - 1.0) < 1e-15
+        N = n + 1
+        assert abs(O.jackson(n, 1) - math.cos(math.pi / (N + 1))) < 1e-15
+
+
+def test_jackson_kernel_positive_and_width():
+    """The Jackson-damped delta is a positive kernel of unit mass whose variance
+    at x = 0 approaches (pi / N)^2 (Weisse et al. RMP 2006)."""
+    n = 60
+    N = n + 1
+    x = np.cos(np.linspace(0, np.pi, 2001))
+    for y in (-0.7, 0.0, 0.31, 0.95):
+        mu = O.cheb_coeffs(1, y, 0.0, n)
+        p = npcheb.chebval(x, mu)
+        assert p.min() > -1e-12 * p.max()
+    mu0 = O.cheb_coeffs(1, 0.0, 0.0, 400)
+    # <x^2> under the weight 1/(pi sqrt(1-x^2)): x^2 = (T0 + T2)/2 and
+    # <T_k> = mu_k (1 + delta_k0)/2
+    var = 0.5 * (mu0[0] + 0.5 * mu0[2])
+    assert abs(var / (math.pi / 401) ** 2 - 1) < 0.02
+
+
+@pytest.mark.parametrize("a,b", [(-0.3, 0.2), (-1.0, -0.9), (0.05, 0.06)])
+def test_indicator_coefficients_by_quadrature(a, b):
+    n = 40
+    mu = O.cheb_coeffs(0, a, b, n)
+    for k in range(n + 1):
+        ck = integrate.quad(lambda th: math.cos(k * th), math.acos(b), math.acos(a),
+                            epsabs=1e-14)[0] * (1 if k == 0 else 2) / math.pi
+        assert abs(mu[k] - O.jackson(n, k) * ck) < 1e-13
+
+
+def test_window_polynomial_bounds_and_limit():
+    n = 400
+    mu = O.cheb_coeffs(0, -0.2, 0.3, n)
+    x = np.linspace(-1, 1, 4001)
+    p = npcheb.chebval(x, mu)
+    assert p.min() > -1e-12 and p.max() < 1 + 1e-12
+    # Jackson tails decay algebraically: ~1e-5 at a quarter-width inside,
+    # ~1e-7 half the window away from an edge at n = 400
+    assert abs(npcheb.chebval(0.05, mu) - 1) < 1e-4
+    assert abs(npcheb.chebval(0.8, mu)) < 1e-5
+
+
+# ---------------------------------------------------------------- filter ----
+def test_filter_chebyshev_identity():
+    """mu = e_n on diag(cos theta) gives T_n(cos theta) = cos(n theta)."""
+    theta = np.linspace(0.01, 3.1, 300)
+    A = O.diagonal(np.cos(theta))
+    V = start_block(A.D, 4, 1)
+    for n in (2, 3, 17, 100):
+        mu = np.zeros(n + 1)
+        mu[n] = 1.0
+        out = O.cheb_filter(A, V, mu, 1.0, 0.0)
+        np.testing.assert_allclose(out, np.cos(n * theta)[:, None] * V, atol=1e-11)
+
+
+def test_filter_diagonal_clenshaw():
+    lam = np.linspace(-3.0, 5.0, 257)
+    A = O.diagonal(lam)
+    alpha, beta = O.scaling(-3.0, 5.0)
+    mu = O.cheb_coeffs(0, -0.1, 0.2, 50)
+    V = start_block(A.D, 3, 2)
+    out = O.cheb_filter(A, V, mu, alpha, beta)
+    np.testing.assert_allclose(out, npcheb.chebval(alpha * lam + beta, mu)[:, None] * V,
+                               atol=1e-12)
+
+
+def test_filter_general_matrix_via_eigendecomposition():
+    A = O.hubbard(6, 3, 3, 1.0, 4.0)
+    lo, hi = O.gershgorin(A)
+    alpha, beta = O.scaling(lo, hi)
+    mu = O.cheb_coeffs(0, alpha * -1 + beta, alpha * 1 + beta, 60)
+    lam, Q = np.linalg.eigh(A.dense())
+    V = start_block(A.D, 5, 3)
+    want = Q @ (npcheb.chebval(alpha * lam + beta, mu)[:, None] * (Q.T @ V))
+    got = O.cheb_filter(A, V, mu, alpha, beta)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want) + 1e-13
+
+
+def test_filter_rejects_degree_below_two():
+    A = O.diagonal(np.ones(4))
+    with pytest.raises(ValueError):
+        O.cheb_filter(A, np.ones((4, 1)), np.ones(2), 1.0, 0.0)
+
+
+# ------------------------------------------------------------ SVQB / RR ----
+def test_svqb2_orthonormal_span_and_rank():
+    rng = np.random.default_rng(0)
+    V = rng.standard_normal((3000, 40)) @ np.diag(np.logspace(0, -6, 40))
+    Q, rank = O.svqb2(V)
+    assert rank == 40
+    assert np.abs(Q.T @ Q - np.eye(40)).max() < 1e-13
+    assert np.linalg.norm(V - Q @ (Q.T @ V)) <= 1e-12 * np.linalg.norm(V)
+    W = np.concatenate([V[:, :10], V[:, :10]], axis=1)
+    _, r2 = O.svqb(W)
+    assert r2 == 10
+
+
+def test_rayleigh_ritz_exact_on_eigenvectors():
+    lam = np.linspace(-2, 2, 50)
+    A = O.diagonal(lam)
+    idx = [3, 17, 30, 44]
+    V = np.eye(50)[:, idx]
+    theta, Vr, Wr, rho = O.rayleigh_ritz(A, V)
+    np.testing.assert_allclose(theta, lam[idx], atol=1e-15)
+    assert rho.max() < 1e-15
+
+
+def test_rayleigh_ritz_residuals_recomputed():
+    A = O.anderson(5, 1.0, 8.0)
+    V, _ = O.svqb2(start_block(A.D, 12, 4))
+    theta, Vr, Wr, rho = O.rayleigh_ritz(A, V)
+    fresh = np.linalg.norm(A.dense() @ Vr - Vr * theta, axis=0)
+    np.testing.assert_allclose(rho, fresh, atol=1e-13)
+
+
+# ---------------------------------------------------------------- FD loop ----
+def test_select_targets_window_and_ties():
+    th = np.array([-0.3, -0.1, 0.1, 0.2, 0.6, -0.6])
+    assert list(O.select_targets(th, -0.5, 0.5, 3)) == [1, 2, 3]
+    assert list(O.select_targets(th, -0.5, 0.5, 9)) == [1, 2, 3, 0]
+    assert list(O.select_targets(th, 0.0, 0.0, 2)) == [1, 2]
+
+
+def test_fd_fig2_diagonal_search_interval():
+    """Fig. 2: 1000 equidistant eigenvalues, N_t = 10, N_s = 20, target
+    [-0.01, 0.01].  A filter whose Jackson broadening fits the search interval
+    [-0.02, 0.02] converges; one sized for [-0.04, 0.04] (more than N_s
+    eigenvalues inside) does not within 20 iterations."""
+    lam = -1 + 2 * np.arange(1000) / 999
+    A = O.diagonal(lam)
+    V0 = start_block(1000, 20, 0)
+    for delta, ok in ((0.01, True), (0.03, False)):
+        n = math.ceil(math.pi * 2 / (2 * delta)) - 2
+        r = O.fd_solve(A, V0, -0.01, 0.01, 10, n, 1e-9, max_iter=20)
+        assert r.converged == ok
+        if ok:
+            want = lam[(lam >= -0.01) & (lam <= 0.01)]
+            np.testing.assert_allclose(r.evals, want, atol=1e-12)
+
+
+@pytest.mark.slow
+def test_fd_hubbard8_vs_dense():
+    """Hubbard L=8 (4 up, 4 down, U = 4): 16 eigenpairs nearest 0 in [-0.5, 0.5],
+    degree 100, N_s = 128, checked against dense diagonalisation."""
+    A = O.hubbard(8, 4, 4, 1.0, 4.0)
+    ev = np.linalg.eigvalsh(A.dense())
+    r = O.fd_solve(A, start_block(A.D, 128, 0), -0.5, 0.5, 16, 100, 1e-9, max_iter=80)
+    assert r.converged
+    want = np.sort(ev[np.argsort(np.abs(ev), kind="stable")[:16]])
+    assert np.abs(r.evals - want).max() <= 1e-10 * r.norm_H
+    assert r.resid.max() <= 1e-9 * r.norm_H
+    fresh = np.linalg.norm(O.spmmv(A, r.evecs) - r.evecs * r.evals, axis=0)
+    assert fresh.max() <= 1e-9 * r.norm_H
