@@ -1,0 +1,232 @@
+/*
+ * fd.h -- C ABI of libfd, an MI355X (gfx950) implementation of the hot path of
+ * filter diagonalization (FD) for sparse symmetric eigenproblems, following
+ * Alvermann, Hager & Fehske, "Orthogonal layers of parallelism in large-scale
+ * eigenvalue computations" (ACM TOPC; arXiv 2209.01974).
+ *
+ * The problem (Sec. 1, Sec. 2): a sparse real symmetric matrix A of dimension
+ * D; find the N_t eigenpairs nearest a target tau, or inside a target window
+ * [tau_l, tau_r], with N_s >= N_t search vectors, to a residual bound
+ * rho = ||A v - lambda v||_2.  FD repeats: orthogonalize the search block,
+ * one extra SpMV for the Ritz values (Rayleigh-Ritz), convergence test, then
+ * the Chebyshev polynomial filter V <- p[A] V (Alg. 1, Alg. 2 captions).
+ *
+ * Conventions for every call
+ *  - Every call returns fd_status; nothing throws across the ABI.  On any
+ *    error fd_last_error() returns a message (thread-local, valid until the
+ *    next failing call on the same thread).  On FD_ERR_INVALID no output has
+ *    been written.
+ *  - Dense blocks ("blocks of vectors") are row-major: entry i of vector j of
+ *    a block X with leading dimension ldx sits at X[i*ldx + j] (Sec. 3.1 asks
+ *    for row-major vector storage).  ld is counted in elements.  Blocks used by
+ *    the sparse kernels must be aligned to 16 bytes and ld must be a multiple
+ *    of the per-lane vector width (2 for FP64, 4 for FP32, or nb if nb is
+ *    smaller); 256-byte alignment is recommended.
+ *  - Pointers named *_dev are device pointers (HIP device memory of the
+ *    current device); pointers named *_host are host pointers.  Device blocks
+ *    are owned by the caller; the library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Kernel-level calls are asynchronous on it; calls that return host data
+ *    (fd_rayleigh_ritz, fd_orthog's rank, fd_solve) synchronize that stream.
+ *  - The library keeps one device workspace per process for the small dense
+ *    steps; calls from several host threads at once are not supported.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FD_OK = 0,
+    FD_ERR_INVALID = 1,       /* bad argument; outputs untouched             */
+    FD_ERR_OOM = 2,           /* host or device allocation failed            */
+    FD_ERR_HIP = 3,           /* a HIP runtime call failed                   */
+    FD_ERR_NOT_CONVERGED = 4, /* fd_solve: best pairs written, see stats     */
+    FD_ERR_BREAKDOWN = 5,     /* non-finite data or a factorization failed   */
+    FD_ERR_UNSUPPORTED = 6    /* valid request outside what is built         */
+} fd_status;
+
+typedef enum { FD_F64 = 0, FD_F32 = 1 } fd_dtype;
+typedef enum { FD_FMT_CSR = 0, FD_FMT_SELL = 1 } fd_format;
+typedef enum {
+    FD_HUBBARD_RING = 0, /* 1D Hubbard model, L sites, n_up + n_dn fermions  */
+    FD_ANDERSON_3D = 1,  /* 3D Anderson lattice, L^3 sites                   */
+    FD_DIAGONAL = 2,     /* A = diag(diag[0..n-1])                          */
+    FD_USER_CSR = 3      /* caller's CSR (D, rowptr, col, val)              */
+} fd_model;
+
+/* Parameters of the generated matrices.
+ * FD_HUBBARD_RING: H = -t sum_{<ij>,s} (c+_is c_js + h.c.) + U sum_i n_iu n_id
+ *   on L sites (3 <= L <= 62); periodic != 0 closes the ring (fermionic
+ *   boundary: the wrap bond carries (-1)^(N_s - 1) for N_s fermions of that
+ *   spin).  Basis: spin configurations are L-bit masks with N bits set, ranked
+ *   in increasing integer order; row = rank(up) * C(L, n_dn) + rank(down).
+ *   The diagonal U * (number of doubly occupied sites) is always stored.
+ *   D = C(L, n_up) C(L, n_dn) (the Hubbard dimension of Sec. 4.1).
+ * FD_ANDERSON_3D: site (x,y,z) -> x + L y + L^2 z, periodic nearest-neighbour
+ *   hopping -t, on-site energy W (u_i - 1/2), u_i the i-th output of
+ *   SplitMix64 seeded with `seed` (top 53 bits times 2^-53), L >= 3.
+ * FD_DIAGONAL: n entries from `diag` (host).
+ * FD_USER_CSR: D rows, rowptr[D+1] (int64), col (uint32, ascending per row),
+ *   val (double); host arrays, copied.  D < 2^32.                          */
+typedef struct {
+    fd_model model;
+    int32_t L, n_up, n_dn, periodic;
+    double t, U, W;
+    uint64_t seed;
+    int64_t n;              /* FD_DIAGONAL */
+    const double *diag;     /* FD_DIAGONAL */
+    int64_t D;              /* FD_USER_CSR */
+    const int64_t *rowptr;  /* FD_USER_CSR */
+    const uint32_t *col;    /* FD_USER_CSR */
+    const double *val;      /* FD_USER_CSR */
+} fd_model_params;
+
+typedef struct fd_matrix_s *fd_matrix; /* opaque, owned by the library */
+
+#define FD_BUILD_HOST_ONLY 1 /* build host arrays only; no device copy */
+
+/* Build the sparse matrix of the model (Sec. 3.1: A stored row-wise, uint32
+ * column indices, S_i = 4).  The canonical form is CSR with ascending columns
+ * and the diagonal always stored; FD_FMT_SELL additionally permutes rows into
+ * SELL-C-sigma: rows stably sorted by descending length inside windows of
+ * sigma rows (perm[new] = old), chunks of C rows (C a power of two, 1..64)
+ * stored column-major (entry j of chunk row r at chunk_ptr[c] + j*C + r),
+ * padded with value 0 and the row's own index as column; slots past D hold
+ * column 0.  Column indices keep the original numbering.  Unless
+ * FD_BUILD_HOST_ONLY is set, FP64 values, FP32 values (round to nearest
+ * even) and the index arrays are copied to the current device.  The
+ * Gershgorin interval of A is computed here.  *out receives a new handle.  */
+fd_status fd_build_matrix(const fd_model_params *params, fd_format fmt, int32_t C,
+                          int32_t sigma, int32_t flags, fd_matrix *out);
+
+/* D, stored non-zeros of the CSR form, stored slots of the device format
+ * (padding included), and the Gershgorin interval [lam_lo, lam_hi].  Any
+ * output pointer may be NULL.                                               */
+fd_status fd_matrix_info(fd_matrix m, int64_t *D, int64_t *nnz, int64_t *stored,
+                         double *lam_lo, double *lam_hi);
+
+/* Copy the canonical CSR into caller host arrays of D+1, nnz, nnz entries.  */
+fd_status fd_matrix_export_csr(fd_matrix m, int64_t *rowptr, uint32_t *col, double *val);
+
+/* Copy the SELL-C-sigma arrays (fmt == FD_FMT_SELL only) into caller host
+ * arrays: perm[D], chunk_ptr[nchunks+1], chunk_len[nchunks], col[stored],
+ * val[stored], nchunks = ceil(D / C).                                       */
+fd_status fd_matrix_export_sell(fd_matrix m, int32_t *perm, int64_t *chunk_ptr,
+                                int32_t *chunk_len, uint32_t *col, double *val);
+
+void fd_matrix_free(fd_matrix m);
+
+/* Block SpMV (SpMMV), Sec. 3.1 Eq. SpMVprocess for nb vectors at once:
+ * Y = A X, X and Y device blocks D x nb (row-major, ld as above, in dtype).
+ * FD_F32 uses the FP32 copy of the values and accumulates in FP32.
+ * nb in {1,2,4,8,16,32,64}.  X and Y must not overlap.                     */
+fd_status fd_spmmv(fd_matrix m, fd_dtype dtype, int32_t nb, const void *X_dev, int64_t ldx,
+                   void *Y_dev, int64_t ldy, void *stream);
+
+/* Chebyshev polynomial filter, Alg. 2 caption: V <- p[B] V with
+ * p(x) = sum_{k=0}^{degree} mu[k] T_k(x), B = alpha A + beta, degree >= 2,
+ * exactly `degree` SpMMVs per bundle.  V is a D x (nb * n_bundles) device
+ * block (ld ldv) filtered bundle by bundle (bundle b = columns
+ * [b nb, (b+1) nb)).  W1, W2: device workspaces of D rows, ld ldw.  If
+ * ldw >= nb * n_bundles all bundles run in one launch per degree step (each
+ * bundle uses its own columns of W1/W2); otherwise the bundles run one after
+ * another and W1, W2 need only nb columns.  mu_host holds degree+1 FP64
+ * coefficients (rounded to FP32 for FD_F32, as are alpha and beta).       */
+fd_status fd_cheb_filter(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t n_bundles,
+                         void *V_dev, int64_t ldv, const double *mu_host, int32_t degree,
+                         double alpha, double beta, void *W1_dev, void *W2_dev, int64_t ldw,
+                         void *stream);
+
+/* Chebyshev coefficients (host, FP64) of the window function, Sec. 2
+ * (p(x) = sum_k mu_k T_k(x)): kind 0 = indicator of [a, b] (scaled to
+ * [-1, 1]) with Jackson damping for degree+1 moments; kind 1 = Jackson-damped
+ * delta at a (b unused).  mu_host has degree+1 entries.                     */
+fd_status fd_cheb_coeffs(int32_t kind, double a, double b, int32_t degree, double *mu_host);
+
+/* G = X^T Y for device blocks X (D x m, ld ldx) and Y (D x n, ld ldy), FP64,
+ * on FP64 MFMA with a fixed-order two-stage reduction over D (bitwise
+ * reproducible).  G is a device m x n row-major block (ld ldg).  m, n <= 512.
+ * This is the Gram product of SVQB (Sec. 3, stack layout: V^t V).          */
+fd_status fd_gram(int64_t D, int32_t m, int32_t n, const double *X_dev, int64_t ldx,
+                  const double *Y_dev, int64_t ldy, double *G_dev, int64_t ldg, void *stream);
+
+/* X <- X Q in place, X a device D x m block (ld ldx), Q a device m x n
+ * row-major block (ld ldq), n <= m <= 512 (columns n..m-1 of X are left
+ * unchanged when n < m).  FP64 MFMA.                                        */
+fd_status fd_rotate(int64_t D, int32_t m, int32_t n, double *X_dev, int64_t ldx,
+                    const double *Q_dev, int64_t ldq, void *stream);
+
+/* Symmetric eigendecomposition of a small device matrix (n <= 512), FP64,
+ * cyclic parallel Jacobi on the GPU: S = U diag(w) U^t.  S_dev (ld lds) is
+ * overwritten; w_dev (n) ascending; U_dev (n x n, ld ldu) eigenvectors in
+ * columns.                                                                  */
+fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *U_dev,
+                  int64_t ldu, void *stream);
+
+#define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */
+#define FD_ORTHO_CHOLQR2 1 /* two Cholesky-QR passes, SVQB2 if one fails    */
+
+/* Orthonormalize the columns of the device block V (D x ns, ld ldv) in place,
+ * FP64 (Sec. 2: orthogonalization after the random start and after each
+ * filter; SVQB needs only the ns x ns Gram matrix V^t V).  Columns whose
+ * scaled Gram eigenvalue falls below 1e-14 of the largest are replaced by
+ * seeded random vectors and orthogonalized again; *rank (may be NULL)
+ * receives the number of columns kept.  ns <= 512.  Synchronizes stream.  */
+fd_status fd_orthog(int64_t D, int32_t ns, double *V_dev, int64_t ldv, int32_t method,
+                    uint64_t seed, int32_t *rank, void *stream);
+
+/* Rayleigh-Ritz step, Sec. 2 ("a single additional SpMV provides the Ritz
+ * values"): W = A V (FP64 SpMMV), H = V^t W, H = Y diag(theta) Y^t,
+ * V <- V Y, W <- W Y, rho_j = ||W_j - theta_j V_j||_2.  V must have
+ * orthonormal columns.  V, W: device D x ns blocks with the same ld; ns a
+ * multiple of nb (nb in {1,...,64}, the bundle width used for A V).
+ * theta_host, resid_host: ns entries, theta ascending.  Synchronizes.      */
+fd_status fd_rayleigh_ritz(fd_matrix m, int32_t ns, int32_t nb, double *V_dev, double *W_dev,
+                           int64_t ld, double *theta_host, double *resid_host, void *stream);
+
+typedef struct {
+    double tau_lo, tau_hi; /* target window; tau_lo == tau_hi: nearest tau   */
+    int32_t n_target;      /* N_t                                             */
+    int32_t n_search;      /* N_s, a multiple of nb, N_t <= N_s <= 512        */
+    int32_t nb;            /* bundle width for the filter and SpMMV           */
+    int32_t degree;        /* filter degree n >= 2                            */
+    int32_t max_iter;      /* outer iterations (filter applications)          */
+    double tol;            /* converged when rho <= tol * ||H||               */
+    int32_t precision;     /* 0: FP64 filter; 1: FP32 filter, FP64 rest       */
+    int32_t ortho;         /* FD_ORTHO_SVQB2 or FD_ORTHO_CHOLQR2              */
+    uint64_t seed;         /* start block when V0 is NULL                     */
+} fd_solve_params;
+
+typedef struct {
+    int32_t iters;        /* filter applications performed                   */
+    int32_t n_conv;       /* Ritz pairs in the window with rho <= tol ||H||   */
+    int32_t iters_fp32;   /* of which in FP32 (precision 1)                   */
+    int64_t spmmv_count;  /* SpMMVs on nb-vector bundles                      */
+    double t_filter, t_orthog, t_rr, t_total; /* seconds                      */
+    double norm_H;        /* max(|lam_lo|, |lam_hi|) of the Gershgorin bound  */
+    double max_resid;     /* largest rho among the returned pairs             */
+} fd_solve_stats;
+
+/* Plain FD (Alg. 1 caption): Gershgorin inclusion interval, alpha and beta,
+ * start block V0_host (D x N_s row-major host array) or, if NULL, N(0,1)
+ * entries from SplitMix64(seed) by Box-Muller; then repeat orthogonalize ->
+ * Rayleigh-Ritz -> convergence test on the N_t Ritz pairs nearest tau inside
+ * the window -> filter with the window's Jackson-damped indicator
+ * coefficients.  Outputs: evals_host[N_t] ascending, evecs_dev (device
+ * D x N_t, ld N_t) or NULL, resid_host[N_t] or NULL, stats or NULL.  Returns
+ * FD_ERR_NOT_CONVERGED (outputs written) if max_iter is reached.          */
+fd_status fd_solve(fd_matrix m, const fd_solve_params *params, const double *V0_host,
+                   double *evals_host, double *evecs_dev, double *resid_host,
+                   fd_solve_stats *stats);
+
+const char *fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FD_H */

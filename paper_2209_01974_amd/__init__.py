@@ -1,0 +1,312 @@
+"""Python binding of libfd (filter-diagonalization hot path on MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in libfd's HIP
+kernels and host code.  Device blocks are torch tensors on the GPU (2-D,
+row-major, unit stride along the row); PyTorch provides memory and streams.
+The library must be built (``python -m paper_2209_01974_amd.build`` or
+``__graft_entry__.build()``); there is no fallback path.
+
+Function names follow the C ABI in include/fd.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfd.so")
+
+FD_OK, FD_ERR_INVALID, FD_ERR_OOM, FD_ERR_HIP, FD_ERR_NOT_CONVERGED, FD_ERR_BREAKDOWN, FD_ERR_UNSUPPORTED = range(7)
+FD_F64, FD_F32 = 0, 1
+FD_FMT_CSR, FD_FMT_SELL = 0, 1
+FD_HUBBARD_RING, FD_ANDERSON_3D, FD_DIAGONAL, FD_USER_CSR = range(4)
+FD_BUILD_HOST_ONLY = 1
+FD_ORTHO_SVQB2, FD_ORTHO_CHOLQR2 = 0, 1
+
+STATUS_NAMES = {0: "FD_OK", 1: "FD_ERR_INVALID", 2: "FD_ERR_OOM", 3: "FD_ERR_HIP",
+                4: "FD_ERR_NOT_CONVERGED", 5: "FD_ERR_BREAKDOWN", 6: "FD_ERR_UNSUPPORTED"}
+
+
+class FDError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+class ModelParams(C.Structure):
+    _fields_ = [("model", C.c_int), ("L", C.c_int32), ("n_up", C.c_int32), ("n_dn", C.c_int32),
+                ("periodic", C.c_int32), ("t", C.c_double), ("U", C.c_double), ("W", C.c_double),
+                ("seed", C.c_uint64), ("n", C.c_int64), ("diag", C.c_void_p), ("D", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tau_lo", C.c_double), ("tau_hi", C.c_double), ("n_target", C.c_int32),
+                ("n_search", C.c_int32), ("nb", C.c_int32), ("degree", C.c_int32),
+                ("max_iter", C.c_int32), ("tol", C.c_double), ("precision", C.c_int32),
+                ("ortho", C.c_int32), ("seed", C.c_uint64)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_conv", C.c_int32), ("iters_fp32", C.c_int32),
+                ("spmmv_count", C.c_int64), ("t_filter", C.c_double), ("t_orthog", C.c_double),
+                ("t_rr", C.c_double), ("t_total", C.c_double), ("norm_H", C.c_double),
+                ("max_resid", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_D = C.c_double
+
+_SIGS = {
+    "fd_build_matrix": [C.POINTER(ModelParams), C.c_int, _I32, _I32, _I32, C.POINTER(_P)],
+    "fd_matrix_info": [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D)],
+    "fd_matrix_export_csr": [_P, _P, _P, _P],
+    "fd_matrix_export_sell": [_P, _P, _P, _P, _P, _P],
+    "fd_spmmv": [_P, C.c_int, _I32, _P, _I64, _P, _I64, _P],
+    "fd_cheb_filter": [_P, C.c_int, _I32, _I32, _P, _I64, _P, _I32, _D, _D, _P, _P, _I64, _P],
+    "fd_cheb_coeffs": [_I32, _D, _D, _I32, _P],
+    "fd_gram": [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P],
+    "fd_rotate": [_I64, _I32, _I32, _P, _I64, _P, _I64, _P],
+    "fd_syev": [_I32, _P, _I64, _P, _P, _I64, _P],
+    "fd_orthog": [_I64, _I32, _P, _I64, _I32, C.c_uint64, C.POINTER(_I32), _P],
+    "fd_rayleigh_ritz": [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P],
+    "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
+}
+
+
+def lib() -> C.CDLL:
+    """Load libfd.so (raises if it has not been built: no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfd.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.fd_matrix_free.argtypes = [_P]
+        L.fd_matrix_free.restype = None
+        L.fd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=(FD_OK,)) -> int:
+    if st not in allow:
+        raise FDError(st, lib().fd_last_error().decode())
+    return st
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _blk(t, name: str):
+    """(pointer, leading dimension, dtype code) of a 2-D row-major GPU tensor."""
+    import torch
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be a 2-D tensor with unit column stride" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if t.dtype == torch.float64:
+        dt = FD_F64
+    elif t.dtype == torch.float32:
+        dt = FD_F32
+    else:
+        raise ValueError("%s must be float64 or float32" % name)
+    return C.c_void_p(t.data_ptr()), t.stride(0), dt
+
+
+# --------------------------------------------------------------------- matrix --
+class Matrix:
+    """Owning wrapper of an fd_matrix handle."""
+
+    def __init__(self, handle: C.c_void_p, fmt: int, C_: int):
+        self._h = handle
+        self.fmt = fmt
+        self.C = C_
+        D, nnz, stored = _I64(), _I64(), _I64()
+        lo, hi = _D(), _D()
+        _check(lib().fd_matrix_info(self._h, C.byref(D), C.byref(nnz), C.byref(stored),
+                                    C.byref(lo), C.byref(hi)))
+        self.D, self.nnz, self.stored = D.value, nnz.value, stored.value
+        self.lam_lo, self.lam_hi = lo.value, hi.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export_csr(self):
+        rowptr = np.empty(self.D + 1, np.int64)
+        col = np.empty(self.nnz, np.uint32)
+        val = np.empty(self.nnz, np.float64)
+        _check(lib().fd_matrix_export_csr(self._h, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data))
+        return rowptr, col, val
+
+    def export_sell(self):
+        nch = (self.D + self.C - 1) // self.C
+        perm = np.empty(self.D, np.int32)
+        cptr = np.empty(nch + 1, np.int64)
+        clen = np.empty(nch, np.int32)
+        col = np.empty(self.stored, np.uint32)
+        val = np.empty(self.stored, np.float64)
+        _check(lib().fd_matrix_export_sell(self._h, perm.ctypes.data, cptr.ctypes.data, clen.ctypes.data,
+                                           col.ctypes.data, val.ctypes.data))
+        return perm, cptr, clen, col, val
+
+    def free(self):
+        if self._h:
+            lib().fd_matrix_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host_only: bool = False,
+                 L: int = 0, n_up: int = 0, n_dn: int = 0, periodic: bool = True, t: float = 1.0,
+                 U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None) -> Matrix:
+    """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"}."""
+    p = ModelParams()
+    keep = []
+    codes = {"hubbard": FD_HUBBARD_RING, "anderson": FD_ANDERSON_3D, "diagonal": FD_DIAGONAL, "csr": FD_USER_CSR}
+    p.model = codes[model]
+    p.L, p.n_up, p.n_dn, p.periodic = L, n_up, n_dn, int(periodic)
+    p.t, p.U, p.W, p.seed = t, U, W, seed
+    if diag is not None:
+        d = np.ascontiguousarray(diag, dtype=np.float64)
+        keep.append(d)
+        p.n = d.size
+        p.diag = d.ctypes.data
+    if csr is not None:
+        rowptr, col, val = (np.ascontiguousarray(csr[0], np.int64), np.ascontiguousarray(csr[1], np.uint32),
+                            np.ascontiguousarray(csr[2], np.float64))
+        keep += [rowptr, col, val]
+        p.D = rowptr.size - 1
+        p.rowptr, p.col, p.val = rowptr.ctypes.data, col.ctypes.data, val.ctypes.data
+    f = {"csr": FD_FMT_CSR, "sell": FD_FMT_SELL}[fmt]
+    h = C.c_void_p()
+    _check(lib().fd_build_matrix(C.byref(p), f, C_, sigma, FD_BUILD_HOST_ONLY if host_only else 0, C.byref(h)))
+    return Matrix(h, f, C_ if f == FD_FMT_SELL else 1)
+
+
+# -------------------------------------------------------------------- kernels --
+def spmmv(m: Matrix, X, Y, stream=None) -> None:
+    """Y = A X (fd_spmmv); nb = X.shape[1]."""
+    px, ldx, dt = _blk(X, "X")
+    py, ldy, dty = _blk(Y, "Y")
+    if dt != dty or X.shape != Y.shape or X.shape[0] != m.D:
+        raise ValueError("X and Y must be D x nb blocks of one dtype")
+    _check(lib().fd_spmmv(m.handle, dt, X.shape[1], px, ldx, py, ldy, _stream(stream)))
+
+
+def cheb_filter(m: Matrix, V, mu, alpha: float, beta: float, W1, W2, nb: int, stream=None) -> None:
+    """V <- p[alpha A + beta] V bundle by bundle (fd_cheb_filter)."""
+    pv, ldv, dt = _blk(V, "V")
+    p1, ldw, d1 = _blk(W1, "W1")
+    p2, ldw2, d2 = _blk(W2, "W2")
+    if not (dt == d1 == d2) or ldw != ldw2:
+        raise ValueError("V, W1, W2 must share a dtype and W1, W2 a leading dimension")
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    if V.shape[1] % nb:
+        raise ValueError("V width must be a multiple of nb")
+    _check(lib().fd_cheb_filter(m.handle, dt, nb, V.shape[1] // nb, pv, ldv, mu.ctypes.data, mu.size - 1,
+                                alpha, beta, p1, p2, ldw, _stream(stream)))
+
+
+def cheb_coeffs(kind: int, a: float, b: float, degree: int) -> np.ndarray:
+    mu = np.empty(degree + 1)
+    _check(lib().fd_cheb_coeffs(kind, a, b, degree, mu.ctypes.data))
+    return mu
+
+
+def gram(X, Y, G, stream=None) -> None:
+    """G = X^t Y (fd_gram), FP64."""
+    px, ldx, _ = _blk(X, "X")
+    py, ldy, _ = _blk(Y, "Y")
+    pg, ldg, _ = _blk(G, "G")
+    _check(lib().fd_gram(X.shape[0], X.shape[1], Y.shape[1], px, ldx, py, ldy, pg, ldg, _stream(stream)))
+
+
+def rotate(X, Q, stream=None) -> None:
+    """X[:, :n] <- X Q in place (fd_rotate), Q is m x n."""
+    px, ldx, _ = _blk(X, "X")
+    pq, ldq, _ = _blk(Q, "Q")
+    _check(lib().fd_rotate(X.shape[0], Q.shape[0], Q.shape[1], px, ldx, pq, ldq, _stream(stream)))
+
+
+def syev(S, w, U, stream=None) -> None:
+    """S = U diag(w) U^t on the GPU (fd_syev); S is overwritten."""
+    ps, lds, _ = _blk(S, "S")
+    pu, ldu, _ = _blk(U, "U")
+    _check(lib().fd_syev(S.shape[0], ps, lds, C.c_void_p(w.data_ptr()), pu, ldu, _stream(stream)))
+
+
+def orthog(V, method: int = FD_ORTHO_SVQB2, seed: int = 0, stream=None) -> int:
+    pv, ldv, _ = _blk(V, "V")
+    r = _I32()
+    _check(lib().fd_orthog(V.shape[0], V.shape[1], pv, ldv, method, seed, C.byref(r), _stream(stream)))
+    return r.value
+
+
+def rayleigh_ritz(m: Matrix, V, W, nb: int, stream=None):
+    pv, ld, _ = _blk(V, "V")
+    pw, ldw, _ = _blk(W, "W")
+    if ld != ldw:
+        raise ValueError("V and W must share a leading dimension")
+    ns = V.shape[1]
+    th = np.empty(ns)
+    rho = np.empty(ns)
+    _check(lib().fd_rayleigh_ritz(m.handle, ns, nb, pv, pw, ld, th.ctypes.data, rho.ctypes.data, _stream(stream)))
+    return th, rho
+
+
+@dataclass
+class SolveResult:
+    status: int
+    evals: np.ndarray
+    resid: np.ndarray
+    evecs: object
+    stats: dict
+
+
+def solve(m: Matrix, tau_lo: float, tau_hi: float, n_target: int, n_search: int, nb: int, degree: int,
+          max_iter: int = 50, tol: float = 1e-9, precision: int = 0, ortho: int = FD_ORTHO_SVQB2,
+          seed: int = 0, V0: np.ndarray | None = None, want_vectors: bool = True) -> SolveResult:
+    """fd_solve; V0 is a host D x n_search float64 array (or None)."""
+    import torch
+    p = SolveParams(tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol, precision, ortho, seed)
+    ev = np.full(n_target, np.nan)
+    rs = np.full(n_target, np.nan)
+    vecs = torch.empty((m.D, n_target), dtype=torch.float64, device="cuda") if want_vectors else None
+    v0p = None
+    if V0 is not None:
+        V0 = np.ascontiguousarray(V0, dtype=np.float64)
+        if V0.shape != (m.D, n_search):
+            raise ValueError("V0 must be D x n_search")
+        v0p = V0.ctypes.data
+    st = SolveStats()
+    torch.cuda.synchronize()
+    status = _check(lib().fd_solve(m.handle, C.byref(p), v0p, ev.ctypes.data,
+                                   vecs.data_ptr() if vecs is not None else None, rs.ctypes.data,
+                                   C.byref(st)), allow=(FD_OK, FD_ERR_NOT_CONVERGED))
+    return SolveResult(status, ev, rs, vecs, st.as_dict())

@@ -1,0 +1,568 @@
+// libfd C ABI: handles, argument checks, the Chebyshev filter loop, the
+// orthogonalization and Rayleigh-Ritz steps and the FD driver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+namespace {
+thread_local std::string g_err;
+}
+
+fd_status fail(fd_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+fd_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? FD_ERR_OOM : FD_ERR_HIP;
+}
+
+namespace {
+
+int vec_width(fd_dtype dt, int nb) {
+    const int w = (dt == FD_F64) ? 2 : 4;
+    return std::min(w, nb);
+}
+
+bool nb_ok(int nb) {
+    return nb == 1 || nb == 2 || nb == 4 || nb == 8 || nb == 16 || nb == 32 || nb == 64;
+}
+
+size_t esize(fd_dtype dt) { return dt == FD_F64 ? 8 : 4; }
+
+fd_status check_block(const void *p, int64_t ld, int64_t cols, fd_dtype dt, int nb, const char *name) {
+    if (!p) return fail(FD_ERR_INVALID, std::string(name) + ": null pointer");
+    if (ld < cols) return fail(FD_ERR_INVALID, std::string(name) + ": leading dimension smaller than width");
+    const int vw = vec_width(dt, nb);
+    if (ld % vw) return fail(FD_ERR_INVALID, std::string(name) + ": leading dimension not a multiple of the vector width");
+    if (((uintptr_t)p) % (vw * esize(dt))) return fail(FD_ERR_INVALID, std::string(name) + ": misaligned");
+    return FD_OK;
+}
+
+bool overlap(const void *a, int64_t la, const void *b, int64_t lb, int64_t D, size_t es) {
+    const char *a0 = (const char *)a, *a1 = a0 + (size_t)D * la * es;
+    const char *b0 = (const char *)b, *b1 = b0 + (size_t)D * lb * es;
+    return a0 < b1 && b0 < a1;
+}
+
+fd_status upload(fd_matrix m) {
+    DevMatrix &d = m->dev;
+    const int64_t D = m->csr.D;
+    d.D = D;
+    std::vector<uint32_t> ptr;
+    const std::vector<uint32_t> *col;
+    const std::vector<double> *val;
+    std::vector<int32_t> perm;
+    if (m->fmt == FD_FMT_CSR) {
+        if (m->csr.rowptr[D] >= (int64_t)UINT32_MAX) return fail(FD_ERR_UNSUPPORTED, "matrix: more than 2^32 entries");
+        d.cshift = 0;
+        d.nslots = D;
+        d.stored = m->csr.rowptr[D];
+        ptr.assign(m->csr.rowptr.begin(), m->csr.rowptr.end());
+        col = &m->csr.col;
+        val = &m->csr.val;
+    } else {
+        const HostSELL &S = m->sell;
+        const int64_t nch = (int64_t)S.chunk_len.size();
+        if (S.chunk_ptr[nch] >= (int64_t)UINT32_MAX) return fail(FD_ERR_UNSUPPORTED, "matrix: more than 2^32 slots");
+        d.cshift = __builtin_ctz(S.C);
+        d.nslots = nch * S.C;
+        d.stored = S.chunk_ptr[nch];
+        ptr.assign(S.chunk_ptr.begin(), S.chunk_ptr.end());
+        col = &S.col;
+        val = &S.val;
+        perm.assign(d.nslots, -1);
+        std::copy(S.perm.begin(), S.perm.end(), perm.begin());
+    }
+    std::vector<float> v32(val->size());
+    for (size_t i = 0; i < val->size(); i++) v32[i] = (float)(*val)[i];
+    const size_t st = std::max<size_t>(1, (size_t)d.stored);
+    FD_HIP(hipMalloc(&d.ptr, ptr.size() * sizeof(uint32_t)));
+    FD_HIP(hipMalloc(&d.col, st * sizeof(uint32_t)));
+    FD_HIP(hipMalloc(&d.val64, st * sizeof(double)));
+    FD_HIP(hipMalloc(&d.val32, st * sizeof(float)));
+    FD_HIP(hipMemcpy(d.ptr, ptr.data(), ptr.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    FD_HIP(hipMemcpy(d.col, col->data(), col->size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    FD_HIP(hipMemcpy(d.val64, val->data(), val->size() * sizeof(double), hipMemcpyHostToDevice));
+    FD_HIP(hipMemcpy(d.val32, v32.data(), v32.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (!perm.empty()) {
+        FD_HIP(hipMalloc(&d.perm, perm.size() * sizeof(int32_t)));
+        FD_HIP(hipMemcpy(d.perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    FD_HIP(hipGetDevice(&m->device));
+    return FD_OK;
+}
+
+void free_dev(DevMatrix &d) {
+    if (d.ptr) (void)hipFree(d.ptr);
+    if (d.col) (void)hipFree(d.col);
+    if (d.val64) (void)hipFree(d.val64);
+    if (d.val32) (void)hipFree(d.val32);
+    if (d.perm) (void)hipFree(d.perm);
+    d = DevMatrix();
+}
+
+fd_status need_device(fd_matrix m) {
+    if (!m) return fail(FD_ERR_INVALID, "null matrix handle");
+    if (m->device < 0) return fail(FD_ERR_INVALID, "matrix was built host-only");
+    return FD_OK;
+}
+
+// The filter on one group of bundles (all at once, or one at a time).
+fd_status filter_run(const DevMatrix &M, fd_dtype dt, int nb, int nbund, char *V, int64_t ldv,
+                     const double *mu, int degree, double alpha, double beta, char *W1, char *W2,
+                     int64_t ldw, int64_t bw, hipStream_t s) {
+    const size_t es = esize(dt);
+    (void)es;
+    SpmmvCall c;
+    c.nb = nb;
+    c.nbundles = nbund;
+    // step 1: W2 = T_1 V = alpha A V + beta V
+    c.mode = 1;
+    c.x = V; c.ldx = ldv; c.bx = nb;
+    c.y = W2; c.ldy = ldw; c.by = bw;
+    c.a = alpha; c.b = beta;
+    FD_TRY(launch_spmmv(M, dt, c, s));
+    // step 2: W1 = T_2 V = 2 B W2 - V;  V = mu0 V + mu1 W2 + mu2 W1
+    c.mode = 2;
+    c.x = W2; c.ldx = ldw; c.bx = bw;
+    c.y = W1; c.ldy = ldw; c.by = bw;
+    c.v = V; c.ldv = ldv; c.bv = nb;
+    c.a = 2.0 * alpha; c.b = 2.0 * beta;
+    c.cv = mu[0]; c.cx = mu[1]; c.ct = mu[2];
+    FD_TRY(launch_spmmv(M, dt, c, s));
+    // steps k >= 3: prev = 2 B cur - prev (in place); V += mu_k prev
+    char *cur = W1, *prev = W2;
+    for (int k = 3; k <= degree; k++) {
+        c.mode = 3;
+        c.x = cur; c.ldx = ldw; c.bx = bw;
+        c.z = prev; c.ldz = ldw; c.bz = bw;
+        c.y = prev; c.ldy = ldw; c.by = bw;
+        c.ct = mu[k];
+        FD_TRY(launch_spmmv(M, dt, c, s));
+        std::swap(cur, prev);
+    }
+    return FD_OK;
+}
+
+fd_status cheb_filter_impl(fd_matrix m, fd_dtype dt, int nb, int nbund, void *V, int64_t ldv,
+                           const double *mu, int degree, double alpha, double beta, void *W1, void *W2,
+                           int64_t ldw, hipStream_t s) {
+    const DevMatrix &M = m->dev;
+    const size_t es = esize(dt);
+    if (ldw >= (int64_t)nb * nbund) {
+        return filter_run(M, dt, nb, nbund, (char *)V, ldv, mu, degree, alpha, beta, (char *)W1, (char *)W2,
+                          ldw, nb, s);
+    }
+    for (int b = 0; b < nbund; b++) {
+        FD_TRY(filter_run(M, dt, nb, 1, (char *)V + (size_t)b * nb * es, ldv, mu, degree, alpha, beta,
+                          (char *)W1, (char *)W2, ldw, 0, s));
+    }
+    return FD_OK;
+}
+
+// ---------------------------------------------------------- small buffers --
+struct Small {
+    double *G, *Q, *work, *theta, *rho;
+    int *keep, *ints;
+};
+
+fd_status small_buffers(int n, Small &b) {
+    const size_t nn = (size_t)n * n;
+    const size_t bytes = (2 * nn + (2 * n + nn) + 2 * n) * sizeof(double) + (n + 8) * sizeof(int);
+    char *p = (char *)workspace(bytes, 3);
+    if (!p) return fail(FD_ERR_OOM, "small workspace");
+    b.G = (double *)p;
+    b.Q = b.G + nn;
+    b.work = b.Q + nn;
+    b.theta = b.work + 2 * n + nn;
+    b.rho = b.theta + n;
+    b.keep = (int *)(b.rho + n);
+    b.ints = b.keep + n;
+    return FD_OK;
+}
+
+fd_status orthog_impl(int64_t D, int ns, double *V, int64_t ldv, int method, uint64_t seed, int *rank_out,
+                      hipStream_t s) {
+    Small b;
+    FD_TRY(small_buffers(ns, b));
+    if (method == FD_ORTHO_CHOLQR2) {
+        bool ok = true;
+        for (int pass = 0; pass < 2 && ok; pass++) {
+            FD_TRY(gram(D, ns, ns, V, ldv, V, ldv, b.G, ns, true, s));
+            FD_TRY(cholqr_transform(ns, b.G, b.Q, b.ints, s));
+            int okh = 0;
+            FD_HIP(hipMemcpyAsync(&okh, b.ints, sizeof(int), hipMemcpyDeviceToHost, s));
+            FD_HIP(hipStreamSynchronize(s));
+            ok = okh != 0;
+            if (ok) FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
+        }
+        if (ok) {
+            if (rank_out) *rank_out = ns;
+            return FD_OK;
+        }
+        // fall through to SVQB2 on the partly orthogonalized block
+    }
+    int rank = ns;
+    FD_TRY(gram(D, ns, ns, V, ldv, V, ldv, b.G, ns, true, s));
+    FD_TRY(svqb_transform(ns, b.G, b.Q, b.work, b.keep, b.ints, s));
+    FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
+    FD_HIP(hipMemcpyAsync(&rank, b.ints, sizeof(int), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    if (rank < ns) {
+        // replace the directions that were clipped by fresh random vectors
+        FD_TRY(refill_random(D, ns, V, ldv, b.keep, seed, s));
+        FD_TRY(gram(D, ns, ns, V, ldv, V, ldv, b.G, ns, true, s));
+        FD_TRY(svqb_transform(ns, b.G, b.Q, b.work, b.keep, b.ints + 1, s));
+        FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
+    }
+    FD_TRY(gram(D, ns, ns, V, ldv, V, ldv, b.G, ns, true, s));
+    FD_TRY(svqb_transform(ns, b.G, b.Q, b.work, b.keep, b.ints + 2, s));
+    FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
+    if (rank_out) *rank_out = rank;
+    return FD_OK;
+}
+
+fd_status rr_impl(fd_matrix m, int ns, int nb, double *V, double *W, int64_t ld, double *theta_host,
+                  double *resid_host, hipStream_t s) {
+    const int64_t D = m->dev.D;
+    Small b;
+    FD_TRY(small_buffers(ns, b));
+    SpmmvCall c;
+    c.mode = 0;
+    c.nb = nb;
+    c.nbundles = ns / nb;
+    c.x = V; c.ldx = ld; c.bx = nb;
+    c.y = W; c.ldy = ld; c.by = nb;
+    FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
+    FD_TRY(gram(D, ns, ns, V, ld, W, ld, b.G, ns, false, s));
+    FD_TRY(symmetrize(ns, b.G, s));
+    FD_TRY(syev(ns, b.G, ns, b.theta, b.Q, ns, s));
+    FD_TRY(rotate(D, ns, ns, V, ld, b.Q, ns, s));
+    FD_TRY(rotate(D, ns, ns, W, ld, b.Q, ns, s));
+    FD_TRY(col_resid(D, ns, V, W, ld, b.theta, b.rho, s));
+    FD_HIP(hipMemcpyAsync(theta_host, b.theta, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipMemcpyAsync(resid_host, b.rho, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    return FD_OK;
+}
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Ritz values in the window nearest tau (ties: lower value first).
+std::vector<int> select_targets(const std::vector<double> &th, double lo, double hi, int nt) {
+    const double tau = 0.5 * (lo + hi);
+    std::vector<int> idx;
+    for (int j = 0; j < (int)th.size(); j++)
+        if (hi <= lo || (th[j] >= lo && th[j] <= hi)) idx.push_back(j);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const double da = std::fabs(th[a] - tau), db = std::fabs(th[b] - tau);
+        if (da != db) return da < db;
+        return th[a] < th[b];
+    });
+    if ((int)idx.size() > nt) idx.resize(nt);
+    return idx;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    fd_status alloc(size_t bytes, const char *what) {
+        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(FD_ERR_OOM, std::string("fd_solve: cannot allocate ") + what);
+        }
+        return FD_OK;
+    }
+};
+
+}  // namespace
+}  // namespace fd
+
+using namespace fd;
+
+extern "C" {
+
+const char *fd_last_error(void) { return g_err.c_str(); }
+
+fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, int32_t sigma, int32_t flags,
+                          fd_matrix *out) {
+    if (!p || !out) return fail(FD_ERR_INVALID, "fd_build_matrix: null argument");
+    if (fmt != FD_FMT_CSR && fmt != FD_FMT_SELL) return fail(FD_ERR_INVALID, "fd_build_matrix: bad format");
+    fd_matrix m = new (std::nothrow) fd_matrix_s;
+    if (!m) return fail(FD_ERR_OOM, "fd_build_matrix: host allocation");
+    fd_status st;
+    switch (p->model) {
+        case FD_HUBBARD_RING: st = build_hubbard(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->csr); break;
+        case FD_ANDERSON_3D: st = build_anderson(p->L, p->t, p->W, p->seed, m->csr); break;
+        case FD_DIAGONAL: st = build_diagonal(p->n, p->diag, m->csr); break;
+        case FD_USER_CSR: st = build_user(p->D, p->rowptr, p->col, p->val, m->csr); break;
+        default: st = fail(FD_ERR_INVALID, "fd_build_matrix: unknown model");
+    }
+    if (st == FD_OK && fmt == FD_FMT_SELL) st = build_sell(m->csr, C, sigma, m->sell);
+    m->fmt = fmt;
+    if (st == FD_OK) gershgorin(m->csr, m->lam_lo, m->lam_hi);
+    if (st == FD_OK && !(flags & FD_BUILD_HOST_ONLY)) {
+        st = upload(m);
+        if (st != FD_OK) free_dev(m->dev);
+    }
+    if (st != FD_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return FD_OK;
+}
+
+fd_status fd_matrix_info(fd_matrix m, int64_t *D, int64_t *nnz, int64_t *stored, double *lo, double *hi) {
+    if (!m) return fail(FD_ERR_INVALID, "fd_matrix_info: null handle");
+    if (D) *D = m->csr.D;
+    if (nnz) *nnz = m->csr.rowptr[m->csr.D];
+    if (stored) *stored = (m->fmt == FD_FMT_SELL) ? m->sell.chunk_ptr.back() : m->csr.rowptr[m->csr.D];
+    if (lo) *lo = m->lam_lo;
+    if (hi) *hi = m->lam_hi;
+    return FD_OK;
+}
+
+fd_status fd_matrix_export_csr(fd_matrix m, int64_t *rowptr, uint32_t *col, double *val) {
+    if (!m || !rowptr || !col || !val) return fail(FD_ERR_INVALID, "fd_matrix_export_csr: null argument");
+    std::memcpy(rowptr, m->csr.rowptr.data(), m->csr.rowptr.size() * sizeof(int64_t));
+    std::memcpy(col, m->csr.col.data(), m->csr.col.size() * sizeof(uint32_t));
+    std::memcpy(val, m->csr.val.data(), m->csr.val.size() * sizeof(double));
+    return FD_OK;
+}
+
+fd_status fd_matrix_export_sell(fd_matrix m, int32_t *perm, int64_t *cptr, int32_t *clen, uint32_t *col,
+                                double *val) {
+    if (!m || !perm || !cptr || !clen || !col || !val)
+        return fail(FD_ERR_INVALID, "fd_matrix_export_sell: null argument");
+    if (m->fmt != FD_FMT_SELL) return fail(FD_ERR_INVALID, "fd_matrix_export_sell: matrix is not SELL");
+    const HostSELL &S = m->sell;
+    std::memcpy(perm, S.perm.data(), S.perm.size() * sizeof(int32_t));
+    std::memcpy(cptr, S.chunk_ptr.data(), S.chunk_ptr.size() * sizeof(int64_t));
+    std::memcpy(clen, S.chunk_len.data(), S.chunk_len.size() * sizeof(int32_t));
+    std::memcpy(col, S.col.data(), S.col.size() * sizeof(uint32_t));
+    std::memcpy(val, S.val.data(), S.val.size() * sizeof(double));
+    return FD_OK;
+}
+
+void fd_matrix_free(fd_matrix m) {
+    if (!m) return;
+    free_dev(m->dev);
+    delete m;
+}
+
+fd_status fd_spmmv(fd_matrix m, fd_dtype dt, int32_t nb, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                   void *stream) {
+    FD_TRY(need_device(m));
+    if (dt != FD_F64 && dt != FD_F32) return fail(FD_ERR_INVALID, "fd_spmmv: bad dtype");
+    if (!nb_ok(nb)) return fail(FD_ERR_INVALID, "fd_spmmv: nb must be one of 1, 2, 4, 8, 16, 32, 64");
+    FD_TRY(check_block(X, ldx, nb, dt, nb, "fd_spmmv X"));
+    FD_TRY(check_block(Y, ldy, nb, dt, nb, "fd_spmmv Y"));
+    if (overlap(X, ldx, Y, ldy, m->dev.D, esize(dt))) return fail(FD_ERR_INVALID, "fd_spmmv: X and Y overlap");
+    SpmmvCall c;
+    c.mode = 0;
+    c.nb = nb;
+    c.x = X; c.ldx = ldx;
+    c.y = Y; c.ldy = ldy;
+    return launch_spmmv(m->dev, dt, c, (hipStream_t)stream);
+}
+
+fd_status fd_cheb_filter(fd_matrix m, fd_dtype dt, int32_t nb, int32_t nbund, void *V, int64_t ldv,
+                         const double *mu, int32_t degree, double alpha, double beta, void *W1, void *W2,
+                         int64_t ldw, void *stream) {
+    FD_TRY(need_device(m));
+    if (dt != FD_F64 && dt != FD_F32) return fail(FD_ERR_INVALID, "fd_cheb_filter: bad dtype");
+    if (!nb_ok(nb)) return fail(FD_ERR_INVALID, "fd_cheb_filter: nb must be one of 1, 2, 4, 8, 16, 32, 64");
+    if (nbund < 1) return fail(FD_ERR_INVALID, "fd_cheb_filter: n_bundles < 1");
+    if (degree < 2) return fail(FD_ERR_INVALID, "fd_cheb_filter: degree must be >= 2");
+    if (!mu) return fail(FD_ERR_INVALID, "fd_cheb_filter: null coefficients");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(FD_ERR_INVALID, "fd_cheb_filter: alpha/beta not finite");
+    FD_TRY(check_block(V, ldv, (int64_t)nb * nbund, dt, nb, "fd_cheb_filter V"));
+    FD_TRY(check_block(W1, ldw, nb, dt, nb, "fd_cheb_filter W1"));
+    FD_TRY(check_block(W2, ldw, nb, dt, nb, "fd_cheb_filter W2"));
+    const int64_t D = m->dev.D;
+    const size_t es = esize(dt);
+    if (overlap(V, ldv, W1, ldw, D, es) || overlap(V, ldv, W2, ldw, D, es) || overlap(W1, ldw, W2, ldw, D, es))
+        return fail(FD_ERR_INVALID, "fd_cheb_filter: V, W1, W2 overlap");
+    return cheb_filter_impl(m, dt, nb, nbund, V, ldv, mu, degree, alpha, beta, W1, W2, ldw, (hipStream_t)stream);
+}
+
+fd_status fd_cheb_coeffs(int32_t kind, double a, double b, int32_t degree, double *mu) {
+    return cheb_coeffs(kind, a, b, degree, mu);
+}
+
+fd_status fd_gram(int64_t D, int32_t m, int32_t n, const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                  double *G, int64_t ldg, void *stream) {
+    if (!X || !Y || !G || ldx < m || ldy < n || ldg < n) return fail(FD_ERR_INVALID, "fd_gram: bad arguments");
+    return gram(D, m, n, X, ldx, Y, ldy, G, ldg, false, (hipStream_t)stream);
+}
+
+fd_status fd_rotate(int64_t D, int32_t m, int32_t n, double *X, int64_t ldx, const double *Q, int64_t ldq,
+                    void *stream) {
+    if (!X || !Q || ldx < m || ldq < n) return fail(FD_ERR_INVALID, "fd_rotate: bad arguments");
+    return rotate(D, m, n, X, ldx, Q, ldq, (hipStream_t)stream);
+}
+
+fd_status fd_syev(int32_t n, double *S, int64_t lds, double *w, double *U, int64_t ldu, void *stream) {
+    if (!S || !w || !U || lds < n || ldu < n) return fail(FD_ERR_INVALID, "fd_syev: bad arguments");
+    return syev(n, S, lds, w, U, ldu, (hipStream_t)stream);
+}
+
+fd_status fd_orthog(int64_t D, int32_t ns, double *V, int64_t ldv, int32_t method, uint64_t seed, int32_t *rank,
+                    void *stream) {
+    if (!V || D < 1 || ns < 1 || ns > 512 || ldv < ns) return fail(FD_ERR_INVALID, "fd_orthog: bad arguments");
+    if (method != FD_ORTHO_SVQB2 && method != FD_ORTHO_CHOLQR2) return fail(FD_ERR_INVALID, "fd_orthog: bad method");
+    int r = 0;
+    FD_TRY(orthog_impl(D, ns, V, ldv, method, seed, &r, (hipStream_t)stream));
+    if (rank) *rank = r;
+    return FD_OK;
+}
+
+fd_status fd_rayleigh_ritz(fd_matrix m, int32_t ns, int32_t nb, double *V, double *W, int64_t ld, double *theta,
+                           double *resid, void *stream) {
+    FD_TRY(need_device(m));
+    if (!nb_ok(nb) || ns < 1 || ns > 512 || ns % nb) return fail(FD_ERR_INVALID, "fd_rayleigh_ritz: ns must be a multiple of nb <= 512");
+    if (!theta || !resid) return fail(FD_ERR_INVALID, "fd_rayleigh_ritz: null output");
+    FD_TRY(check_block(V, ld, ns, FD_F64, nb, "fd_rayleigh_ritz V"));
+    FD_TRY(check_block(W, ld, ns, FD_F64, nb, "fd_rayleigh_ritz W"));
+    if (overlap(V, ld, W, ld, m->dev.D, 8)) return fail(FD_ERR_INVALID, "fd_rayleigh_ritz: V and W overlap");
+    return rr_impl(m, ns, nb, V, W, ld, theta, resid, (hipStream_t)stream);
+}
+
+fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, double *evals, double *evecs,
+                   double *resid, fd_solve_stats *stats) {
+    FD_TRY(need_device(m));
+    if (!P || !evals) return fail(FD_ERR_INVALID, "fd_solve: null argument");
+    const int nb = P->nb, ns = P->n_search, nt = P->n_target;
+    if (!nb_ok(nb) || ns < nb || ns % nb || ns > 512 || nt < 1 || nt > ns)
+        return fail(FD_ERR_INVALID, "fd_solve: need nb in {1..64}, N_s a multiple of nb, N_t <= N_s <= 512");
+    if (P->degree < 2) return fail(FD_ERR_INVALID, "fd_solve: degree must be >= 2");
+    if (P->max_iter < 0 || !(P->tol > 0)) return fail(FD_ERR_INVALID, "fd_solve: bad max_iter or tol");
+    if (P->precision != 0 && P->precision != 1) return fail(FD_ERR_INVALID, "fd_solve: precision must be 0 or 1");
+    const double lo = m->lam_lo, hi = m->lam_hi;
+    if (!(P->tau_lo <= P->tau_hi) || P->tau_lo < lo || P->tau_hi > hi)
+        return fail(FD_ERR_INVALID, "fd_solve: window must satisfy lam_lo <= tau_lo <= tau_hi <= lam_hi");
+    if (!(hi > lo)) return fail(FD_ERR_INVALID, "fd_solve: spectrum interval is a point");
+    const int64_t D = m->dev.D;
+    if (ns > D) return fail(FD_ERR_INVALID, "fd_solve: N_s > D");
+    const double t0 = now();
+    const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
+    const double normH = std::max(std::fabs(lo), std::fabs(hi));
+    std::vector<double> mu(P->degree + 1);
+    if (P->tau_hi > P->tau_lo) {
+        const double a = std::max(-1.0, std::min(1.0, alpha * P->tau_lo + beta));
+        const double b = std::max(a, std::min(1.0, alpha * P->tau_hi + beta));
+        FD_TRY(cheb_coeffs(0, a, b, P->degree, mu.data()));
+    } else {
+        const double a = std::max(-1.0, std::min(1.0, alpha * P->tau_lo + beta));
+        FD_TRY(cheb_coeffs(1, a, 0.0, P->degree, mu.data()));
+    }
+    hipStream_t s = nullptr;
+    // Workspaces: all bundles in one launch when W1/W2 for every bundle fit in
+    // 512 MB; otherwise bundle by bundle with nb-wide W1/W2.
+    const bool concurrent = (size_t)D * ns * 8 * 2 <= (512ull << 20);
+    const int64_t ldw = concurrent ? ns : nb;
+    DevBuf V, W, W1, W2, V32;
+    FD_TRY(V.alloc((size_t)D * ns * 8, "V"));
+    FD_TRY(W.alloc((size_t)D * ns * 8, "W"));
+    FD_TRY(W1.alloc((size_t)D * ldw * 8, "W1"));
+    FD_TRY(W2.alloc((size_t)D * ldw * 8, "W2"));
+    if (P->precision == 1) FD_TRY(V32.alloc((size_t)D * ns * 4, "V32"));
+    double *Vd = (double *)V.p, *Wd = (double *)W.p;
+    if (V0) {
+        FD_HIP(hipMemcpy(Vd, V0, (size_t)D * ns * 8, hipMemcpyHostToDevice));
+    } else {
+        FD_TRY(fill_normal(D, ns, Vd, ns, P->seed, s));
+    }
+    std::vector<double> th(ns), rho(ns);
+    std::vector<int> sel;
+    fd_solve_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.norm_H = normH;
+    bool fp32 = P->precision == 1;
+    double prev_max = INFINITY;
+    const double tol = P->tol * normH;
+    bool converged = false;
+    int it = 0;
+    for (;;) {
+        double ta = now();
+        int rank = 0;
+        FD_TRY(orthog_impl(D, ns, Vd, ns, P->ortho, P->seed + 0x1000 + it, &rank, s));
+        FD_HIP(hipStreamSynchronize(s));
+        double tb = now();
+        st.t_orthog += tb - ta;
+        FD_TRY(rr_impl(m, ns, nb, Vd, Wd, ns, th.data(), rho.data(), s));
+        st.t_rr += now() - tb;
+        st.spmmv_count += ns / nb;
+        for (int j = 0; j < ns; j++)
+            if (!std::isfinite(th[j]) || !std::isfinite(rho[j]))
+                return fail(FD_ERR_BREAKDOWN, "fd_solve: non-finite Ritz data");
+        sel = select_targets(th, P->tau_lo, P->tau_hi, nt);
+        double mx = 0.0;
+        for (int j : sel) mx = std::max(mx, rho[j]);
+        st.n_conv = 0;
+        for (int j = 0; j < ns; j++)
+            if ((P->tau_hi <= P->tau_lo || (th[j] >= P->tau_lo && th[j] <= P->tau_hi)) && rho[j] <= tol) st.n_conv++;
+        converged = (int)sel.size() == nt && mx <= tol;
+        if (converged || it >= P->max_iter) break;
+        // mixed precision: leave FP32 once the residual is near what an FP32
+        // filter can deliver, or once it stops improving
+        if (fp32 && (mx <= 1e-5 * normH || mx > 0.5 * prev_max)) fp32 = false;
+        prev_max = mx;
+        double tf = now();
+        if (fp32) {
+            float *V32d = (float *)V32.p;
+            FD_TRY(convert_f64_f32(D, ns, Vd, ns, V32d, ns, s));
+            FD_TRY(cheb_filter_impl(m, FD_F32, nb, ns / nb, V32d, ns, mu.data(), P->degree, alpha, beta, W1.p,
+                                    W2.p, ldw, s));
+            FD_TRY(convert_f32_f64(D, ns, V32d, ns, Vd, ns, s));
+            st.iters_fp32++;
+        } else {
+            FD_TRY(cheb_filter_impl(m, FD_F64, nb, ns / nb, Vd, ns, mu.data(), P->degree, alpha, beta, W1.p,
+                                    W2.p, ldw, s));
+        }
+        FD_HIP(hipStreamSynchronize(s));
+        st.t_filter += now() - tf;
+        st.spmmv_count += (int64_t)P->degree * (ns / nb);
+        it++;
+    }
+    st.iters = it;
+    // return the selected pairs sorted by eigenvalue
+    std::vector<int> order(sel);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return th[a] < th[b]; });
+    const int nret = (int)order.size();
+    st.max_resid = 0.0;
+    for (int k = 0; k < nt; k++) {
+        evals[k] = k < nret ? th[order[k]] : NAN;
+        if (resid) resid[k] = k < nret ? rho[order[k]] : NAN;
+        if (k < nret) st.max_resid = std::max(st.max_resid, rho[order[k]]);
+    }
+    if (evecs && nret > 0) {
+        int *idx = (int *)workspace(nret * sizeof(int), 4);
+        if (!idx) return fail(FD_ERR_OOM, "fd_solve: index workspace");
+        FD_HIP(hipMemcpy(idx, order.data(), nret * sizeof(int), hipMemcpyHostToDevice));
+        FD_TRY(gather_cols(D, nret, Vd, ns, idx, evecs, nt, s));
+        FD_HIP(hipStreamSynchronize(s));
+    }
+    st.t_total = now() - t0;
+    if (stats) *stats = st;
+    if (!converged) return fail(FD_ERR_NOT_CONVERGED, "fd_solve: not converged within max_iter");
+    return FD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,348 @@
+// Host-side matrix builders for libfd: generated Hamiltonians -> canonical
+// CSR (ascending columns, diagonal always stored) -> optional SELL-C-sigma,
+// plus the Gershgorin inclusion interval and the Chebyshev coefficients.
+//
+// The FD method needs an inclusion interval [lam_l, lam_r] of the spectrum
+// for the Chebyshev scaling (Sec. 2) and A stored row-wise with uint32 column
+// indices (Sec. 3.1, Eq. traffic with S_i = 4).  Row generation runs on all
+// host cores.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+namespace {
+
+int n_threads() {
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 4;
+    return (int)std::min<unsigned>(h, 32);
+}
+
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+    int T = n_threads();
+    if (n < 4096) T = 1;
+    std::vector<std::thread> th;
+    int64_t per = (n + T - 1) / T;
+    for (int k = 0; k < T; k++) {
+        int64_t lo = k * per, hi = std::min<int64_t>(n, lo + per);
+        if (lo >= hi) break;
+        th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// binomial table C[n][k], n <= 64
+struct Binom {
+    uint64_t c[65][65];
+    Binom() {
+        std::memset(c, 0, sizeof(c));
+        for (int n = 0; n <= 64; n++) {
+            c[n][0] = 1;
+            for (int k = 1; k <= n; k++) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
+        }
+    }
+};
+const Binom &binom() {
+    static Binom b;
+    return b;
+}
+
+// Combinatorial number system: the colex rank of a subset equals the rank of
+// its bitmask in increasing integer order.
+uint64_t subset_rank(uint64_t m) {
+    uint64_t r = 0;
+    int i = 1;
+    while (m) {
+        int p = __builtin_ctzll(m);
+        r += binom().c[p][i];
+        i++;
+        m &= m - 1;
+    }
+    return r;
+}
+
+// next larger integer with the same popcount (Gosper)
+uint64_t next_same_popcount(uint64_t v) {
+    uint64_t t = v | (v - 1);
+    return (t + 1) | (((~t & -~t) - 1) >> (__builtin_ctzll(v) + 1));
+}
+
+struct Hop {
+    uint32_t rank;
+    double el;
+};
+
+// For each spin configuration, the configurations one hop away with their
+// matrix elements, sorted by rank.  The Jordan-Wigner string between the two
+// sites of a bond gives the fermion sign.
+void species_hops(int L, int N, bool periodic, double t, std::vector<uint64_t> &masks,
+                  std::vector<uint32_t> &off, std::vector<Hop> &hops) {
+    uint64_t n = binom().c[L][N];
+    masks.resize(n);
+    uint64_t m = (N == 0) ? 0 : ((N == 64) ? ~0ULL : ((1ULL << N) - 1));
+    for (uint64_t k = 0; k < n; k++) {
+        masks[k] = m;
+        if (k + 1 < n) m = next_same_popcount(m);
+    }
+    off.assign(n + 1, 0);
+    hops.clear();
+    int nbond = periodic ? L : L - 1;
+    std::vector<Hop> tmp;
+    for (uint64_t k = 0; k < n; k++) {
+        tmp.clear();
+        uint64_t s = masks[k];
+        if (t != 0.0) {
+            for (int b = 0; b < nbond; b++) {
+                int i = b, j = (b + 1 == L) ? 0 : b + 1;
+                if (((s >> i) ^ (s >> j)) & 1ULL) {
+                    int lo = std::min(i, j), hi = std::max(i, j);
+                    uint64_t between = (hi - lo > 1) ? (((1ULL << hi) - 1) & ~((2ULL << lo) - 1)) : 0;
+                    int par = __builtin_popcountll(s & between) & 1;
+                    uint64_t s2 = s ^ (1ULL << i) ^ (1ULL << j);
+                    tmp.push_back({(uint32_t)subset_rank(s2), par ? t : -t});
+                }
+            }
+        }
+        std::sort(tmp.begin(), tmp.end(), [](const Hop &x, const Hop &y) { return x.rank < y.rank; });
+        hops.insert(hops.end(), tmp.begin(), tmp.end());
+        off[k + 1] = (uint32_t)hops.size();
+    }
+}
+
+}  // namespace
+
+fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, HostCSR &A) {
+    if (L < 3 || L > 62 || nup < 0 || nup > L || ndn < 0 || ndn > L)
+        return fail(FD_ERR_INVALID, "Hubbard: need 3 <= L <= 62 and 0 <= n_up, n_dn <= L");
+    uint64_t nu = binom().c[L][nup], nd = binom().c[L][ndn];
+    if (nu * nd >= (1ULL << 32)) return fail(FD_ERR_UNSUPPORTED, "Hubbard: D >= 2^32");
+    std::vector<uint64_t> mu, md;
+    std::vector<uint32_t> ou, od;
+    std::vector<Hop> hu, hd;
+    species_hops(L, nup, periodic, t, mu, ou, hu);
+    species_hops(L, ndn, periodic, t, md, od, hd);
+    int64_t D = (int64_t)(nu * nd);
+    A.D = D;
+    try {
+        A.rowptr.assign(D + 1, 0);
+    } catch (...) {
+        return fail(FD_ERR_OOM, "Hubbard: host allocation");
+    }
+    for (uint64_t a = 0; a < nu; a++)
+        for (uint64_t b = 0; b < nd; b++)
+            A.rowptr[a * nd + b + 1] = 1 + (ou[a + 1] - ou[a]) + (od[b + 1] - od[b]);
+    for (int64_t i = 0; i < D; i++) A.rowptr[i + 1] += A.rowptr[i];
+    int64_t nnz = A.rowptr[D];
+    try {
+        A.col.resize(nnz);
+        A.val.resize(nnz);
+    } catch (...) {
+        return fail(FD_ERR_OOM, "Hubbard: host allocation");
+    }
+    parallel_for((int64_t)nu, [&](int64_t a0, int64_t a1) {
+        for (int64_t a = a0; a < a1; a++) {
+            for (uint64_t b = 0; b < nd; b++) {
+                int64_t row = a * (int64_t)nd + b;
+                int64_t k = A.rowptr[row];
+                const Hop *ub = hu.data() + ou[a], *ue = hu.data() + ou[a + 1];
+                const Hop *db = hd.data() + od[b], *de = hd.data() + od[b + 1];
+                // up hops into earlier blocks
+                for (const Hop *h = ub; h != ue && h->rank < (uint64_t)a; ++h) {
+                    A.col[k] = (uint32_t)(h->rank * nd + b);
+                    A.val[k++] = h->el;
+                }
+                // the block of row a: down hops and the diagonal, by column
+                bool diag_done = false;
+                for (const Hop *h = db; h != de; ++h) {
+                    if (!diag_done && h->rank > b) {
+                        A.col[k] = (uint32_t)row;
+                        A.val[k++] = U * (double)__builtin_popcountll(mu[a] & md[b]);
+                        diag_done = true;
+                    }
+                    A.col[k] = (uint32_t)(a * nd + h->rank);
+                    A.val[k++] = h->el;
+                }
+                if (!diag_done) {
+                    A.col[k] = (uint32_t)row;
+                    A.val[k++] = U * (double)__builtin_popcountll(mu[a] & md[b]);
+                }
+                // up hops into later blocks
+                for (const Hop *h = ub; h != ue; ++h)
+                    if (h->rank > (uint64_t)a) {
+                        A.col[k] = (uint32_t)(h->rank * nd + b);
+                        A.val[k++] = h->el;
+                    }
+            }
+        }
+    });
+    return FD_OK;
+}
+
+fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A) {
+    if (L < 3 || (int64_t)L * L * L >= (1LL << 32))
+        return fail(FD_ERR_INVALID, "Anderson: need L >= 3 and L^3 < 2^32");
+    const int64_t L1 = L, L2 = (int64_t)L * L, D = L2 * L;
+    A.D = D;
+    try {
+        A.rowptr.resize(D + 1);
+        A.col.resize(7 * D);
+        A.val.resize(7 * D);
+    } catch (...) {
+        return fail(FD_ERR_OOM, "Anderson: host allocation");
+    }
+    parallel_for(D, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; i++) {
+            // SplitMix64 is counter based: the state after i+1 draws is
+            // seed + (i+1) * gamma, so row i's disorder needs no sequential pass.
+            uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+            z ^= z >> 31;
+            double u = (double)(z >> 11) * 0x1.0p-53;
+            int64_t x = i % L1, y = (i / L1) % L1, zz = i / L2;
+            int64_t nbr[7] = {i,
+                              i - x + (x + 1) % L1, i - x + (x + L1 - 1) % L1,
+                              i + L1 * (((y + 1) % L1) - y), i + L1 * (((y + L1 - 1) % L1) - y),
+                              i + L2 * (((zz + 1) % L1) - zz), i + L2 * (((zz + L1 - 1) % L1) - zz)};
+            std::sort(nbr, nbr + 7);
+            A.rowptr[i] = 7 * i;
+            for (int p = 0; p < 7; p++) {
+                A.col[7 * i + p] = (uint32_t)nbr[p];
+                A.val[7 * i + p] = (nbr[p] == i) ? W * (u - 0.5) : -t;
+            }
+        }
+    });
+    A.rowptr[D] = 7 * D;
+    return FD_OK;
+}
+
+fd_status build_diagonal(int64_t n, const double *d, HostCSR &A) {
+    if (n < 1 || !d || n >= (1LL << 32)) return fail(FD_ERR_INVALID, "diagonal: need 1 <= n < 2^32 and data");
+    A.D = n;
+    A.rowptr.resize(n + 1);
+    A.col.resize(n);
+    A.val.assign(d, d + n);
+    for (int64_t i = 0; i <= n; i++) A.rowptr[i] = i;
+    for (int64_t i = 0; i < n; i++) A.col[i] = (uint32_t)i;
+    return FD_OK;
+}
+
+fd_status build_user(int64_t D, const int64_t *rowptr, const uint32_t *col, const double *val,
+                     HostCSR &A) {
+    if (D < 1 || D >= (1LL << 32) || !rowptr || !col || !val)
+        return fail(FD_ERR_INVALID, "user CSR: need 1 <= D < 2^32 and arrays");
+    if (rowptr[0] != 0) return fail(FD_ERR_INVALID, "user CSR: rowptr[0] != 0");
+    for (int64_t i = 0; i < D; i++) {
+        if (rowptr[i + 1] < rowptr[i]) return fail(FD_ERR_INVALID, "user CSR: rowptr decreasing");
+        bool has_diag = false;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) {
+            if (col[k] >= (uint64_t)D) return fail(FD_ERR_INVALID, "user CSR: column out of range");
+            if (k > rowptr[i] && col[k] <= col[k - 1])
+                return fail(FD_ERR_INVALID, "user CSR: columns not strictly ascending");
+            has_diag |= (col[k] == (uint64_t)i);
+        }
+        if (!has_diag) return fail(FD_ERR_INVALID, "user CSR: every row must store its diagonal");
+    }
+    int64_t nnz = rowptr[D];
+    A.D = D;
+    A.rowptr.assign(rowptr, rowptr + D + 1);
+    A.col.assign(col, col + nnz);
+    A.val.assign(val, val + nnz);
+    return FD_OK;
+}
+
+fd_status build_sell(const HostCSR &A, int C, int sigma, HostSELL &S) {
+    if (C < 1 || C > 64 || (C & (C - 1)) || sigma < 1)
+        return fail(FD_ERR_INVALID, "SELL: C must be a power of two in [1, 64], sigma >= 1");
+    const int64_t D = A.D;
+    S.C = C;
+    S.sigma = sigma;
+    S.perm.resize(D);
+    std::iota(S.perm.begin(), S.perm.end(), 0);
+    auto len = [&](int32_t r) { return A.rowptr[r + 1] - A.rowptr[r]; };
+    for (int64_t w = 0; w < D; w += sigma) {
+        auto b = S.perm.begin() + w, e = S.perm.begin() + std::min<int64_t>(D, w + sigma);
+        std::stable_sort(b, e, [&](int32_t p, int32_t q) { return len(p) > len(q); });
+    }
+    int64_t nch = (D + C - 1) / C;
+    S.chunk_len.assign(nch, 0);
+    S.chunk_ptr.assign(nch + 1, 0);
+    for (int64_t s = 0; s < D; s++) {
+        int32_t &cl = S.chunk_len[s / C];
+        cl = std::max<int32_t>(cl, (int32_t)len(S.perm[s]));
+    }
+    for (int64_t c = 0; c < nch; c++) S.chunk_ptr[c + 1] = S.chunk_ptr[c] + (int64_t)S.chunk_len[c] * C;
+    int64_t total = S.chunk_ptr[nch];
+    try {
+        S.col.assign(total, 0);
+        S.val.assign(total, 0.0);
+    } catch (...) {
+        return fail(FD_ERR_OOM, "SELL: host allocation");
+    }
+    parallel_for(nch, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; c++) {
+            for (int r = 0; r < C; r++) {
+                int64_t s = c * C + r;
+                if (s >= D) continue;  // padding slots past D keep column 0, value 0
+                int32_t o = S.perm[s];
+                int64_t b = A.rowptr[o], n = len(o);
+                for (int64_t j = 0; j < S.chunk_len[c]; j++) {
+                    int64_t at = S.chunk_ptr[c] + j * C + r;
+                    if (j < n) {
+                        S.col[at] = A.col[b + j];
+                        S.val[at] = A.val[b + j];
+                    } else {
+                        S.col[at] = (uint32_t)o;
+                    }
+                }
+            }
+        }
+    });
+    return FD_OK;
+}
+
+void gershgorin(const HostCSR &A, double &lo, double &hi) {
+    lo = INFINITY;
+    hi = -INFINITY;
+    for (int64_t i = 0; i < A.D; i++) {
+        double c = 0, r = 0;
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; k++) {
+            if (A.col[k] == (uint64_t)i) c += A.val[k];
+            else r += std::fabs(A.val[k]);
+        }
+        lo = std::min(lo, c - r);
+        hi = std::max(hi, c + r);
+    }
+}
+
+// Window coefficients (Sec. 2: p(x) = sum_k mu_k T_k(x)).  The indicator of
+// [a, b] has c_k = (2 - delta_k0)/pi * int_{acos b}^{acos a} cos(k th) dth;
+// Jackson damping for M = n + 1 moments multiplies by
+// g_k = [(M - k + 1) cos(k q) + sin(k q) cot q] / (M + 1), q = pi / (M + 1).
+fd_status cheb_coeffs(int kind, double a, double b, int n, double *mu) {
+    if (n < 0 || !mu) return fail(FD_ERR_INVALID, "coefficients: need degree >= 0");
+    if (!(a >= -1.0 && a <= 1.0)) return fail(FD_ERR_INVALID, "coefficients: a outside [-1, 1]");
+    if (kind == 0 && !(b >= a && b <= 1.0)) return fail(FD_ERR_INVALID, "coefficients: need a <= b <= 1");
+    if (kind != 0 && kind != 1) return fail(FD_ERR_INVALID, "coefficients: kind must be 0 or 1");
+    const double M = n + 1.0, q = M_PI / (M + 1.0), cotq = std::cos(q) / std::sin(q);
+    const double tha = std::acos(a), thb = (kind == 0) ? std::acos(b) : 0.0;
+    for (int k = 0; k <= n; k++) {
+        double g = ((M - k + 1.0) * std::cos(k * q) + std::sin(k * q) * cotq) / (M + 1.0);
+        double c;
+        if (kind == 0)
+            c = (k == 0) ? (tha - thb) / M_PI : 2.0 / (k * M_PI) * (std::sin(k * tha) - std::sin(k * thb));
+        else
+            c = (k == 0 ? 1.0 : 2.0) * std::cos(k * tha);
+        mu[k] = g * c;
+    }
+    return FD_OK;
+}
+
+}  // namespace fd

@@ -1,0 +1,703 @@
+// Dense FP64 kernels for the orthogonalization and Rayleigh-Ritz steps on
+// gfx950.
+//
+// Sec. 2 / Sec. 3: after each filter application the N_s search vectors are
+// orthogonalized (SVQB needs only the N_s x N_s Gram matrix V^t V), and one
+// more SpMV gives the Ritz values.  Both reduce to tall-skinny products over
+// D rows (X^t Y and X Q) -- dense contractions, done here on the FP64 matrix
+// cores with v_mfma_f64_16x16x4_f64 -- plus work on N_s x N_s matrices that
+// runs inside one workgroup (parallel cyclic Jacobi, Cholesky, triangular
+// inverse).  Reductions over D are two-stage with a fixed order, so repeated
+// runs are bitwise identical.
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// MFMA f64 16x16x4 operand layout (lane l = i + 16 k):
+//   A[i][k] (16 x 4) and B[k][j] (4 x 16) hold one double per lane;
+//   the 16 x 16 result keeps D[4 (l >> 4) + r][l & 15] in element r.
+__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------ workspace --
+namespace {
+struct WsSlot {
+    void *p = nullptr;
+    size_t n = 0;
+    int dev = -1;
+};
+std::mutex g_ws_mu;
+WsSlot g_ws[8];
+}  // namespace
+
+void *workspace(size_t bytes, int slot) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    WsSlot &w = g_ws[slot];
+    if (w.p && w.n >= bytes && w.dev == dev) return w.p;
+    if (w.p) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(w.p);
+        w.p = nullptr;
+        w.n = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 1 << 20);
+    if (hipMalloc(&w.p, want) != hipSuccess) {
+        w.p = nullptr;
+        return nullptr;
+    }
+    w.n = want;
+    w.dev = dev;
+    return w.p;
+}
+
+// ----------------------------------------------------------------- Gram --
+namespace {
+
+constexpr int GT = 64;  // Gram tile edge per wave
+
+struct TileList {
+    int n;
+    unsigned char ti[64], tj[64];
+};
+
+__global__ __launch_bounds__(64) void k_gram(const double *__restrict__ X, int64_t ldx,
+                                              const double *__restrict__ Y, int64_t ldy,
+                                              int64_t D, int m, int n, int64_t rps, TileList tl,
+                                              double *__restrict__ P) {
+    const int tile = blockIdx.x;
+    const int64_t slice = blockIdx.y;
+    const int ti = tl.ti[tile], tj = tl.tj[tile];
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int64_t r0 = slice * rps;
+    const int64_t r1 = min(D, r0 + rps);
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = (dbl4)0.0;
+    int ca[4], cb[4];
+    bool va[4], vb[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        ca[q] = ti * GT + q * 16 + li;
+        cb[q] = tj * GT + q * 16 + li;
+        va[q] = ca[q] < m;
+        vb[q] = cb[q] < n;
+    }
+    for (int64_t r = r0; r < r1; r += 4) {
+        const int64_t rr = r + lk;
+        const bool rv = rr < r1;
+        double a[4], b[4];
+        const double *xr = X + rr * ldx;
+        const double *yr = Y + rr * ldy;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            a[q] = (rv && va[q]) ? xr[ca[q]] : 0.0;
+            b[q] = (rv && vb[q]) ? yr[cb[q]] : 0.0;
+        }
+#pragma unroll
+        for (int qa = 0; qa < 4; qa++)
+#pragma unroll
+            for (int qb = 0; qb < 4; qb++) acc[qa][qb] = mfma16x16x4(a[qa], b[qb], acc[qa][qb]);
+    }
+    double *out = P + ((int64_t)slice * tl.n + tile) * (GT * GT);
+#pragma unroll
+    for (int qa = 0; qa < 4; qa++)
+#pragma unroll
+        for (int qb = 0; qb < 4; qb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int il = qa * 16 + 4 * (lane >> 4) + r;
+                const int jl = qb * 16 + (lane & 15);
+                out[il * GT + jl] = acc[qa][qb][r];
+            }
+}
+
+__global__ void k_gram_reduce(const double *__restrict__ P, int S, int ntiles, int m, int n,
+                              bool sym, int nt_n, double *__restrict__ G, int64_t ldg) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    if (sym && i > j) {
+        int t = i;
+        i = j;
+        j = t;
+    }
+    const int ti = i / GT, tj = j / GT;
+    int tile;
+    if (sym) {
+        // upper-triangle tiles listed row by row: (0,0..T-1), (1,1..T-1), ...
+        tile = ti * nt_n - ti * (ti - 1) / 2 + (tj - ti);
+    } else {
+        tile = ti * nt_n + tj;
+    }
+    const int64_t off = (int64_t)tile * (GT * GT) + (i % GT) * GT + (j % GT);
+    double s = 0.0;
+    for (int k = 0; k < S; k++) s += P[(int64_t)k * ntiles * (GT * GT) + off];
+    G[(e / n) * ldg + (e % n)] = s;
+}
+
+}  // namespace
+
+fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const double *Y,
+               int64_t ldy, double *G, int64_t ldg, bool sym, hipStream_t s) {
+    if (m < 1 || n < 1 || m > 512 || n > 512 || D < 1)
+        return fail(FD_ERR_INVALID, "gram: need 1 <= m, n <= 512 and D >= 1");
+    if (sym && m != n) return fail(FD_ERR_INVALID, "gram: symmetric product needs m == n");
+    const int ntm = (m + GT - 1) / GT, ntn = (n + GT - 1) / GT;
+    TileList tl;
+    tl.n = 0;
+    for (int a = 0; a < ntm; a++)
+        for (int b = sym ? a : 0; b < ntn; b++) {
+            tl.ti[tl.n] = (unsigned char)a;
+            tl.tj[tl.n] = (unsigned char)b;
+            tl.n++;
+        }
+    int64_t target = std::max<int64_t>(1, 2048 / tl.n);
+    int64_t rps = std::max<int64_t>(256, (D + target - 1) / target);
+    rps = (rps + 3) / 4 * 4;
+    int64_t S = (D + rps - 1) / rps;
+    double *P = (double *)workspace((size_t)S * tl.n * GT * GT * sizeof(double), 0);
+    if (!P) return fail(FD_ERR_OOM, "gram: workspace");
+    hipLaunchKernelGGL(k_gram, dim3(tl.n, (unsigned)S), dim3(64), 0, s, X, ldx, Y, ldy, D, m, n, rps,
+                       tl, P);
+    FD_HIP(hipGetLastError());
+    const int64_t tot = (int64_t)m * n;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, P, (int)S,
+                       tl.n, m, n, sym, ntn, G, ldg);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+// ------------------------------------------------------------- rotation --
+namespace {
+
+template <int TM>
+__global__ __launch_bounds__(512) void k_rotate(double *__restrict__ X, int64_t ldx, int64_t D,
+                                                 int m, int n, const double *__restrict__ Q,
+                                                 int64_t ldq, int ls, int g) {
+    extern __shared__ double sX[];
+    const int64_t r0 = (int64_t)blockIdx.x * TM;
+    const int m4 = (m + 3) & ~3;
+    for (int e = threadIdx.x; e < TM * m4; e += 512) {
+        const int r = e / m4, k = e - r * m4;
+        const int64_t rr = r0 + r;
+        sX[r * ls + k] = (rr < D && k < m) ? X[rr * ldx + k] : 0.0;
+    }
+    __syncthreads();
+    constexpr int RB = TM / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int ncb = (n + 15) >> 4;
+    const int cb0 = wave * g;
+    if (cb0 >= ncb) return;
+    dbl4 acc[RB][4];
+#pragma unroll
+    for (int a = 0; a < RB; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = (dbl4)0.0;
+    int cc[4];
+    bool cv[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        cc[q] = (cb0 + q) * 16 + li;
+        cv[q] = (q < g) && (cc[q] < n);
+    }
+    for (int k0 = 0; k0 < m4; k0 += 4) {
+        const int kk = k0 + lk;
+        const bool kv = kk < m;
+        double b[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] = (kv && cv[q]) ? Q[(int64_t)kk * ldq + cc[q]] : 0.0;
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const double a = sX[(rb * 16 + li) * ls + kk];
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (q < g) acc[rb][q] = mfma16x16x4(a, b[q], acc[rb][q]);
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (q >= g) continue;
+            const int col = (cb0 + q) * 16 + (lane & 15);
+            if (col >= n) continue;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t row = r0 + rb * 16 + 4 * (lane >> 4) + r;
+                if (row < D) X[row * ldx + col] = acc[rb][q][r];
+            }
+        }
+}
+
+}  // namespace
+
+fd_status rotate(int64_t D, int m, int n, double *X, int64_t ldx, const double *Q, int64_t ldq,
+                 hipStream_t s) {
+    if (m < 1 || n < 1 || n > m || m > 512 || D < 1)
+        return fail(FD_ERR_INVALID, "rotate: need 1 <= n <= m <= 512 and D >= 1");
+    const int m4 = (m + 3) & ~3;
+    const int ls = ((m4 + 31) / 32) * 32 + 4;  // padded LDS row: spreads the 16 rows over banks
+    const int ncb = (n + 15) / 16;
+    const int g = std::min(4, (ncb + 7) / 8);
+    if (m <= 256) {
+        size_t sh = (size_t)64 * ls * sizeof(double);
+        FD_HIP(hipFuncSetAttribute((const void *)k_rotate<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)sh));
+        hipLaunchKernelGGL(k_rotate<64>, dim3((unsigned)((D + 63) / 64)), dim3(512), sh, s, X, ldx, D, m, n,
+                           Q, ldq, ls, g);
+    } else {
+        size_t sh = (size_t)32 * ls * sizeof(double);
+        FD_HIP(hipFuncSetAttribute((const void *)k_rotate<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)sh));
+        hipLaunchKernelGGL(k_rotate<32>, dim3((unsigned)((D + 31) / 32)), dim3(512), sh, s, X, ldx, D, m, n,
+                           Q, ldq, ls, g);
+    }
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+// -------------------------------------------------------------- Jacobi --
+namespace {
+
+constexpr int JT = 1024;  // threads of the one-workgroup small-matrix kernels
+
+__device__ double block_sum(double v, double *red) {
+    // fixed-order tree reduction over the 1024 threads
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = JT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Cyclic Jacobi with the round-robin ("chess tournament") ordering: in each
+// round the N/2 disjoint index pairs are rotated at once -- rows of all pairs
+// first, then columns -- so one round applies J^t A J for J a product of
+// commuting plane rotations.  A (n x n, ld lda) may live in LDS or global
+// memory; U (ld ldu) accumulates the rotations.
+__device__ void jacobi_body(int n, double *A, int lda, double *U, int ldu, double *cs_c,
+                            double *cs_s, int *pp, int *pq, double *red) {
+    const int tid = threadIdx.x;
+    const int N = n + (n & 1);  // even number of "players"; index n is a dummy
+    const int half = N / 2;
+    for (int e = tid; e < n * n; e += JT) {
+        const int i = e / n, j = e % n;
+        U[(int64_t)i * ldu + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double fro = 0.0;
+    for (int e = tid; e < n * n; e += JT) {
+        const double a = A[(e / n) * lda + e % n];
+        fro += a * a;
+    }
+    fro = block_sum(fro, red);
+    for (int sweep = 0; sweep < 40; sweep++) {
+        double off = 0.0;
+        for (int e = tid; e < n * n; e += JT) {
+            const int i = e / n, j = e % n;
+            if (i != j) {
+                const double a = A[i * lda + j];
+                off += a * a;
+            }
+        }
+        off = block_sum(off, red);
+        if (!(off > 1e-32 * fro)) break;  // also stops on NaN
+        for (int rnd = 0; rnd < N - 1; rnd++) {
+            for (int k = tid; k < half; k += JT) {
+                // circle method: position 0 fixed, positions 1..N-1 rotate
+                auto who = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + rnd) % (N - 1); };
+                int p = who(k), q = who(N - 1 - k);
+                if (p > q) {
+                    int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[p * lda + q];
+                    if (apq != 0.0) {
+                        const double app = A[p * lda + p], aqq = A[q * lda + q];
+                        const double th = (aqq - app) / (2.0 * apq);
+                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                pp[k] = p;
+                pq[k] = q;
+                cs_c[k] = c;
+                cs_s[k] = s;
+            }
+            __syncthreads();
+            // rows p, q  <-  (c row_p - s row_q, s row_p + c row_q)
+            for (int e = tid; e < half * n; e += JT) {
+                const int k = e / n, j = e % n;
+                const int p = pp[k], q = pq[k];
+                const double s = cs_s[k];
+                if (q >= n || s == 0.0) continue;
+                const double c = cs_c[k];
+                const double ap = A[p * lda + j], aq = A[q * lda + j];
+                A[p * lda + j] = c * ap - s * aq;
+                A[q * lda + j] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns p, q of A and U
+            for (int e = tid; e < half * n; e += JT) {
+                const int k = e / n, i = e % n;
+                const int p = pp[k], q = pq[k];
+                const double s = cs_s[k];
+                if (q >= n || s == 0.0) continue;
+                const double c = cs_c[k];
+                const double ap = A[i * lda + p], aq = A[i * lda + q];
+                A[i * lda + p] = c * ap - s * aq;
+                A[i * lda + q] = s * ap + c * aq;
+                const double up = U[(int64_t)i * ldu + p], uq = U[(int64_t)i * ldu + q];
+                U[(int64_t)i * ldu + p] = c * up - s * uq;
+                U[(int64_t)i * ldu + q] = s * up + c * uq;
+            }
+            __syncthreads();
+            for (int k = tid; k < half; k += JT) {
+                const int p = pp[k], q = pq[k];
+                if (q < n && cs_s[k] != 0.0) {
+                    A[p * lda + q] = 0.0;
+                    A[q * lda + p] = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// eigenvalues ascending (ties by index), eigenvector columns permuted alike
+__device__ void jacobi_sort(int n, const double *A, int lda, const double *U, int ldu, double *w,
+                            double *Uo, int64_t ldo) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += JT) {
+        const double wi = A[i * lda + i];
+        int r = 0;
+        for (int j = 0; j < n; j++) {
+            const double wj = A[j * lda + j];
+            r += (wj < wi) || (wj == wi && j < i);
+        }
+        w[r] = wi;
+        for (int k = 0; k < n; k++) Uo[(int64_t)k * ldo + r] = U[(int64_t)k * ldu + i];
+    }
+}
+
+__global__ __launch_bounds__(JT) void k_syev(int n, double *S, int64_t lds, double *w, double *Uo,
+                                               int64_t ldo, double *Uw, int in_lds) {
+    extern __shared__ double sh[];
+    __shared__ double red[JT];
+    __shared__ double cs_c[256], cs_s[256];
+    __shared__ int pp[256], pq[256];
+    double *A;
+    int lda;
+    if (in_lds) {
+        A = sh;
+        lda = n + 1;
+        for (int e = threadIdx.x; e < n * n; e += JT) A[(e / n) * lda + e % n] = S[(e / n) * lds + e % n];
+        __syncthreads();
+    } else {
+        A = S;
+        lda = (int)lds;
+    }
+    jacobi_body(n, A, lda, Uw, n, cs_c, cs_s, pp, pq, red);
+    __syncthreads();
+    jacobi_sort(n, A, lda, Uw, n, w, Uo, ldo);
+    if (in_lds) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += JT) S[(e / n) * lds + e % n] = A[(e / n) * lda + e % n];
+    }
+}
+
+size_t syev_lds(int n) { return (size_t)n * (n + 1) * sizeof(double); }
+
+fd_status launch_syev(int n, double *S, int64_t lds, double *w, double *Uo, int64_t ldo, double *Uw,
+                      hipStream_t s) {
+    const bool in_lds = syev_lds(n) <= 144 * 1024;  // + 14 KB static LDS, under 160 KB
+    size_t sh = in_lds ? syev_lds(n) : 0;
+    FD_HIP(hipFuncSetAttribute((const void *)k_syev, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)std::max<size_t>(sh, 1)));
+    hipLaunchKernelGGL(k_syev, dim3(1), dim3(JT), sh, s, n, S, lds, w, Uo, ldo, Uw, in_lds ? 1 : 0);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+}  // namespace
+
+fd_status syev(int n, double *S, int64_t lds, double *w, double *U, int64_t ldu, hipStream_t s) {
+    if (n < 1 || n > 512) return fail(FD_ERR_INVALID, "syev: need 1 <= n <= 512");
+    double *Uw = (double *)workspace((size_t)n * n * sizeof(double), 1);
+    if (!Uw) return fail(FD_ERR_OOM, "syev: workspace");
+    return launch_syev(n, S, lds, w, U, ldu, Uw, s);
+}
+
+// ------------------------------------------------------ SVQB / CholQR ----
+namespace {
+
+// G (n x n, ld n) -> Dg G Dg in place; d[i] = 1/sqrt(G_ii) (1 for G_ii <= 0)
+__global__ void k_scale_gram(int n, double *G, double *d) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double g = G[i * n + i];
+        d[i] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) G[e] *= d[e / n] * d[e % n];
+}
+
+// Q = Dg U L^-1/2 with L clipped at 1e-14 max(L); keep[j] = L_j > floor
+__global__ void k_svqb_q(int n, const double *d, const double *lam, const double *U, double *Q,
+                         int *keep, int *rank) {
+    __shared__ double fl;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int j = 0; j < n; j++) mx = fmax(mx, lam[j]);
+        fl = 1e-14 * mx;
+        cnt = 0;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const bool k = lam[j] > fl && fl > 0.0;
+        keep[j] = k ? 1 : 0;
+        if (k) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        const double l = fmax(lam[j], fl > 0.0 ? fl : 1.0);
+        Q[e] = d[i] * U[e] / sqrt(l);
+    }
+    if (threadIdx.x == 0) *rank = cnt;
+}
+
+// G = R^t R (R upper), then Q = R^-1; ok = 0 if a pivot is not positive
+__global__ __launch_bounds__(1024) void k_cholinv(int n, double *G, double *Q, int *ok) {
+    __shared__ int good;
+    if (threadIdx.x == 0) good = 1;
+    __syncthreads();
+    for (int k = 0; k < n; k++) {
+        const double piv = G[k * n + k];
+        if (!(piv > 0.0)) {
+            if (threadIdx.x == 0) good = 0;
+            break;
+        }
+        const double r = sqrt(piv);
+        __syncthreads();
+        for (int j = k + threadIdx.x; j < n; j += blockDim.x) G[k * n + j] = (j == k) ? r : G[k * n + j] / r;
+        __syncthreads();
+        const int rem = n - k - 1;
+        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+            const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+            if (j >= i) G[i * n + j] -= G[k * n + i] * G[k * n + j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (!good) {
+        if (threadIdx.x == 0) *ok = 0;
+        return;
+    }
+    // column j of X = R^-1: back substitution, one column per thread
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        for (int i = n - 1; i >= 0; i--) {
+            double s = (i == j) ? 1.0 : 0.0;
+            if (i > j) {
+                Q[i * n + j] = 0.0;
+                continue;
+            }
+            for (int k = i + 1; k <= j; k++) s -= G[i * n + k] * Q[k * n + j];
+            Q[i * n + j] = s / G[i * n + i];
+        }
+    }
+    if (threadIdx.x == 0) *ok = 1;
+}
+
+}  // namespace
+
+fd_status svqb_transform(int n, double *G, double *Q, double *work, int *keep, int *rank_dev,
+                         hipStream_t s) {
+    // work: d (n) + lam (n) + U (n*n)
+    double *d = work, *lam = work + n, *U = work + 2 * n;
+    hipLaunchKernelGGL(k_scale_gram, dim3(1), dim3(1024), 0, s, n, G, d);
+    FD_HIP(hipGetLastError());
+    FD_TRY(syev(n, G, n, lam, U, n, s));
+    hipLaunchKernelGGL(k_svqb_q, dim3(1), dim3(1024), 0, s, n, d, lam, U, Q, keep, rank_dev);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), 0, s, n, G, Q, ok_dev);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+// ----------------------------------------------------- residual norms ----
+namespace {
+
+__global__ __launch_bounds__(256) void k_resid_part(int64_t D, int n, const double *__restrict__ V,
+                                                    const double *__restrict__ W, int64_t ld,
+                                                    const double *__restrict__ theta, int64_t rpb,
+                                                    double *__restrict__ P) {
+    const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = min(D, r0 + rpb);
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double th = theta[j];
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; r++) {
+            const double e = W[r * ld + j] - th * V[r * ld + j];
+            s += e * e;
+        }
+        P[(int64_t)blockIdx.x * n + j] = s;
+    }
+}
+
+__global__ void k_resid_final(int nblk, int n, const double *P, double *rho) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) s += P[(int64_t)b * n + j];
+    rho[j] = sqrt(s);
+}
+
+}  // namespace
+
+fd_status col_resid(int64_t D, int n, const double *V, const double *W, int64_t ld, const double *theta,
+                    double *rho, hipStream_t s) {
+    int64_t rpb = std::max<int64_t>(64, (D + 2047) / 2048);
+    int nblk = (int)((D + rpb - 1) / rpb);
+    double *P = (double *)workspace((size_t)nblk * n * sizeof(double), 2);
+    if (!P) return fail(FD_ERR_OOM, "resid: workspace");
+    hipLaunchKernelGGL(k_resid_part, dim3(nblk), dim3(256), 0, s, D, n, V, W, ld, theta, rpb, P);
+    FD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_resid_final, dim3((n + 255) / 256), dim3(256), 0, s, nblk, n, P, rho);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+// --------------------------------------------------- element-wise kernels --
+namespace {
+
+__device__ __forceinline__ uint64_t smix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// N(0,1) for entry (i, j) of a D x n block: SplitMix64 outputs number
+// 2 (i n + j) + 1 and + 2 of the stream `seed` (counter based), Box-Muller
+// with u1 -> 1 - u1 so that the logarithm stays finite.
+__device__ __forceinline__ double normal_at(uint64_t seed, int64_t i, int n, int j) {
+    const uint64_t c = 2 * ((uint64_t)i * (uint64_t)n + (uint64_t)j);
+    const uint64_t g = 0x9E3779B97F4A7C15ULL;
+    const double u1 = (double)(smix(seed + (c + 1) * g) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(smix(seed + (c + 2) * g) >> 11) * 0x1.0p-53;
+    return sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
+}
+
+__global__ void k_fill_normal(int64_t D, int n, double *V, int64_t ldv, const int *keep, uint64_t seed) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D * n) return;
+    const int64_t i = e / n;
+    const int j = (int)(e % n);
+    if (keep && keep[j]) return;
+    V[i * ldv + j] = normal_at(seed, i, n, j);
+}
+
+__global__ void k_f64_to_f32(int64_t D, int n, const double *a, int64_t la, float *b, int64_t lb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D * n) return;
+    const int64_t i = e / n;
+    const int j = (int)(e % n);
+    b[i * lb + j] = (float)a[i * la + j];
+}
+
+__global__ void k_f32_to_f64(int64_t D, int n, const float *a, int64_t la, double *b, int64_t lb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D * n) return;
+    const int64_t i = e / n;
+    const int j = (int)(e % n);
+    b[i * lb + j] = (double)a[i * la + j];
+}
+
+__global__ void k_gather_cols(int64_t D, int n, const double *a, int64_t la, const int *idx, double *b,
+                              int64_t lb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D * n) return;
+    const int64_t i = e / n;
+    const int j = (int)(e % n);
+    b[i * lb + j] = a[i * la + idx[j]];
+}
+
+__global__ void k_symmetrize(int n, double *H) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int i = e / n, j = e % n;
+    if (i < j) {
+        const double a = 0.5 * (H[i * n + j] + H[j * n + i]);
+        H[i * n + j] = a;
+        H[j * n + i] = a;
+    }
+}
+
+unsigned nblocks(int64_t tot) { return (unsigned)((tot + 255) / 256); }
+
+}  // namespace
+
+fd_status fill_normal(int64_t D, int n, double *V, int64_t ldv, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_normal, dim3(nblocks(D * n)), dim3(256), 0, s, D, n, V, ldv, (const int *)nullptr,
+                       seed);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status refill_random(int64_t D, int n, double *V, int64_t ldv, const int *keep, uint64_t seed,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_normal, dim3(nblocks(D * n)), dim3(256), 0, s, D, n, V, ldv, keep, seed);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status convert_f64_f32(int64_t D, int n, const double *src, int64_t lds, float *dst, int64_t ldd,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(nblocks(D * n)), dim3(256), 0, s, D, n, src, lds, dst, ldd);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status convert_f32_f64(int64_t D, int n, const float *src, int64_t lds, double *dst, int64_t ldd,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(nblocks(D * n)), dim3(256), 0, s, D, n, src, lds, dst, ldd);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status gather_cols(int64_t D, int n, const double *src, int64_t lds, const int *idx, double *dst,
+                      int64_t ldd, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_cols, dim3(nblocks(D * n)), dim3(256), 0, s, D, n, src, lds, idx, dst, ldd);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status symmetrize(int n, double *H, hipStream_t s) {
+    hipLaunchKernelGGL(k_symmetrize, dim3(nblocks((int64_t)n * n)), dim3(256), 0, s, n, H);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+}  // namespace fd

@@ -1,0 +1,136 @@
+// Internal declarations shared by the libfd translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fd.h"
+
+namespace fd {
+
+// ------------------------------------------------------------------ errors --
+fd_status fail(fd_status st, const std::string &msg);
+fd_status hip_fail(hipError_t e, const char *what);
+
+#define FD_HIP(call)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return ::fd::hip_fail(e_, #call);           \
+    } while (0)
+
+#define FD_TRY(call)                                                      \
+    do {                                                                  \
+        fd_status s_ = (call);                                            \
+        if (s_ != FD_OK) return s_;                                       \
+    } while (0)
+
+// ------------------------------------------------------------ host matrix --
+struct HostCSR {
+    int64_t D = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<uint32_t> col;
+    std::vector<double> val;
+};
+
+struct HostSELL {
+    int32_t C = 1, sigma = 1;
+    std::vector<int32_t> perm;       // perm[new] = old
+    std::vector<int64_t> chunk_ptr;  // nchunks + 1
+    std::vector<int32_t> chunk_len;  // nchunks
+    std::vector<uint32_t> col;
+    std::vector<double> val;
+};
+
+fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, HostCSR &A);
+fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A);
+fd_status build_diagonal(int64_t n, const double *d, HostCSR &A);
+fd_status build_user(int64_t D, const int64_t *rowptr, const uint32_t *col, const double *val,
+                     HostCSR &A);
+fd_status build_sell(const HostCSR &A, int C, int sigma, HostSELL &S);
+void gershgorin(const HostCSR &A, double &lo, double &hi);
+fd_status cheb_coeffs(int kind, double a, double b, int n, double *mu);
+
+// --------------------------------------------------------- device matrix --
+// One layout serves CSR and SELL: "slot" s of the device format belongs to
+// chunk s >> cshift; its entries start at ptr[chunk] + (s & (C-1)) and step
+// by C; the chunk length is (ptr[chunk+1] - ptr[chunk]) >> cshift.  CSR is
+// the case C = 1 (cshift 0, ptr = rowptr) with no permutation.
+struct DevMatrix {
+    int64_t D = 0;
+    int32_t cshift = 0;
+    int64_t nslots = 0;        // D rounded up to a multiple of C
+    int64_t stored = 0;        // value slots incl. padding
+    uint32_t *ptr = nullptr;   // nchunks + 1
+    uint32_t *col = nullptr;   // stored
+    double *val64 = nullptr;   // stored
+    float *val32 = nullptr;    // stored
+    int32_t *perm = nullptr;   // nslots (SELL) or null (CSR); -1 for padding slots
+};
+
+}  // namespace fd
+
+struct fd_matrix_s {
+    fd_format fmt = FD_FMT_CSR;
+    fd::HostCSR csr;
+    fd::HostSELL sell;
+    double lam_lo = 0, lam_hi = 0;
+    int device = -1;
+    fd::DevMatrix dev;
+};
+
+namespace fd {
+
+// -------------------------------------------------------- kernel launchers --
+// Sparse kernels (fd_spmmv.hip).  mode: 0 y = A x; 1 y = a A x + b x;
+// 2 t = a A x + b x - v, y = t, v = cv v + cx x + ct t;
+// 3 t = a A x + b x - z, y = t (y may alias z), v = v + ct t.
+struct SpmmvCall {
+    int mode = 0;
+    int nb = 1;
+    int nbundles = 1;          // bundles in this launch (grid y)
+    const void *x = nullptr;   int64_t ldx = 0; int64_t bx = 0;  // bx: column offset per bundle
+    void *y = nullptr;         int64_t ldy = 0; int64_t by = 0;
+    const void *z = nullptr;   int64_t ldz = 0; int64_t bz = 0;
+    void *v = nullptr;         int64_t ldv = 0; int64_t bv = 0;
+    double a = 1, b = 0, cv = 0, cx = 0, ct = 0;
+};
+fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s);
+
+// Tunables of the sparse kernels (rows per block and XCD mapping).
+struct SpmmvTune {
+    int iters = 4;     // row groups per wave
+    int xcd = 1;       // 1: contiguous row range per XCD
+};
+SpmmvTune &spmmv_tune();
+
+// Dense kernels (fd_dense.hip).
+fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const double *Y,
+               int64_t ldy, double *G, int64_t ldg, bool sym, hipStream_t s);
+fd_status rotate(int64_t D, int m, int n, double *X, int64_t ldx, const double *Q, int64_t ldq,
+                 hipStream_t s);
+fd_status syev(int n, double *S, int64_t lds, double *w, double *U, int64_t ldu, hipStream_t s);
+fd_status col_resid(int64_t D, int n, const double *V, const double *W, int64_t ld,
+                    const double *theta, double *rho, hipStream_t s);
+// SVQB transform: Q = Dg U L^-1/2 from Gram G (n x n, dense ld n); returns
+// the rank in *rank_dev (device int) and a keep-mask (device int[n]).
+fd_status svqb_transform(int n, double *G, double *Q, double *work, int *keep, int *rank_dev,
+                         hipStream_t s);
+fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, hipStream_t s);
+fd_status refill_random(int64_t D, int n, double *V, int64_t ldv, const int *keep,
+                        uint64_t seed, hipStream_t s);
+fd_status fill_normal(int64_t D, int n, double *V, int64_t ldv, uint64_t seed, hipStream_t s);
+fd_status convert_f64_f32(int64_t D, int n, const double *src, int64_t lds, float *dst,
+                          int64_t ldd, hipStream_t s);
+fd_status convert_f32_f64(int64_t D, int n, const float *src, int64_t lds, double *dst,
+                          int64_t ldd, hipStream_t s);
+fd_status gather_cols(int64_t D, int n, const double *src, int64_t lds, const int *idx,
+                      double *dst, int64_t ldd, hipStream_t s);
+fd_status symmetrize(int n, double *H, hipStream_t s);
+
+// Process-wide device workspace for the small dense steps.
+void *workspace(size_t bytes, int slot);
+
+}  // namespace fd

@@ -1,0 +1,207 @@
+// Sparse kernels for gfx950: block SpMV (SpMMV) and the fused Chebyshev step.
+//
+// Sec. 3.1 (Eq. SpMVprocess, Eq. traffic): y_i = sum_j A_ij x_j for n_b
+// vectors at once, vectors row-major so that one row of the block (n_b
+// values) is contiguous; each matrix entry is loaded once per n_b vectors.
+// Alg. 2 caption: the SpMV and the vector updates of the Chebyshev step are
+// one kernel, so that W2 is not reloaded (kappa = 5 in Sec. 3.3).
+//
+// Mapping on a 64-wide wavefront: a row of the block (nb values) is split
+// over G lanes that each own VEC consecutive values (16-byte loads when the
+// row is wide enough); a wave covers 64/G rows at a time, a 256-thread block
+// 256/G rows, and each block walks `iters` such row groups.  Matrix entries
+// of a row are broadcast to its G lanes; the gathered rows x[col] are read
+// with one 16-byte load per lane.  With SELL-C-sigma the C rows of a chunk
+// read entry j from consecutive addresses (coalesced); CSR is SELL-1-1.
+// Blocks are remapped so that each of the 8 XCDs walks a contiguous range of
+// rows: stencil neighbours (+-1, +-L) then hit the XCD's own L2.
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+template <typename T, int VEC> struct VecT;
+template <> struct VecT<double, 1> { typedef double type; };
+template <> struct VecT<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct VecT<float, 1> { typedef float type; };
+template <> struct VecT<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct VecT<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+
+template <typename T>
+struct KArgs {
+    const uint32_t *__restrict__ ptr;
+    const uint32_t *__restrict__ col;
+    const T *__restrict__ val;
+    const int32_t *__restrict__ perm;
+    int64_t nslots;
+    int64_t nblk;
+    int32_t cshift;
+    int32_t iters;
+    int32_t xcd;
+    const T *x; int64_t ldx, bx;
+    T *y; int64_t ldy, by;
+    const T *z; int64_t ldz, bz;
+    T *v; int64_t ldv, bv;
+    T a, b, cv, cx, ct;
+};
+
+template <typename V>
+__device__ __forceinline__ V ld(const void *p) { return *reinterpret_cast<const V *>(p); }
+template <typename V>
+__device__ __forceinline__ void st(void *p, V x) { *reinterpret_cast<V *>(p) = x; }
+
+template <typename T, int VEC, int G, int MODE, bool PERM>
+__global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
+    typedef typename VecT<T, VEC>::type V;
+    constexpr int RPB = 256 / G;
+    int64_t blk = blockIdx.x;
+    if (p.xcd) {
+        const int64_t per = (p.nblk + 7) >> 3;
+        blk = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        if (blk >= p.nblk) return;
+    }
+    const int64_t bnd = blockIdx.y;
+    const T *x = p.x + bnd * p.bx;
+    T *y = p.y + bnd * p.by;
+    const int grp = threadIdx.x / G;
+    const int q = threadIdx.x % G;
+    const uint32_t step = 1u << p.cshift;
+    for (int it = 0; it < p.iters; ++it) {
+        const int64_t s = (blk * p.iters + it) * RPB + grp;
+        if (s >= p.nslots) break;
+        const int64_t c = s >> p.cshift;
+        const uint32_t p0 = p.ptr[c];
+        const uint32_t len = (p.ptr[c + 1] - p0) >> p.cshift;
+        const uint32_t base = p0 + (uint32_t)(s & (step - 1));
+        const int64_t row = PERM ? (int64_t)p.perm[s] : s;
+        if (row < 0) continue;  // padding slot past D
+        const T *xq = x + q * VEC;
+        V acc0 = (V)0, acc1 = (V)0;
+        uint32_t j = 0;
+        for (; j + 4 <= len; j += 4) {
+            const uint32_t k = base + j * step;
+            const uint32_t c0 = p.col[k], c1 = p.col[k + step];
+            const uint32_t c2 = p.col[k + 2 * step], c3 = p.col[k + 3 * step];
+            const T a0 = p.val[k], a1 = p.val[k + step];
+            const T a2 = p.val[k + 2 * step], a3 = p.val[k + 3 * step];
+            const V x0 = ld<V>(xq + (int64_t)c0 * p.ldx);
+            const V x1 = ld<V>(xq + (int64_t)c1 * p.ldx);
+            const V x2 = ld<V>(xq + (int64_t)c2 * p.ldx);
+            const V x3 = ld<V>(xq + (int64_t)c3 * p.ldx);
+            acc0 += a0 * x0;
+            acc1 += a1 * x1;
+            acc0 += a2 * x2;
+            acc1 += a3 * x3;
+        }
+        for (; j < len; ++j) {
+            const uint32_t k = base + j * step;
+            const uint32_t cj = p.col[k];
+            const T aj = p.val[k];
+            acc0 += aj * ld<V>(xq + (int64_t)cj * p.ldx);
+        }
+        const V acc = acc0 + acc1;
+        T *yr = y + row * p.ldy + q * VEC;
+        if constexpr (MODE == 0) {
+            st<V>(yr, acc);
+        } else {
+            const V xi = ld<V>(xq + row * p.ldx);
+            V t = p.a * acc + p.b * xi;
+            if constexpr (MODE == 1) {
+                st<V>(yr, t);
+            } else if constexpr (MODE == 2) {
+                T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
+                V vi = ld<V>(vr);
+                t -= vi;
+                st<V>(yr, t);
+                st<V>(vr, p.cv * vi + p.cx * xi + p.ct * t);
+            } else {
+                const V zi = ld<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+                t -= zi;
+                st<V>(yr, t);
+                T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
+                V vi = ld<V>(vr);
+                st<V>(vr, vi + p.ct * t);
+            }
+        }
+    }
+}
+
+template <typename T, int VEC, int G>
+fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStream_t s) {
+    KArgs<T> p;
+    p.ptr = M.ptr;
+    p.col = M.col;
+    p.val = val;
+    p.perm = M.perm;
+    p.nslots = M.nslots;
+    p.cshift = M.cshift;
+    constexpr int RPB = 256 / G;
+    const SpmmvTune &tn = spmmv_tune();
+    int iters = tn.iters;
+    if (iters <= 0) {
+        // about 8192 blocks or more per bundle for a large matrix
+        int64_t want = M.nslots / ((int64_t)RPB * 8192);
+        iters = (int)std::max<int64_t>(1, std::min<int64_t>(64, want));
+    }
+    p.iters = iters;
+    p.nblk = (M.nslots + (int64_t)RPB * iters - 1) / ((int64_t)RPB * iters);
+    p.xcd = tn.xcd;
+    p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;
+    p.y = (T *)c.y; p.ldy = c.ldy; p.by = c.by;
+    p.z = (const T *)c.z; p.ldz = c.ldz; p.bz = c.bz;
+    p.v = (T *)c.v; p.ldv = c.ldv; p.bv = c.bv;
+    p.a = (T)c.a; p.b = (T)c.b; p.cv = (T)c.cv; p.cx = (T)c.cx; p.ct = (T)c.ct;
+    int64_t gx = p.xcd ? ((p.nblk + 7) / 8) * 8 : p.nblk;
+    if (gx > 0x7fffffff) return fail(FD_ERR_UNSUPPORTED, "SpMMV: grid too large");
+    dim3 grid((unsigned)gx, (unsigned)c.nbundles), block(256);
+    const bool perm = M.perm != nullptr;
+#define FD_L(MODE, PERM) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM>), grid, block, 0, s, p)
+    switch (c.mode * 2 + (perm ? 1 : 0)) {
+        case 0: FD_L(0, false); break;
+        case 1: FD_L(0, true); break;
+        case 2: FD_L(1, false); break;
+        case 3: FD_L(1, true); break;
+        case 4: FD_L(2, false); break;
+        case 5: FD_L(2, true); break;
+        case 6: FD_L(3, false); break;
+        case 7: FD_L(3, true); break;
+        default: return fail(FD_ERR_INVALID, "SpMMV: bad mode");
+    }
+#undef FD_L
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+}  // namespace
+
+SpmmvTune &spmmv_tune() {
+    static SpmmvTune t{0, 1};
+    return t;
+}
+
+fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s) {
+    if (dt == FD_F64) {
+        switch (c.nb) {
+            case 1: return launch_t<double, 1, 1>(M, M.val64, c, s);
+            case 2: return launch_t<double, 2, 1>(M, M.val64, c, s);
+            case 4: return launch_t<double, 2, 2>(M, M.val64, c, s);
+            case 8: return launch_t<double, 2, 4>(M, M.val64, c, s);
+            case 16: return launch_t<double, 2, 8>(M, M.val64, c, s);
+            case 32: return launch_t<double, 2, 16>(M, M.val64, c, s);
+            case 64: return launch_t<double, 2, 32>(M, M.val64, c, s);
+        }
+    } else {
+        switch (c.nb) {
+            case 1: return launch_t<float, 1, 1>(M, M.val32, c, s);
+            case 2: return launch_t<float, 2, 1>(M, M.val32, c, s);
+            case 4: return launch_t<float, 4, 1>(M, M.val32, c, s);
+            case 8: return launch_t<float, 4, 2>(M, M.val32, c, s);
+            case 16: return launch_t<float, 4, 4>(M, M.val32, c, s);
+            case 32: return launch_t<float, 4, 8>(M, M.val32, c, s);
+            case 64: return launch_t<float, 4, 16>(M, M.val32, c, s);
+        }
+    }
+    return fail(FD_ERR_INVALID, "nb must be one of 1, 2, 4, 8, 16, 32, 64");
+}
+
+}  // namespace fd

@@ -1,0 +1,138 @@
+"""libfd without a GPU: the shared library loads and exports every entry point
+that include/fd.h declares; the host-side builders match the oracle bit for
+bit; coefficients agree; argument errors follow the documented conventions."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2209_01974_amd as fd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(fd.LIB_PATH):
+        from paper_2209_01974_amd import build
+        build.build()
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "fd.h")).read()
+    declared = set(re.findall(r"^\s*(?:fd_status|void|const char \*)\s*(fd_[a-z_]+)\s*\(", hdr, re.M))
+    assert {"fd_build_matrix", "fd_spmmv", "fd_cheb_filter", "fd_orthog", "fd_rayleigh_ritz",
+            "fd_solve"} <= declared
+    L = fd.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _same_csr(m, A):
+    rowptr, col, val = m.export_csr()
+    assert np.array_equal(rowptr, A.rowptr)
+    assert np.array_equal(col, A.col)
+    assert np.array_equal(val.view(np.uint64), A.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("L,nu,nd,U,per", [(6, 3, 3, 4.0, True), (8, 4, 4, 4.0, True), (7, 2, 3, 2.5, True),
+                                           (8, 4, 4, 4.0, False), (5, 0, 2, 1.0, True), (6, 3, 3, 0.0, True)])
+def test_hubbard_bit_exact(L, nu, nd, U, per):
+    m = fd.build_matrix("hubbard", host_only=True, L=L, n_up=nu, n_dn=nd, t=1.0, U=U, periodic=per)
+    _same_csr(m, O.hubbard(L, nu, nd, 1.0, U, per))
+
+
+def test_hubbard_zero_hopping_stores_diagonal_only():
+    m = fd.build_matrix("hubbard", host_only=True, L=6, n_up=3, n_dn=3, t=0.0, U=2.0)
+    _same_csr(m, O.hubbard(6, 3, 3, 0.0, 2.0))
+    assert m.nnz == m.D
+
+
+@pytest.mark.parametrize("L,W,seed", [(3, 16.5, 1), (5, 16.5, 1), (12, 3.0, 7)])
+def test_anderson_bit_exact(L, W, seed):
+    m = fd.build_matrix("anderson", host_only=True, L=L, t=1.0, W=W, seed=seed)
+    _same_csr(m, O.anderson(L, 1.0, W, seed))
+
+
+@pytest.mark.slow
+def test_hubbard_config_sizes_and_gershgorin():
+    m = fd.build_matrix("hubbard", host_only=True, L=8, n_up=4, n_dn=4, t=1.0, U=4.0)
+    assert (m.D, m.nnz) == (4900, 49700)
+    assert (m.lam_lo, m.lam_hi) == O.gershgorin(O.hubbard(8, 4, 4, 1.0, 4.0))
+    m = fd.build_matrix("anderson", host_only=True, L=40, t=1.0, W=16.5, seed=1)
+    A = O.anderson(40, 1.0, 16.5, 1)
+    _same_csr(m, A)
+    assert (m.lam_lo, m.lam_hi) == O.gershgorin(A)
+
+
+@pytest.mark.parametrize("C_,sigma", [(1, 1), (4, 1), (8, 32), (32, 128), (64, 1 << 20)])
+def test_sell_bit_exact(C_, sigma):
+    m = fd.build_matrix("hubbard", fmt="sell", C_=C_, sigma=sigma, host_only=True, L=7, n_up=3, n_dn=2,
+                        t=1.0, U=3.0)
+    S = O.sell(O.hubbard(7, 3, 2, 1.0, 3.0), C_, sigma)
+    perm, cptr, clen, col, val = m.export_sell()
+    assert np.array_equal(perm, S.perm)
+    assert np.array_equal(cptr, S.chunk_ptr)
+    assert np.array_equal(clen, S.chunk_len)
+    assert np.array_equal(col, S.col)
+    assert np.array_equal(val.view(np.uint64), S.val.view(np.uint64))
+
+
+def test_sell_round_trip_to_csr():
+    A = O.anderson(6, 1.0, 5.0, 2)
+    m = fd.build_matrix("anderson", fmt="sell", C_=16, sigma=64, host_only=True, L=6, t=1.0, W=5.0, seed=2)
+    perm, cptr, clen, col, val = m.export_sell()
+    C_ = 16
+    for s in range(A.D):
+        o = perm[s]
+        c, r = divmod(s, C_)
+        n = A.rowptr[o + 1] - A.rowptr[o]
+        got_c = [col[cptr[c] + j * C_ + r] for j in range(n)]
+        got_v = [val[cptr[c] + j * C_ + r] for j in range(n)]
+        assert got_c == list(A.col[A.rowptr[o]:A.rowptr[o + 1]])
+        assert got_v == list(A.val[A.rowptr[o]:A.rowptr[o + 1]])
+
+
+def test_user_csr_and_diagonal_round_trip():
+    A = O.hubbard(6, 2, 3, 1.0, 1.5)
+    m = fd.build_matrix("csr", host_only=True, csr=(A.rowptr, A.col, A.val))
+    _same_csr(m, A)
+    d = np.linspace(-1, 1, 17)
+    m = fd.build_matrix("diagonal", host_only=True, diag=d)
+    _same_csr(m, O.diagonal(d))
+
+
+def test_user_csr_rejects_bad_input():
+    A = O.hubbard(6, 2, 3, 1.0, 1.5)
+    col = A.col.copy()
+    col[1], col[2] = col[2], col[1]
+    with pytest.raises(fd.FDError) as e:
+        fd.build_matrix("csr", host_only=True, csr=(A.rowptr, col, A.val))
+    assert e.value.status == fd.FD_ERR_INVALID
+
+
+@pytest.mark.parametrize("kind,a,b,n", [(0, -0.3, 0.2, 50), (0, -1.0, 1.0, 10), (1, 0.1, 0.0, 800),
+                                        (0, 0.01, 0.02, 800)])
+def test_coefficients_match_oracle(kind, a, b, n):
+    np.testing.assert_allclose(fd.cheb_coeffs(kind, a, b, n), O.cheb_coeffs(kind, a, b, n), rtol=0, atol=2e-15)
+
+
+def test_argument_errors():
+    with pytest.raises(fd.FDError) as e:
+        fd.build_matrix("hubbard", host_only=True, L=2, n_up=1, n_dn=1)
+    assert e.value.status == fd.FD_ERR_INVALID
+    with pytest.raises(fd.FDError) as e:
+        fd.build_matrix("anderson", fmt="sell", C_=3, sigma=1, host_only=True, L=4)
+    assert e.value.status == fd.FD_ERR_INVALID
+    with pytest.raises(fd.FDError):
+        fd.cheb_coeffs(0, 0.5, 0.2, 10)
+    # device entry points refuse a host-only matrix before touching the GPU
+    m = fd.build_matrix("anderson", host_only=True, L=4, W=1.0)
+    st = fd.lib().fd_spmmv(m.handle, fd.FD_F64, 8, C.c_void_p(256), 8, C.c_void_p(1 << 20), 8, None)
+    assert st == fd.FD_ERR_INVALID
+    assert b"host-only" in fd.lib().fd_last_error()
+    st = fd.lib().fd_orthog(10, 0, None, 1, 0, 0, None, None)
+    assert st == fd.FD_ERR_INVALID

@@ -1,0 +1,244 @@
+"""GPU parity of libfd's kernels against the CPU oracle (through the C ABI).
+
+Tolerances: FP64 results within 1e-12 relative (Frobenius) of the oracle;
+bit-exact where every partial sum is an exact integer; FP32 results within a
+bound derived from the FP32 unit roundoff times the accumulation length.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from fd_inputs import int_block, start_block
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2209_01974_amd as fd  # noqa: E402
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+MATS = {
+    "hub8": (dict(model="hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0), lambda: O.hubbard(8, 4, 4, 1.0, 4.0)),
+    "hub7": (dict(model="hubbard", L=7, n_up=3, n_dn=2, t=1.0, U=2.5), lambda: O.hubbard(7, 3, 2, 1.0, 2.5)),
+    "and13": (dict(model="anderson", L=13, t=1.0, W=16.5, seed=1), lambda: O.anderson(13, 1.0, 16.5, 1)),
+}
+FMTS = [("csr", 1, 1), ("sell", 32, 256), ("sell", 64, 1), ("sell", 8, 1 << 20)]
+
+
+def build(name, fmt, C_, sigma):
+    kw, ora = MATS[name]
+    return fd.build_matrix(fmt=fmt, C_=C_, sigma=sigma, **kw), ora()
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("fmt,C_,sigma", FMTS)
+@pytest.mark.parametrize("nb", [1, 2, 4, 8, 16, 32, 64])
+def test_spmmv_fp64_parity(name, fmt, C_, sigma, nb):
+    m, A = build(name, fmt, C_, sigma)
+    X = start_block(A.D, nb, 11)
+    Y = torch.empty((A.D, nb), dtype=torch.float64, device="cuda")
+    fd.spmmv(m, dev(X), Y)
+    torch.cuda.synchronize()
+    assert relerr(Y.cpu().numpy(), O.spmmv(A, X)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["hub8", "and13"])
+@pytest.mark.parametrize("fmt,C_,sigma", FMTS[:2])
+@pytest.mark.parametrize("nb", [1, 4, 8, 64])
+def test_spmmv_integer_bit_exact(name, fmt, C_, sigma, nb):
+    kw, _ = MATS[name]
+    if name == "and13":
+        kw = dict(kw, W=0.0)  # integer values
+        A = O.anderson(13, 1.0, 0.0, 1)
+    else:
+        A = MATS[name][1]()
+    m = fd.build_matrix(fmt=fmt, C_=C_, sigma=sigma, **kw)
+    for dt, bound in ((torch.float64, 1 << 10), (torch.float32, 1 << 8)):
+        X = int_block(A.D, nb, 3, bound)
+        Y = torch.empty((A.D, nb), dtype=dt, device="cuda")
+        fd.spmmv(m, dev(X, dt), Y)
+        torch.cuda.synchronize()
+        assert np.array_equal(Y.cpu().double().numpy(), O.spmmv(A, X))
+
+
+@pytest.mark.parametrize("nb", [1, 8, 64])
+def test_spmmv_fp32_error_bound(nb):
+    m, A = build("hub8", "csr", 1, 1)
+    X = start_block(A.D, nb, 5)
+    X32 = X.astype(np.float32)
+    Y = torch.empty((A.D, nb), dtype=torch.float32, device="cuda")
+    fd.spmmv(m, dev(X32), Y)
+    torch.cuda.synchronize()
+    # |fl(sum) - sum| <= len * u * sum |a x| with u = 2^-24 and len <= 17
+    Aabs = O.CSR(A.D, A.rowptr, A.col, np.abs(A.val))
+    bound = 17 * 2.0 ** -24 * O.spmmv(Aabs, np.abs(X32.astype(np.float64)))
+    ref = O.spmmv(A, X32.astype(np.float64))
+    assert np.all(np.abs(Y.cpu().double().numpy() - ref) <= bound + 1e-30)
+
+
+def test_spmmv_ld_and_errors():
+    m, A = build("hub7", "csr", 1, 1)
+    X = start_block(A.D, 16, 1)
+    Xd = torch.zeros((A.D, 24), dtype=torch.float64, device="cuda")
+    Xd[:, 4:12] = dev(X[:, :8])
+    Y = torch.full((A.D, 10), 7.0, dtype=torch.float64, device="cuda")
+    fd.spmmv(m, Xd[:, 4:12], Y[:, :8])
+    torch.cuda.synchronize()
+    assert relerr(Y[:, :8].cpu().numpy(), O.spmmv(A, X[:, :8])) <= 1e-12
+    assert torch.all(Y[:, 8:] == 7.0)
+    with pytest.raises(fd.FDError):
+        fd.spmmv(m, Xd[:, :3], torch.empty((A.D, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(fd.FDError):  # misaligned (odd element offset, FP64 needs 16 bytes)
+        fd.spmmv(m, Xd[:, 1:9], Y[:, :8])
+
+
+# ------------------------------------------------------------------ filter --
+@pytest.mark.parametrize("name", ["hub8", "and13"])
+@pytest.mark.parametrize("fmt,C_,sigma", FMTS[:2])
+@pytest.mark.parametrize("nb,nbund,concurrent", [(1, 2, False), (8, 3, True), (16, 2, False), (64, 1, False)])
+def test_filter_fp64_parity(name, fmt, C_, sigma, nb, nbund, concurrent):
+    m, A = build(name, fmt, C_, sigma)
+    lo, hi = O.gershgorin(A)
+    alpha, beta = O.scaling(lo, hi)
+    mu = O.cheb_coeffs(0, alpha * -0.5 + beta, alpha * 0.5 + beta, 37)
+    ns = nb * nbund
+    V = start_block(A.D, ns, 2)
+    ldw = ns if concurrent else nb
+    Vd = dev(V)
+    W1 = torch.empty((A.D, ldw), dtype=torch.float64, device="cuda")
+    W2 = torch.empty_like(W1)
+    fd.cheb_filter(m, Vd, mu, alpha, beta, W1, W2, nb)
+    torch.cuda.synchronize()
+    assert relerr(Vd.cpu().numpy(), O.cheb_filter(A, V, mu, alpha, beta)) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 50])
+def test_filter_chebyshev_identity(n):
+    theta = np.linspace(0.01, 3.1, 999)
+    m = fd.build_matrix("diagonal", diag=np.cos(theta))
+    V = start_block(999, 8, 4)
+    mu = np.zeros(n + 1)
+    mu[n] = 1.0
+    Vd = dev(V)
+    W1 = torch.empty_like(Vd)
+    W2 = torch.empty_like(Vd)
+    fd.cheb_filter(m, Vd, mu, 1.0, 0.0, W1, W2, 8)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(Vd.cpu().numpy(), np.cos(n * theta)[:, None] * V, atol=1e-12)
+
+
+def test_filter_fp32_error():
+    m, A = build("hub8", "csr", 1, 1)
+    lo, hi = O.gershgorin(A)
+    alpha, beta = O.scaling(lo, hi)
+    mu = O.cheb_coeffs(0, alpha * -0.5 + beta, alpha * 0.5 + beta, 100)
+    V = start_block(A.D, 16, 6).astype(np.float32)
+    Vd = dev(V)
+    W1 = torch.empty_like(Vd)
+    W2 = torch.empty_like(Vd)
+    fd.cheb_filter(m, Vd, mu, alpha, beta, W1, W2, 16)
+    torch.cuda.synchronize()
+    ref = O.cheb_filter(A, V.astype(np.float64), mu, alpha, beta)
+    # an FP32 recurrence of degree n loses about n * 2^-24 relative
+    assert relerr(Vd.cpu().double().numpy(), ref) <= 100 * 2.0 ** -24 * 10
+
+
+# -------------------------------------------------------------- dense FP64 --
+@pytest.mark.parametrize("D,m_,n", [(10007, 64, 64), (5001, 17, 33), (4096, 256, 256), (333, 1, 5),
+                                    (70000, 128, 100), (2000, 512, 512)])
+def test_gram_parity_and_reproducible(D, m_, n):
+    X = start_block(D, m_, 1)
+    Y = start_block(D, n, 2)
+    G = torch.empty((m_, n), dtype=torch.float64, device="cuda")
+    fd.gram(dev(X), dev(Y), G)
+    g1 = G.cpu().numpy()
+    ref = X.T @ Y
+    assert np.abs(g1 - ref).max() <= 1e-13 * np.sqrt(D) * max(1.0, np.abs(ref).max()) / 10
+    fd.gram(dev(X), dev(Y), G)
+    assert np.array_equal(G.cpu().numpy(), g1)
+
+
+@pytest.mark.parametrize("D,m_,n", [(10007, 64, 64), (5001, 17, 9), (4096, 256, 256), (999, 300, 300),
+                                    (3000, 512, 512), (50, 20, 1)])
+def test_rotate_parity(D, m_, n):
+    X = start_block(D, m_, 3)
+    Q = start_block(m_, n, 4)
+    Xd = dev(X)
+    fd.rotate(Xd, dev(Q))
+    out = Xd.cpu().numpy()
+    ref = X @ Q
+    assert np.abs(out[:, :n] - ref).max() <= 1e-13 * np.sqrt(m_) * np.abs(ref).max()
+    assert np.array_equal(out[:, n:], X[:, n:])
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 127, 128, 200, 256, 512])
+def test_syev_parity(n):
+    rng = np.random.default_rng(n)
+    S = rng.standard_normal((n, n))
+    S = S + S.T
+    if n >= 64:  # exact multiplicities, as in Ritz matrices of symmetric models
+        lam, Q = np.linalg.eigh(S)
+        lam[: n // 4] = 1.5
+        S = (Q * lam) @ Q.T
+        S = 0.5 * (S + S.T)
+    Sd = dev(S)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    U = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    fd.syev(Sd, w, U)
+    wn, Un = w.cpu().numpy(), U.cpu().numpy()
+    ref = np.linalg.eigvalsh(S)
+    nrm = np.linalg.norm(S, 2)
+    assert np.abs(wn - ref).max() <= 1e-13 * nrm * max(1, np.sqrt(n) / 4)
+    assert np.abs(Un.T @ Un - np.eye(n)).max() <= 1e-13 * max(1, n / 64)
+    assert np.abs(S @ Un - Un * wn).max() <= 1e-12 * nrm * max(1, n / 64)
+
+
+@pytest.mark.parametrize("method", [fd.FD_ORTHO_SVQB2, fd.FD_ORTHO_CHOLQR2])
+@pytest.mark.parametrize("D,ns", [(5000, 64), (20011, 128), (3000, 16), (40000, 256)])
+def test_orthog(method, D, ns):
+    V = start_block(D, ns, 9) @ np.diag(np.logspace(0, -5, ns))
+    Vd = dev(V)
+    r = fd.orthog(Vd, method)
+    Q = Vd.cpu().numpy()
+    assert r == ns
+    assert np.abs(Q.T @ Q - np.eye(ns)).max() <= 1e-13
+    assert np.linalg.norm(V - Q @ (Q.T @ V)) <= 1e-11 * np.linalg.norm(V)
+
+
+def test_orthog_rank_deficient_refill():
+    D, ns = 4000, 32
+    V = start_block(D, ns, 1)
+    V[:, 20:] = V[:, :12]  # 12 duplicated columns
+    Vd = dev(V)
+    r = fd.orthog(Vd, fd.FD_ORTHO_SVQB2, seed=5)
+    Q = Vd.cpu().numpy()
+    assert r == 20
+    assert np.abs(Q.T @ Q - np.eye(ns)).max() <= 1e-13
+    # the kept span contains the original columns
+    assert np.linalg.norm(V - Q @ (Q.T @ V)) <= 1e-11 * np.linalg.norm(V)
+
+
+@pytest.mark.parametrize("name,nb,ns", [("hub8", 16, 64), ("and13", 8, 40), ("hub7", 4, 12)])
+def test_rayleigh_ritz_parity(name, nb, ns):
+    m, A = build(name, "csr", 1, 1)
+    V, _ = O.svqb2(start_block(A.D, ns, 8))
+    th_o, Vr_o, Wr_o, rho_o = O.rayleigh_ritz(A, V)
+    Vd = dev(V)
+    Wd = torch.empty_like(Vd)
+    th, rho = fd.rayleigh_ritz(m, Vd, Wd, nb)
+    normH = max(abs(m.lam_lo), abs(m.lam_hi))
+    assert np.abs(th - th_o).max() <= 1e-12 * normH
+    assert np.abs(rho - rho_o).max() <= 1e-11 * normH
+    Vn = Vd.cpu().numpy()
+    fresh = np.linalg.norm(O.spmmv(A, Vn) - Vn * th, axis=0)
+    assert np.abs(fresh - rho).max() <= 1e-11 * normH
