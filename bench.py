@@ -1,0 +1,295 @@
+#!/usr/bin/env python3
+"""Benchmark of the filter-diagonalization (FD) hot path on one MI355X.
+
+A step is one FD outer iteration on the 3D Anderson lattice L=200 (D = 8.0M,
+7-point hopping t=1, periodic, disorder W=16.5 drawn with seed 1), with
+N_s = 512 search vectors in 8 bundles of nb = 64, target "nearest E = 0":
+  coefficients (Jackson-damped delta at E=0, degree 500, host)
+  -> Chebyshev filter (500 fused SpMMV steps per bundle)
+  -> SVQB2 orthogonalization (MFMA Gram + GPU Jacobi + MFMA rotation)
+  -> Rayleigh-Ritz (one more SpMMV per bundle, Gram, Jacobi, rotations,
+     residual norms) -> selection of the pairs nearest E = 0 (host).
+Inputs (matrix and the N(0,1) start block) are resident in HBM before the
+timed region.  `value` is the whole step's algorithmic bytes (Eq. traffic
+with kappa = 5 for the fused steps, plus the dense passes) divided by the
+step's wall time.
+
+Extra fields: a SpMMV / filter bandwidth sweep over nb and precision, the FD
+eigenpairs/s comparison FP64 vs mixed precision (Hubbard ring L=8, and L=14
+with --hubbard14), the roofline of the dominant kernel (the fused Chebyshev
+step) and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpMMV GB/s (% of HBM peak); FD eigenpairs/s at residual 1e-9, mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------- byte counts ----
+def spmmv_bytes(nnz, D, nb, sv):
+    """Eq. traffic at N_p = 1: matrix (value + uint32 index), row pointers,
+    X read once, Y written once."""
+    return nnz * (sv + 4) + 4 * (D + 1) + 2 * D * nb * sv
+
+
+def fused_bytes(nnz, D, nb, sv, kappa=5):
+    """Fused Chebyshev step: W1 read once, W2 and V read and written."""
+    return nnz * (sv + 4) + 4 * (D + 1) + kappa * D * nb * sv
+
+
+def filter_bytes(nnz, D, nb, sv, degree):
+    """One filter application on one bundle: step 1 (SpMMV + write), step 2
+    (kappa = 4: gather, read V, write W1 and V), steps 3..n (kappa = 5)."""
+    return (fused_bytes(nnz, D, nb, sv, 2) + fused_bytes(nnz, D, nb, sv, 4)
+            + (degree - 2) * fused_bytes(nnz, D, nb, sv, 5))
+
+
+def dense_bytes(D, ns):
+    """SVQB2 (2 Gram reads + 2 in-place rotations) and Rayleigh-Ritz (Gram of
+    V and W, two rotations, residual norms), FP64."""
+    blk = D * ns * 8
+    return 2 * blk + 2 * 2 * blk + 2 * blk + 2 * 2 * blk + 2 * blk
+
+
+# ------------------------------------------------------------- helpers ----
+def traffic_from_profile(kernel_src: str):
+    """HBM bytes per launch of the fused step from the committed rocprofv3
+    PMC summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "fused_step_anderson200_nb64_f64_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if prof.get("kernel_source_sha256") != h:
+        return None
+    return prof.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=200)
+    ap.add_argument("--nb", type=int, default=64)
+    ap.add_argument("--ns", type=int, default=512)
+    ap.add_argument("--degree", type=int, default=500)
+    ap.add_argument("--fmt", choices=["csr", "sell"], default="csr")
+    ap.add_argument("--C", type=int, default=32)
+    ap.add_argument("--sigma", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the nb / precision sweep")
+    ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
+    ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
+    ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the filter would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2209_01974_amd as fd
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------- workload ----
+    L, nb, ns, degree = args.L, args.nb, args.ns, args.degree
+    t0 = time.time()
+    m = fd.build_matrix("anderson", fmt=args.fmt, C_=args.C, sigma=args.sigma, L=L, t=1.0, W=16.5, seed=1)
+    D, nnz = m.D, m.nnz
+    log("built Anderson L=%d D=%d nnz=%d (%s) in %.1fs" % (L, D, nnz, args.fmt, time.time() - t0))
+    lam_lo, lam_hi = m.lam_lo, m.lam_hi
+    alpha, beta = 2.0 / (lam_hi - lam_lo), -(lam_hi + lam_lo) / (lam_hi - lam_lo)
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    V = torch.randn((D, ns), generator=g, dtype=torch.float64, device=dev)
+    W = torch.empty_like(V)
+    W1 = torch.empty((D, nb), dtype=torch.float64, device=dev)
+    W2 = torch.empty_like(W1)
+    nbund = ns // nb
+    torch.cuda.synchronize()
+
+    def step(record=None):
+        mu = fd.cheb_coeffs(1, alpha * 0.0 + beta, 0.0, degree)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fd.cheb_filter(m, V, mu, alpha, beta, W1, W2, nb, stream=stream)
+        e1.record(stream)
+        fd.orthog(V, fd.FD_ORTHO_SVQB2, seed=7, stream=stream)
+        th, rho = fd.rayleigh_ritz(m, V, W, nb, stream=stream)
+        order = np.argsort(np.abs(th), kind="stable")[:128]
+        torch.cuda.synchronize()
+        if record is not None:
+            record.append(e0.elapsed_time(e1) * 1e-3)
+        return th[order], rho[order]
+
+    fd.orthog(V, fd.FD_ORTHO_SVQB2, seed=7, stream=stream)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        step()
+        log("warmup step %d done" % i)
+    filt_times = []
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for i in range(args.steps):
+        th, rho = step(filt_times)
+        log("step %d: filter %.3fs, min |theta| %.3e, max rho(128 nearest 0) %.3e"
+            % (i, filt_times[-1], np.abs(th).min(), rho.max()))
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    t_step = (te - ts) / args.steps
+    fb = filter_bytes(nnz, D, nb, 8, degree) * nbund
+    step_bytes = fb + nbund * spmmv_bytes(nnz, D, nb, 8) + dense_bytes(D, ns)
+    value = step_bytes / t_step / 1e9
+
+    # roofline of the dominant kernel: the fused Chebyshev step (HIP events
+    # around each filter call on the launch stream; every launch in it is the
+    # SpMMV/Chebyshev kernel, 2 of each `degree` launches are the lighter
+    # first two steps)
+    t_filter = sum(filt_times) / len(filt_times)
+    launches = degree * nbund
+    avg_launch = t_filter / launches
+    achieved = fb / t_filter / 1e9
+    per_launch = fused_bytes(nnz, D, nb, 8)
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2209_01974_amd", "csrc", "fd_spmmv.hip"))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_spmmv<double,2,32,MODE=3> (fused Chebyshev step, FP64, nb=64)",
+                "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": round(avg_launch * 1e6, 2)}
+    del W
+    torch.cuda.empty_cache()
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "anderson3d_L%d_W16.5_seed1" % L, "D": D, "nnz": nnz,
+                      "n_search": ns, "nb": nb, "degree": degree, "format": args.fmt,
+                      "target": "128 pairs nearest E=0 (damped delta)", "parallelism": "single GPU"},
+           "roofline": roofline,
+           "hbm_frac_of_step": round(value / HBM_PEAK_GBS, 4)}
+
+    # ---------------------------------------------------------- sweep ----
+    if not args.no_sweep:
+        sweep = []
+        # device copy (STREAM-like): torch's elementwise copy on 4 GB
+        a = torch.empty((D, 64), dtype=torch.float64, device=dev).normal_()
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["stream_copy_GBs"] = round(2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del a, b
+        for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
+            for w in (1, 4, 8, 16, 32, 64):
+                X = torch.empty((D, w), dtype=dt, device=dev).normal_()
+                Y = torch.empty_like(X)
+                for _ in range(3):
+                    fd.spmmv(m, X, Y, stream=stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = 20
+                e0.record(stream)
+                for _ in range(reps):
+                    fd.spmmv(m, X, Y, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts_ = e0.elapsed_time(e1) * 1e-3 / reps
+                gbs = spmmv_bytes(nnz, D, w, sv) / ts_ / 1e9
+                # filter of degree 50 on one bundle of width w
+                Z1, Z2 = torch.empty_like(X), torch.empty_like(X)
+                mu = fd.cheb_coeffs(1, beta, 0.0, 50)
+                fd.cheb_filter(m, X, mu, alpha, beta, Z1, Z2, w, stream=stream)
+                e0.record(stream)
+                fd.cheb_filter(m, X, mu, alpha, beta, Z1, Z2, w, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                tf = e0.elapsed_time(e1) * 1e-3
+                fgbs = filter_bytes(nnz, D, w, sv, 50) / tf / 1e9
+                sweep.append({"dtype": "f64" if sv == 8 else "f32", "nb": w,
+                              "spmmv_us": round(ts_ * 1e6, 1), "spmmv_GBs": round(gbs, 1),
+                              "spmmv_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "filter_step_us": round(tf / 50 * 1e6, 1), "filter_GBs": round(fgbs, 1),
+                              "filter_frac": round(fgbs / HBM_PEAK_GBS, 4)})
+                log("sweep %s nb=%d: SpMMV %.0f GB/s, filter %.0f GB/s" % (sweep[-1]["dtype"], w, gbs, fgbs))
+                del X, Y, Z1, Z2
+        out["sweep"] = sweep
+
+    # ---------------------------------------------------- FD eigenpairs/s ----
+    if not args.no_fd:
+        from fd_inputs import start_block
+        fdres = {}
+        runs = [("hubbard8", dict(L=8, n_up=4, n_dn=4, U=4.0), -0.5, 0.5, 16, 128, 16, 100)]
+        if args.hubbard14:
+            runs.append(("hubbard14", dict(L=14, n_up=7, n_dn=7, U=8.0), -1.0, 1.0, 64, 256, 32, 800))
+        for name, kw, lo, hi, nt, nsr, nbr, deg in runs:
+            mh = fd.build_matrix("hubbard", t=1.0, **kw)
+            V0 = start_block(mh.D, nsr, 0) if mh.D * nsr <= 50_000_000 else None
+            res = {}
+            for prec, label in ((0, "fp64"), (1, "mixed")):
+                r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=200, tol=1e-9, precision=prec, V0=V0,
+                             seed=0, want_vectors=False)
+                st = r.stats
+                res[label] = {"converged": r.status == fd.FD_OK, "eigenpairs_per_s": round(nt / st["t_total"], 3),
+                              "t_total_s": round(st["t_total"], 3), "iters": st["iters"],
+                              "iters_fp32": st["iters_fp32"], "spmmv": st["spmmv_count"],
+                              "t_filter_s": round(st["t_filter"], 3), "t_orthog_s": round(st["t_orthog"], 3),
+                              "t_rr_s": round(st["t_rr"], 3), "max_resid_rel": st["max_resid"] / st["norm_H"]}
+                res[label + "_evals"] = r.evals
+                normH = st["norm_H"]
+                log("FD %s %s: %s" % (name, label, res[label]))
+            d = np.abs(res.pop("mixed_evals") - res.pop("fp64_evals")) / normH
+            res["mixed_vs_fp64_max_rel_eval_diff"] = float(np.max(d))
+            res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
+            fdres[name] = res
+        out["fd"] = fdres
+
+    # ------------------------------------------------------- CPU oracle ----
+    if not args.no_cpu:
+        import oracle as O
+        t0 = time.time()
+        A = O.anderson(L, 1.0, 16.5, 1)
+        log("oracle matrix built in %.1fs" % (time.time() - t0))
+        Vc = np.random.default_rng(0).standard_normal((D, nb))
+        mu = O.cheb_coeffs(1, beta, 0.0, args.cpu_degree)
+        t0 = time.perf_counter()
+        O.cheb_filter(A, Vc, mu, alpha, beta)
+        tc = time.perf_counter() - t0
+        cb = filter_bytes(nnz, D, nb, 8, args.cpu_degree)
+        out["cpu_baseline"] = {"value": round(cb / tc / 1e9, 2), "unit": "GB/s", "cores": O.num_threads(),
+                               "kind": "oracle",
+                               "sample": "unfused FP64 filter, degree %d, one bundle of nb=%d on Anderson L=%d "
+                                         "(%.1f s); same algorithmic byte count as the GPU filter"
+                                         % (args.cpu_degree, nb, L, tc)}
+        log("cpu baseline %.2f GB/s in %.1fs" % (cb / tc / 1e9, tc))
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,6 +46,7 @@ def lib():
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.orc_num_threads.restype = C.c_int
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_splitmix64.argtypes = [C.POINTER(C.c_uint64)]
         L.orc_uniform_fill.argtypes = [C.c_uint64, C.c_int64, f64p]
@@ -97,6 +98,11 @@ class CSR:
         rows = np.repeat(np.arange(self.D), np.diff(self.rowptr))
         A[rows, self.col.astype(np.int64)] = self.val
         return A
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().orc_num_threads())
 
 
 def splitmix64_first(seed: int, count: int) -> list[int]:

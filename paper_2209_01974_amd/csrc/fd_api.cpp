@@ -513,7 +513,9 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
             if (!std::isfinite(th[j]) || !std::isfinite(rho[j]))
                 return fail(FD_ERR_BREAKDOWN, "fd_solve: non-finite Ritz data");
         sel = select_targets(th, P->tau_lo, P->tau_hi, nt);
-        double mx = 0.0;
+        // largest residual of the N_t selected pairs (infinite while fewer
+        // than N_t Ritz values lie in the window)
+        double mx = (int)sel.size() == nt ? 0.0 : INFINITY;
         for (int j : sel) mx = std::max(mx, rho[j]);
         st.n_conv = 0;
         for (int j = 0; j < ns; j++)
@@ -521,8 +523,11 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         converged = (int)sel.size() == nt && mx <= tol;
         if (converged || it >= P->max_iter) break;
         // mixed precision: leave FP32 once the residual is near what an FP32
-        // filter can deliver, or once it stops improving
-        if (fp32 && (mx <= 1e-5 * normH || mx > 0.5 * prev_max)) fp32 = false;
+        // filter can deliver (1e-5 ||H||), or once it stalls (under 10 %
+        // progress per iteration) below 1e-3 ||H||
+        if (fp32 && std::isfinite(mx) &&
+            (mx <= 1e-5 * normH || (mx > 0.9 * prev_max && mx < 1e-3 * normH)))
+            fp32 = false;
         prev_max = mx;
         double tf = now();
         if (fp32) {

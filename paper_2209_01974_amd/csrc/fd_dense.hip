@@ -21,7 +21,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // MFMA f64 16x16x4 operand layout (lane l = i + 16 k):
 //   A[i][k] (16 x 4) and B[k][j] (4 x 16) hold one double per lane;
-//   the 16 x 16 result keeps D[4 (l >> 4) + r][l & 15] in element r.
+//   the 16 x 16 result keeps D[(l >> 4) + 4 r][l & 15] in element r.
 __device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_gram(const double *__restrict__ X, int64
         for (int qb = 0; qb < 4; qb++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int il = qa * 16 + 4 * (lane >> 4) + r;
+                const int il = qa * 16 + (lane >> 4) + 4 * r;
                 const int jl = qb * 16 + (lane & 15);
                 out[il * GT + jl] = acc[qa][qb][r];
             }
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(512) void k_rotate(double *__restrict__ X, int64_t 
             if (col >= n) continue;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int64_t row = r0 + rb * 16 + 4 * (lane >> 4) + r;
+                const int64_t row = r0 + rb * 16 + (lane >> 4) + 4 * r;
                 if (row < D) X[row * ldx + col] = acc[rb][q][r];
             }
         }
