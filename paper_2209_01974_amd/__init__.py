@@ -88,6 +88,9 @@ def lib() -> C.CDLL:
     """Load libfd.so (raises if it has not been built: no fallback)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime; loading it first makes libfd bind
+        # to that same runtime (one HIP runtime per process).
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError("libfd.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
         L = C.CDLL(LIB_PATH)
