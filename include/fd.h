@@ -162,11 +162,15 @@ fd_status fd_rotate(int64_t D, int32_t m, int32_t n, double *X_dev, int64_t ldx,
                     const double *Q_dev, int64_t ldq, void *stream);
 
 /* Symmetric eigendecomposition of a small device matrix (n <= 512), FP64,
- * cyclic parallel Jacobi on the GPU: S = U diag(w) U^t.  S_dev (ld lds) is
- * overwritten; w_dev (n) ascending; U_dev (n x n, ld ldu) eigenvectors in
- * columns.                                                                  */
+ * cyclic block Jacobi on the GPU: S = U diag(w) U^t.  S_dev (ld lds) is
+ * symmetric; w_dev (n) ascending; U_dev (n x n, ld ldu) eigenvectors in
+ * columns.  S_dev is only read.                                            */
 fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *U_dev,
                   int64_t ldu, void *stream);
+
+/* Outer Jacobi sweeps of the last fd_syev (or internal eigensolve) on this
+ * process; a diagnostic for tests and tuning.                               */
+int32_t fd_syev_last_sweeps(void);
 
 #define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */
 #define FD_ORTHO_CHOLQR2 1 /* two Cholesky-QR passes, SVQB2 if one fails    */

@@ -101,6 +101,8 @@ def lib() -> C.CDLL:
         L.fd_matrix_free.argtypes = [_P]
         L.fd_matrix_free.restype = None
         L.fd_last_error.restype = C.c_char_p
+        L.fd_syev_last_sweeps.restype = C.c_int32
+        L.fd_syev_last_sweeps.argtypes = []
         _lib = L
     return _lib
 
@@ -262,6 +264,10 @@ def syev(S, w, U, stream=None) -> None:
     ps, lds, _ = _blk(S, "S")
     pu, ldu, _ = _blk(U, "U")
     _check(lib().fd_syev(S.shape[0], ps, lds, C.c_void_p(w.data_ptr()), pu, ldu, _stream(stream)))
+
+
+def syev_last_sweeps() -> int:
+    return int(lib().fd_syev_last_sweeps())
 
 
 def orthog(V, method: int = FD_ORTHO_SVQB2, seed: int = 0, stream=None) -> int:

@@ -423,6 +423,8 @@ fd_status fd_syev(int32_t n, double *S, int64_t lds, double *w, double *U, int64
     return syev(n, S, lds, w, U, ldu, (hipStream_t)stream);
 }
 
+int32_t fd_syev_last_sweeps(void) { return last_syev_sweeps(); }
+
 fd_status fd_orthog(int64_t D, int32_t ns, double *V, int64_t ldv, int32_t method, uint64_t seed, int32_t *rank,
                     void *stream) {
     if (!V || D < 1 || ns < 1 || ns > 512 || ldv < ns) return fail(FD_ERR_INVALID, "fd_orthog: bad arguments");

@@ -267,184 +267,363 @@ fd_status rotate(int64_t D, int m, int n, double *X, int64_t ldx, const double *
     return FD_OK;
 }
 
-// -------------------------------------------------------------- Jacobi --
+// -------------------------------------------------------- block Jacobi --
+// Symmetric eigensolver for n <= 512 (FP64): cyclic block Jacobi.  Indices
+// are cut into blocks of 16; a round pairs the blocks by the round-robin
+// ("chess tournament") schedule.  For every pair (I, J) one wavefront
+// diagonalizes the 32 x 32 matrix A[I u J, I u J] in LDS with scalar cyclic
+// Jacobi and keeps the accumulated rotation R; then A <- J^t A J and U <- U J
+// for the block-diagonal J of all pairs, as independent 32 x 32 tiles
+// R_a^t A_ab R_b and U_rb R_b on the FP64 matrix cores.  Sweeps repeat until
+// the off-diagonal norm stops decreasing or falls below 4 n eps ||A||_F.
+// Indices past n are zero rows and columns: they never mix with the others.
 namespace {
 
-constexpr int JT = 1024;  // threads of the one-workgroup small-matrix kernels
+constexpr int JB = 16;  // index block
+constexpr int JG = 32;  // pair group: two index blocks
 
-__device__ double block_sum(double v, double *red) {
-    // fixed-order tree reduction over the 1024 threads
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = JT / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
+struct PairList {
+    int n;
+    unsigned char I[16], J[16];
+};
+
+__device__ __forceinline__ int grp_index(int l, int I, int J) { return l < JB ? I * JB + l : J * JB + (l - JB); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
-// Cyclic Jacobi with the round-robin ("chess tournament") ordering: in each
-// round the N/2 disjoint index pairs are rotated at once -- rows of all pairs
-// first, then columns -- so one round applies J^t A J for J a product of
-// commuting plane rotations.  A (n x n, ld lda) may live in LDS or global
-// memory; U (ld ldu) accumulates the rotations.
-__device__ void jacobi_body(int n, double *A, int lda, double *U, int ldu, double *cs_c,
-                            double *cs_s, int *pp, int *pq, double *red) {
-    const int tid = threadIdx.x;
-    const int N = n + (n & 1);  // even number of "players"; index n is a dummy
-    const int half = N / 2;
-    for (int e = tid; e < n * n; e += JT) {
-        const int i = e / n, j = e % n;
-        U[(int64_t)i * ldu + j] = (i == j) ? 1.0 : 0.0;
+__global__ __launch_bounds__(256) void k_bj_solve(int np, const double *__restrict__ A, PairList pl,
+                                                  double *__restrict__ Rbuf, double thr2) {
+    __shared__ double red[2][256];
+    __shared__ double S[JG][JG + 1];
+    __shared__ double R[JG][JG + 1];
+    __shared__ double cc[JG / 2], ss[JG / 2];
+    __shared__ int pp[JG / 2], pq[JG / 2];
+    const int k = blockIdx.x, I = pl.I[k], J = pl.J[k];
+    const int lane = threadIdx.x;  // 0..255
+    for (int e = lane; e < JG * JG; e += 256) {
+        const int r = e / JG, c = e % JG;
+        S[r][c] = A[(int64_t)grp_index(r, I, J) * np + grp_index(c, I, J)];
+        R[r][c] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    double fro = 0.0;
-    for (int e = tid; e < n * n; e += JT) {
-        const double a = A[(e / n) * lda + e % n];
-        fro += a * a;
-    }
-    fro = block_sum(fro, red);
-    for (int sweep = 0; sweep < 40; sweep++) {
-        double off = 0.0;
-        for (int e = tid; e < n * n; e += JT) {
-            const int i = e / n, j = e % n;
-            if (i != j) {
-                const double a = A[i * lda + j];
-                off += a * a;
-            }
+    for (int sweep = 0; sweep < 10; sweep++) {
+        double off = 0.0, dg = 0.0;
+        for (int e = lane; e < JG * JG; e += 256) {
+            const int r = e / JG, c = e % JG;
+            const double v = S[r][c];
+            if (r == c) dg += v * v;
+            else off += v * v;
         }
-        off = block_sum(off, red);
-        if (!(off > 1e-32 * fro)) break;  // also stops on NaN
-        for (int rnd = 0; rnd < N - 1; rnd++) {
-            for (int k = tid; k < half; k += JT) {
-                // circle method: position 0 fixed, positions 1..N-1 rotate
-                auto who = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + rnd) % (N - 1); };
-                int p = who(k), q = who(N - 1 - k);
+        red[0][lane] = off;
+        red[1][lane] = dg;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (lane < w) {
+                red[0][lane] += red[0][lane + w];
+                red[1][lane] += red[1][lane + w];
+            }
+            __syncthreads();
+        }
+        off = red[0][0];
+        dg = red[1][0];
+        __syncthreads();
+        // thr2: squared relative target, about 1e-3 of the whole matrix's
+        // off-diagonal level after the previous sweep (down to 1e-16)
+        if (!(off > thr2 * (off + dg))) break;
+        for (int rnd = 0; rnd < JG - 1; rnd++) {
+            if (lane < JG / 2) {
+                auto who = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + rnd) % (JG - 1); };
+                int p = who(lane), q = who(JG - 1 - lane);
                 if (p > q) {
-                    int t = p;
+                    const int t = p;
                     p = q;
                     q = t;
                 }
                 double c = 1.0, s = 0.0;
-                if (q < n) {
-                    const double apq = A[p * lda + q];
-                    if (apq != 0.0) {
-                        const double app = A[p * lda + p], aqq = A[q * lda + q];
-                        const double th = (aqq - app) / (2.0 * apq);
-                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                    }
+                const double apq = S[p][q];
+                if (apq != 0.0) {
+                    const double th = (S[q][q] - S[p][p]) / (2.0 * apq);
+                    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
                 }
-                pp[k] = p;
-                pq[k] = q;
-                cs_c[k] = c;
-                cs_s[k] = s;
+                pp[lane] = p;
+                pq[lane] = q;
+                cc[lane] = c;
+                ss[lane] = s;
             }
             __syncthreads();
-            // rows p, q  <-  (c row_p - s row_q, s row_p + c row_q)
-            for (int e = tid; e < half * n; e += JT) {
-                const int k = e / n, j = e % n;
-                const int p = pp[k], q = pq[k];
-                const double s = cs_s[k];
-                if (q >= n || s == 0.0) continue;
-                const double c = cs_c[k];
-                const double ap = A[p * lda + j], aq = A[q * lda + j];
-                A[p * lda + j] = c * ap - s * aq;
-                A[q * lda + j] = s * ap + c * aq;
+            for (int e = lane; e < (JG / 2) * JG; e += 256) {  // rows p, q
+                const int kk = e / JG, j = e % JG;
+                const double s = ss[kk];
+                if (s == 0.0) continue;
+                const int p = pp[kk], q = pq[kk];
+                const double c = cc[kk];
+                const double ap = S[p][j], aq = S[q][j];
+                S[p][j] = c * ap - s * aq;
+                S[q][j] = s * ap + c * aq;
             }
             __syncthreads();
-            // columns p, q of A and U
-            for (int e = tid; e < half * n; e += JT) {
-                const int k = e / n, i = e % n;
-                const int p = pp[k], q = pq[k];
-                const double s = cs_s[k];
-                if (q >= n || s == 0.0) continue;
-                const double c = cs_c[k];
-                const double ap = A[i * lda + p], aq = A[i * lda + q];
-                A[i * lda + p] = c * ap - s * aq;
-                A[i * lda + q] = s * ap + c * aq;
-                const double up = U[(int64_t)i * ldu + p], uq = U[(int64_t)i * ldu + q];
-                U[(int64_t)i * ldu + p] = c * up - s * uq;
-                U[(int64_t)i * ldu + q] = s * up + c * uq;
+            for (int e = lane; e < (JG / 2) * JG; e += 256) {  // columns p, q of S and R
+                const int kk = e / JG, i = e % JG;
+                const double s = ss[kk];
+                if (s == 0.0) continue;
+                const int p = pp[kk], q = pq[kk];
+                const double c = cc[kk];
+                const double ap = S[i][p], aq = S[i][q];
+                S[i][p] = c * ap - s * aq;
+                S[i][q] = s * ap + c * aq;
+                const double rp = R[i][p], rq = R[i][q];
+                R[i][p] = c * rp - s * rq;
+                R[i][q] = s * rp + c * rq;
             }
             __syncthreads();
-            for (int k = tid; k < half; k += JT) {
-                const int p = pp[k], q = pq[k];
-                if (q < n && cs_s[k] != 0.0) {
-                    A[p * lda + q] = 0.0;
-                    A[q * lda + p] = 0.0;
-                }
+            if (lane < JG / 2 && ss[lane] != 0.0) {
+                S[pp[lane]][pq[lane]] = 0.0;
+                S[pq[lane]][pp[lane]] = 0.0;
             }
             __syncthreads();
         }
     }
+    double *Ro = Rbuf + (int64_t)k * JG * JG;
+    for (int e = lane; e < JG * JG; e += 256) Ro[e] = R[e / JG][e % JG];
 }
 
-// eigenvalues ascending (ties by index), eigenvector columns permuted alike
-__device__ void jacobi_sort(int n, const double *A, int lda, const double *U, int ldu, double *w,
-                            double *Uo, int64_t ldo) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += JT) {
-        const double wi = A[i * lda + i];
+// out = X * Y for 32 x 32 LDS tiles (TX: use X^t), one wavefront, FP64 MFMA.
+template <bool TX>
+__device__ void mm32(const double (*X)[JG + 1], const double (*Y)[JG + 1], double (*O)[JG + 1]) {
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = (dbl4)0.0;
+#pragma unroll
+    for (int k0 = 0; k0 < JG; k0 += 4) {
+        double xa[2], yb[2];
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            xa[q] = TX ? X[k0 + lk][q * 16 + li] : X[q * 16 + li][k0 + lk];
+            yb[q] = Y[k0 + lk][q * 16 + li];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) acc[a][b] = mfma16x16x4(xa[a], yb[b], acc[a][b]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) O[a * 16 + lk + 4 * r][b * 16 + li] = acc[a][b][r];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_bj_apply(int np, double *__restrict__ A, double *__restrict__ U,
+                                                 PairList pl, const double *__restrict__ Rbuf) {
+    __shared__ double T[JG][JG + 1];
+    __shared__ double X[JG][JG + 1];
+    __shared__ double Ra[JG][JG + 1];
+    __shared__ double Rb[JG][JG + 1];
+    const int ng = pl.n, lane = threadIdx.x;
+    const int t = blockIdx.x;
+    if (t < ng * ng) {
+        const int a = t / ng, b = t % ng;
+        const int Ia = pl.I[a], Ja = pl.J[a], Ib = pl.I[b], Jb = pl.J[b];
+        for (int e = lane; e < JG * JG; e += 64) {
+            const int r = e / JG, c = e % JG;
+            T[r][c] = A[(int64_t)grp_index(r, Ia, Ja) * np + grp_index(c, Ib, Jb)];
+            Ra[r][c] = Rbuf[(int64_t)a * JG * JG + e];
+            Rb[r][c] = Rbuf[(int64_t)b * JG * JG + e];
+        }
+        __syncthreads();
+        mm32<false>(T, Rb, X);   // X = A_ab R_b
+        mm32<true>(Ra, X, T);    // T = R_a^t X
+        for (int e = lane; e < JG * JG; e += 64) {
+            const int r = e / JG, c = e % JG;
+            A[(int64_t)grp_index(r, Ia, Ja) * np + grp_index(c, Ib, Jb)] = T[r][c];
+        }
+    } else {
+        const int u = t - ng * ng;
+        const int rt = u / ng, b = u % ng;
+        const int Ib = pl.I[b], Jb = pl.J[b];
+        for (int e = lane; e < JG * JG; e += 64) {
+            const int r = e / JG, c = e % JG;
+            T[r][c] = U[(int64_t)(rt * JG + r) * np + grp_index(c, Ib, Jb)];
+            Rb[r][c] = Rbuf[(int64_t)b * JG * JG + e];
+        }
+        __syncthreads();
+        mm32<false>(T, Rb, X);   // X = U_rb R_b
+        for (int e = lane; e < JG * JG; e += 64) {
+            const int r = e / JG, c = e % JG;
+            U[(int64_t)(rt * JG + r) * np + grp_index(c, Ib, Jb)] = X[r][c];
+        }
+    }
+}
+
+// A (np x np, zero padded) <- S; U <- I
+__global__ void k_bj_init(int n, int np, const double *__restrict__ S, int64_t lds, double *__restrict__ A,
+                          double *__restrict__ U) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)np * np) return;
+    const int i = (int)(e / np), j = (int)(e % np);
+    A[e] = (i < n && j < n) ? S[(int64_t)i * lds + j] : 0.0;
+    U[e] = (i == j) ? 1.0 : 0.0;
+}
+
+// off-diagonal and total squared Frobenius norms (one workgroup, fixed order)
+__global__ __launch_bounds__(1024) void k_bj_norms(int np, const double *__restrict__ A, double *out) {
+    __shared__ double so[1024], sd[1024];
+    double o = 0.0, d = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)np * np; e += 1024) {
+        const double v = A[e];
+        if (e / np == e % np) d += v * v;
+        else o += v * v;
+    }
+    so[threadIdx.x] = o;
+    sd[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            so[threadIdx.x] += so[threadIdx.x + w];
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = so[0];
+        out[1] = sd[0];
+    }
+}
+
+// G <- 1.5 I - 0.5 G  (one Newton-Schulz step toward (U^t U)^(-1/2))
+__global__ void k_newton_schulz(int n, double *G) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    G[e] = ((e / n == e % n) ? 1.5 : 0.0) - 0.5 * G[e];
+}
+
+// lam_j = u_j^t (S u_j): column sums of U o (S U), fixed order
+__global__ void k_rayleigh_cols(int n, const double *__restrict__ U, int64_t ldu, const double *__restrict__ SU,
+                                double *__restrict__ lam) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += U[(int64_t)i * ldu + j] * SU[(int64_t)i * n + j];
+    lam[j] = s;
+}
+
+__global__ void k_copy_mat(int n, const double *__restrict__ a, int64_t lda, double *__restrict__ b, int64_t ldb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    b[(int64_t)(e / n) * ldb + e % n] = a[(int64_t)(e / n) * lda + e % n];
+}
+
+// w = lam sorted ascending (ties by index), Uo = columns of X permuted alike
+__global__ __launch_bounds__(1024) void k_sort_pairs(int n, const double *__restrict__ lam,
+                                                     const double *__restrict__ X, int64_t ldx, double *w,
+                                                     double *Uo, int64_t ldo) {
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double wi = lam[i];
+        int r = 0;
+        for (int j = 0; j < n; j++) r += (lam[j] < wi) || (lam[j] == wi && j < i);
+        w[r] = wi;
+        for (int k = 0; k < n; k++) Uo[(int64_t)k * ldo + r] = X[(int64_t)k * ldx + i];
+    }
+}
+
+// eigenvalues ascending (ties by index) and the eigenvector columns alike
+__global__ __launch_bounds__(1024) void k_bj_finish(int n, int np, const double *__restrict__ A,
+                                                    const double *__restrict__ U, double *w, double *Uo,
+                                                    int64_t ldo) {
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double wi = A[(int64_t)i * np + i];
         int r = 0;
         for (int j = 0; j < n; j++) {
-            const double wj = A[j * lda + j];
+            const double wj = A[(int64_t)j * np + j];
             r += (wj < wi) || (wj == wi && j < i);
         }
         w[r] = wi;
-        for (int k = 0; k < n; k++) Uo[(int64_t)k * ldo + r] = U[(int64_t)k * ldu + i];
+        for (int k = 0; k < n; k++) Uo[(int64_t)k * ldo + r] = U[(int64_t)k * np + i];
     }
-}
-
-__global__ __launch_bounds__(JT) void k_syev(int n, double *S, int64_t lds, double *w, double *Uo,
-                                               int64_t ldo, double *Uw, int in_lds) {
-    extern __shared__ double sh[];
-    __shared__ double red[JT];
-    __shared__ double cs_c[256], cs_s[256];
-    __shared__ int pp[256], pq[256];
-    double *A;
-    int lda;
-    if (in_lds) {
-        A = sh;
-        lda = n + 1;
-        for (int e = threadIdx.x; e < n * n; e += JT) A[(e / n) * lda + e % n] = S[(e / n) * lds + e % n];
-        __syncthreads();
-    } else {
-        A = S;
-        lda = (int)lds;
-    }
-    jacobi_body(n, A, lda, Uw, n, cs_c, cs_s, pp, pq, red);
-    __syncthreads();
-    jacobi_sort(n, A, lda, Uw, n, w, Uo, ldo);
-    if (in_lds) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += JT) S[(e / n) * lds + e % n] = A[(e / n) * lda + e % n];
-    }
-}
-
-size_t syev_lds(int n) { return (size_t)n * (n + 1) * sizeof(double); }
-
-fd_status launch_syev(int n, double *S, int64_t lds, double *w, double *Uo, int64_t ldo, double *Uw,
-                      hipStream_t s) {
-    const bool in_lds = syev_lds(n) <= 144 * 1024;  // + 14 KB static LDS, under 160 KB
-    size_t sh = in_lds ? syev_lds(n) : 0;
-    FD_HIP(hipFuncSetAttribute((const void *)k_syev, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)std::max<size_t>(sh, 1)));
-    hipLaunchKernelGGL(k_syev, dim3(1), dim3(JT), sh, s, n, S, lds, w, Uo, ldo, Uw, in_lds ? 1 : 0);
-    FD_HIP(hipGetLastError());
-    return FD_OK;
 }
 
 }  // namespace
 
-fd_status syev(int n, double *S, int64_t lds, double *w, double *U, int64_t ldu, hipStream_t s) {
+static int g_syev_sweeps = 0;
+int last_syev_sweeps() { return g_syev_sweeps; }
+
+fd_status syev(int n, double *S, int64_t lds, double *w, double *Uo, int64_t ldu, hipStream_t s) {
     if (n < 1 || n > 512) return fail(FD_ERR_INVALID, "syev: need 1 <= n <= 512");
-    double *Uw = (double *)workspace((size_t)n * n * sizeof(double), 1);
-    if (!Uw) return fail(FD_ERR_OOM, "syev: workspace");
-    return launch_syev(n, S, lds, w, U, ldu, Uw, s);
+    g_syev_sweeps = 0;
+    const int np = (n + JG - 1) / JG * JG;
+    const int nbk = np / JB;        // even
+    const int ng = nbk / 2;
+    const size_t nn = (size_t)np * np;
+    double *ws = (double *)workspace((2 * nn + (size_t)ng * JG * JG + 2) * sizeof(double), 1);
+    if (!ws) return fail(FD_ERR_OOM, "syev: workspace");
+    double *A = ws, *U = ws + nn, *Rbuf = ws + 2 * nn, *nrm = Rbuf + (size_t)ng * JG * JG;
+    hipLaunchKernelGGL(k_bj_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, np, S, lds, A, U);
+    FD_HIP(hipGetLastError());
+    double prev = INFINITY, rel = 1.0;
+    const double tol = n * 2.220446049250313e-16;
+    for (int sweep = 0; sweep < 30; sweep++) {
+        const double thr2 = std::max(1e-32, 1e-6 * rel * rel);
+        for (int rnd = 0; rnd < nbk - 1; rnd++) {
+            PairList pl;
+            pl.n = ng;
+            for (int k = 0; k < ng; k++) {
+                auto who = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + rnd) % (nbk - 1); };
+                int p = who(k), q = who(nbk - 1 - k);
+                pl.I[k] = (unsigned char)std::min(p, q);
+                pl.J[k] = (unsigned char)std::max(p, q);
+            }
+            hipLaunchKernelGGL(k_bj_solve, dim3(ng), dim3(256), 0, s, np, A, pl, Rbuf, thr2);
+            FD_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_bj_apply, dim3(2 * ng * ng), dim3(64), 0, s, np, A, U, pl, Rbuf);
+            FD_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_bj_norms, dim3(1), dim3(1024), 0, s, np, A, nrm);
+        FD_HIP(hipGetLastError());
+        double h[2];
+        FD_HIP(hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, s));
+        FD_HIP(hipStreamSynchronize(s));
+        const double off = std::sqrt(h[0]), fro = std::sqrt(h[0] + h[1]);
+        g_syev_sweeps = sweep + 1;
+        if (!std::isfinite(off)) return fail(FD_ERR_BREAKDOWN, "syev: non-finite matrix");
+        // converged, or stalled at the rounding floor of the tile updates
+        if (off <= tol * fro || (off > 0.9 * prev && off <= 10 * tol * fro)) break;
+        prev = off;
+        rel = off / fro;
+    }
+    hipLaunchKernelGGL(k_bj_finish, dim3(1), dim3(1024), 0, s, n, np, A, U, w, Uo, ldu);
+    FD_HIP(hipGetLastError());
+    // The product of many block rotations drifts from orthogonality by a few
+    // hundred ulps; one Newton-Schulz step U <- U (3 I - U^t U) / 2 squares
+    // that error.  A is free now and holds the n x n Gram matrix.
+    FD_TRY(gram(n, n, n, Uo, ldu, Uo, ldu, A, n, true, s));
+    hipLaunchKernelGGL(k_newton_schulz, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, n, A);
+    FD_HIP(hipGetLastError());
+    FD_TRY(rotate(n, n, n, Uo, ldu, A, n, s));
+    // Eigenvalues as Rayleigh quotients u_j^t S u_j of the untouched input:
+    // error O(eps ||S||) plus the square of the eigenvector error, instead of
+    // the rounding the tile updates left on the diagonal of A.
+    const unsigned gb = (unsigned)((n * n + 255) / 256);
+    hipLaunchKernelGGL(k_copy_mat, dim3(gb), dim3(256), 0, s, n, S, lds, U, (int64_t)n);
+    FD_HIP(hipGetLastError());
+    FD_TRY(rotate(n, n, n, U, n, Uo, ldu, s));  // U <- S Uo
+    hipLaunchKernelGGL(k_rayleigh_cols, dim3((n + 255) / 256), dim3(256), 0, s, n, Uo, ldu, U, A);
+    FD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_copy_mat, dim3(gb), dim3(256), 0, s, n, Uo, ldu, U, (int64_t)n);
+    FD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_pairs, dim3(1), dim3(1024), 0, s, n, A, U, (int64_t)n, w, Uo, ldu);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
 }
 
 // ------------------------------------------------------ SVQB / CholQR ----

@@ -112,6 +112,7 @@ fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const doub
 fd_status rotate(int64_t D, int m, int n, double *X, int64_t ldx, const double *Q, int64_t ldq,
                  hipStream_t s);
 fd_status syev(int n, double *S, int64_t lds, double *w, double *U, int64_t ldu, hipStream_t s);
+int last_syev_sweeps();
 fd_status col_resid(int64_t D, int n, const double *V, const double *W, int64_t ld,
                     const double *theta, double *rho, hipStream_t s);
 // SVQB transform: Q = Dg U L^-1/2 from Gram G (n x n, dense ld n); returns

@@ -23,7 +23,7 @@ def built():
 
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "fd.h")).read()
-    declared = set(re.findall(r"^\s*(?:fd_status|void|const char \*)\s*(fd_[a-z_]+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:fd_status|void|int32_t|const char \*)\s*(fd_[a-z_]+)\s*\(", hdr, re.M))
     assert {"fd_build_matrix", "fd_spmmv", "fd_cheb_filter", "fd_orthog", "fd_rayleigh_ritz",
             "fd_solve"} <= declared
     L = fd.lib()
