@@ -172,6 +172,13 @@ fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *
  * process; a diagnostic for tests and tuning.                               */
 int32_t fd_syev_last_sweeps(void);
 
+/* Launch shape of the sparse kernels, process-wide (tuning; results do not
+ * depend on it).  order 0: each block walks `iters` consecutive groups of
+ * rows (0 = automatic); order 1: grid-stride over `grid` blocks per bundle
+ * (0 = automatic).  xcd != 0: every XCD owns a contiguous eighth of the rows.
+ * nontemporal != 0: operands that are streamed once bypass the caches.     */
+fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal);
+
 #define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */
 #define FD_ORTHO_CHOLQR2 1 /* two Cholesky-QR passes, SVQB2 if one fails    */
 

@@ -81,6 +81,7 @@ _SIGS = {
     "fd_orthog": [_I64, _I32, _P, _I64, _I32, C.c_uint64, C.POINTER(_I32), _P],
     "fd_rayleigh_ritz": [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P],
     "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
+    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32],
 }
 
 
@@ -264,6 +265,11 @@ def syev(S, w, U, stream=None) -> None:
     ps, lds, _ = _blk(S, "S")
     pu, ldu, _ = _blk(U, "U")
     _check(lib().fd_syev(S.shape[0], ps, lds, C.c_void_p(w.data_ptr()), pu, ldu, _stream(stream)))
+
+
+def spmmv_tune(order: int = 0, xcd: int = 1, iters: int = 0, grid: int = 0, nontemporal: int = 0) -> None:
+    """Launch shape of the sparse kernels (process-wide; results unchanged)."""
+    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal))
 
 
 def syev_last_sweeps() -> int:

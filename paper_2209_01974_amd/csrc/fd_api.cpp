@@ -425,6 +425,18 @@ fd_status fd_syev(int32_t n, double *S, int64_t lds, double *w, double *U, int64
 
 int32_t fd_syev_last_sweeps(void) { return last_syev_sweeps(); }
 
+fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal) {
+    if (order < 0 || order > 1 || iters < 0 || grid < 0 || grid > (1 << 24))
+        return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
+    SpmmvTune &t = spmmv_tune();
+    t.order = order;
+    t.xcd = xcd != 0;
+    t.iters = iters;
+    t.grid = grid;
+    t.nontemporal = nontemporal != 0;
+    return FD_OK;
+}
+
 fd_status fd_orthog(int64_t D, int32_t ns, double *V, int64_t ldv, int32_t method, uint64_t seed, int32_t *rank,
                     void *stream) {
     if (!V || D < 1 || ns < 1 || ns > 512 || ldv < ns) return fail(FD_ERR_INVALID, "fd_orthog: bad arguments");

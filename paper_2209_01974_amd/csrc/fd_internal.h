@@ -100,9 +100,17 @@ struct SpmmvCall {
 fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s);
 
 // Tunables of the sparse kernels (rows per block and XCD mapping).
+// Defaults from a sweep on MI355X (Anderson L=200, nb 1..64, FP64/FP32):
+// one row group per block with the hardware's own block order keeps the rows
+// in flight in one compact window, so the +-L and +-L^2 neighbours of the
+// gather are still in L2 / Infinity Cache; per-XCD row ranges (8 windows)
+// overflowed the Infinity Cache at nb = 64.
 struct SpmmvTune {
-    int iters = 4;     // row groups per wave
-    int xcd = 1;       // 1: contiguous row range per XCD
+    int order = 0;        // 0: consecutive row groups per block; 1: grid-stride
+    int xcd = 0;          // 1: each XCD owns a contiguous eighth of the rows
+    int iters = 1;        // order 0: row groups per block (0: automatic)
+    int grid = 0;         // order 1: blocks per bundle (0: automatic)
+    int nontemporal = 1;  // 1: streamed operands bypass the caches
 };
 SpmmvTune &spmmv_tune();
 

@@ -13,8 +13,10 @@
 // of a row are broadcast to its G lanes; the gathered rows x[col] are read
 // with one 16-byte load per lane.  With SELL-C-sigma the C rows of a chunk
 // read entry j from consecutive addresses (coalesced); CSR is SELL-1-1.
-// Blocks are remapped so that each of the 8 XCDs walks a contiguous range of
-// rows: stencil neighbours (+-1, +-L) then hit the XCD's own L2.
+// The rows in flight form one compact window (small blocks in launch order)
+// so that the gathered neighbours of a row are found in L2 / Infinity Cache;
+// the streamed operands (y, v, z) use non-temporal loads and stores.  A
+// per-XCD row partition and a grid-stride order are available as tunables.
 #include "fd_internal.h"
 
 namespace fd {
@@ -34,10 +36,12 @@ struct KArgs {
     const T *__restrict__ val;
     const int32_t *__restrict__ perm;
     int64_t nslots;
-    int64_t nblk;
+    int64_t ngroups;   // row groups of 256/G slots
+    int64_t nblk;      // logical blocks (order 0)
     int32_t cshift;
     int32_t iters;
     int32_t xcd;
+    int32_t order;     // 0: a block walks `iters` consecutive groups; 1: grid-stride
     const T *x; int64_t ldx, bx;
     T *y; int64_t ldy, by;
     const T *z; int64_t ldz, bz;
@@ -49,16 +53,49 @@ template <typename V>
 __device__ __forceinline__ V ld(const void *p) { return *reinterpret_cast<const V *>(p); }
 template <typename V>
 __device__ __forceinline__ void st(void *p, V x) { *reinterpret_cast<V *>(p) = x; }
+// streamed operands (read or written once per step): non-temporal, so that
+// they do not evict the gathered rows of x from L2 / Infinity Cache
+template <typename V, bool NT>
+__device__ __forceinline__ V lds(const void *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    else return *reinterpret_cast<const V *>(p);
+}
+template <typename V, bool NT>
+__device__ __forceinline__ void sts(void *p, V x) {
+    if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<V *>(p));
+    else *reinterpret_cast<V *>(p) = x;
+}
 
-template <typename T, int VEC, int G, int MODE, bool PERM>
+template <typename T, int VEC, int G, int MODE, bool PERM, bool NT>
 __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int RPB = 256 / G;
-    int64_t blk = blockIdx.x;
-    if (p.xcd) {
-        const int64_t per = (p.nblk + 7) >> 3;
-        blk = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // Row groups of this block.  order 0: groups [b iters, (b+1) iters) of
+    // logical block b; order 1: grid-stride, so that the blocks running at a
+    // time cover one compact window of rows.  With xcd != 0 the hardware's
+    // round-robin of workgroups over the 8 XCDs is undone: XCD x owns the
+    // x-th eighth of the groups.
+    int64_t g0, g1, gstep;
+    if (p.order == 0) {
+        int64_t blk = blockIdx.x;
+        if (p.xcd) {
+            const int64_t per = (p.nblk + 7) >> 3;
+            blk = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        }
         if (blk >= p.nblk) return;
+        g0 = blk * p.iters;
+        g1 = min(p.ngroups, g0 + p.iters);
+        gstep = 1;
+    } else if (p.xcd) {
+        const int64_t per = (p.ngroups + 7) >> 3;
+        const int64_t x = blockIdx.x & 7;
+        g0 = x * per + (blockIdx.x >> 3);
+        g1 = min(p.ngroups, (x + 1) * per);
+        gstep = gridDim.x >> 3;
+    } else {
+        g0 = blockIdx.x;
+        g1 = p.ngroups;
+        gstep = gridDim.x;
     }
     const int64_t bnd = blockIdx.y;
     const T *x = p.x + bnd * p.bx;
@@ -66,8 +103,8 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     const int grp = threadIdx.x / G;
     const int q = threadIdx.x % G;
     const uint32_t step = 1u << p.cshift;
-    for (int it = 0; it < p.iters; ++it) {
-        const int64_t s = (blk * p.iters + it) * RPB + grp;
+    for (int64_t g = g0; g < g1; g += gstep) {
+        const int64_t s = g * RPB + grp;
         if (s >= p.nslots) break;
         const int64_t c = s >> p.cshift;
         const uint32_t p0 = p.ptr[c];
@@ -102,25 +139,25 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
         const V acc = acc0 + acc1;
         T *yr = y + row * p.ldy + q * VEC;
         if constexpr (MODE == 0) {
-            st<V>(yr, acc);
+            sts<V, NT>(yr, acc);
         } else {
             const V xi = ld<V>(xq + row * p.ldx);
             V t = p.a * acc + p.b * xi;
             if constexpr (MODE == 1) {
-                st<V>(yr, t);
+                sts<V, NT>(yr, t);
             } else if constexpr (MODE == 2) {
                 T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
-                V vi = ld<V>(vr);
+                V vi = lds<V, NT>(vr);
                 t -= vi;
-                st<V>(yr, t);
-                st<V>(vr, p.cv * vi + p.cx * xi + p.ct * t);
+                sts<V, NT>(yr, t);
+                sts<V, NT>(vr, p.cv * vi + p.cx * xi + p.ct * t);
             } else {
-                const V zi = ld<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+                const V zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
                 t -= zi;
-                st<V>(yr, t);
+                sts<V, NT>(yr, t);
                 T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
-                V vi = ld<V>(vr);
-                st<V>(vr, vi + p.ct * t);
+                V vi = lds<V, NT>(vr);
+                sts<V, NT>(vr, vi + p.ct * t);
             }
         }
     }
@@ -137,36 +174,51 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     p.cshift = M.cshift;
     constexpr int RPB = 256 / G;
     const SpmmvTune &tn = spmmv_tune();
-    int iters = tn.iters;
-    if (iters <= 0) {
-        // about 8192 blocks or more per bundle for a large matrix
-        int64_t want = M.nslots / ((int64_t)RPB * 8192);
-        iters = (int)std::max<int64_t>(1, std::min<int64_t>(64, want));
-    }
-    p.iters = iters;
-    p.nblk = (M.nslots + (int64_t)RPB * iters - 1) / ((int64_t)RPB * iters);
+    p.ngroups = (M.nslots + RPB - 1) / RPB;
+    p.order = tn.order;
     p.xcd = tn.xcd;
+    int64_t gx;
+    if (p.order == 0) {
+        int iters = tn.iters;
+        if (iters <= 0) {
+            // about 8192 blocks or more per bundle for a large matrix
+            int64_t want = M.nslots / ((int64_t)RPB * 8192);
+            iters = (int)std::max<int64_t>(1, std::min<int64_t>(64, want));
+        }
+        p.iters = iters;
+        p.nblk = (p.ngroups + iters - 1) / iters;
+        gx = p.xcd ? ((p.nblk + 7) / 8) * 8 : p.nblk;
+    } else {
+        p.iters = 0;
+        p.nblk = 0;
+        int64_t want = tn.grid > 0 ? tn.grid : 2048;
+        gx = std::min<int64_t>(want, std::max<int64_t>(8, p.ngroups));
+        gx = (gx + 7) / 8 * 8;
+    }
     p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;
     p.y = (T *)c.y; p.ldy = c.ldy; p.by = c.by;
     p.z = (const T *)c.z; p.ldz = c.ldz; p.bz = c.bz;
     p.v = (T *)c.v; p.ldv = c.ldv; p.bv = c.bv;
     p.a = (T)c.a; p.b = (T)c.b; p.cv = (T)c.cv; p.cx = (T)c.cx; p.ct = (T)c.ct;
-    int64_t gx = p.xcd ? ((p.nblk + 7) / 8) * 8 : p.nblk;
     if (gx > 0x7fffffff) return fail(FD_ERR_UNSUPPORTED, "SpMMV: grid too large");
     dim3 grid((unsigned)gx, (unsigned)c.nbundles), block(256);
     const bool perm = M.perm != nullptr;
-#define FD_L(MODE, PERM) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM>), grid, block, 0, s, p)
+    const bool nt = tn.nontemporal != 0;
+#define FD_L(MODE, PERM, NT) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT>), grid, block, 0, s, p)
+#define FD_L2(MODE, PERM) \
+    if (nt) FD_L(MODE, PERM, true); else FD_L(MODE, PERM, false)
     switch (c.mode * 2 + (perm ? 1 : 0)) {
-        case 0: FD_L(0, false); break;
-        case 1: FD_L(0, true); break;
-        case 2: FD_L(1, false); break;
-        case 3: FD_L(1, true); break;
-        case 4: FD_L(2, false); break;
-        case 5: FD_L(2, true); break;
-        case 6: FD_L(3, false); break;
-        case 7: FD_L(3, true); break;
+        case 0: FD_L2(0, false); break;
+        case 1: FD_L2(0, true); break;
+        case 2: FD_L2(1, false); break;
+        case 3: FD_L2(1, true); break;
+        case 4: FD_L2(2, false); break;
+        case 5: FD_L2(2, true); break;
+        case 6: FD_L2(3, false); break;
+        case 7: FD_L2(3, true); break;
         default: return fail(FD_ERR_INVALID, "SpMMV: bad mode");
     }
+#undef FD_L2
 #undef FD_L
     FD_HIP(hipGetLastError());
     return FD_OK;
@@ -175,7 +227,7 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
 }  // namespace
 
 SpmmvTune &spmmv_tune() {
-    static SpmmvTune t{0, 1};
+    static SpmmvTune t;
     return t;
 }
 
