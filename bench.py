@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
     ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
+                         "filter on one nb=64 FP64 bundle of the workload; prints the sizes and exits")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -123,6 +126,20 @@ def main():
     alpha, beta = 2.0 / (lam_hi - lam_lo), -(lam_hi + lam_lo) / (lam_hi - lam_lo)
     g = torch.Generator(device=dev)
     g.manual_seed(0)
+    if args.pmc_sample:
+        n = 1 << 27  # 1 GiB of doubles
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        fd.stream(0, a, c, stream=stream)
+        torch.cuda.synchronize()
+        V1 = torch.randn((D, nb), generator=g, dtype=torch.float64, device=dev)
+        Z1, Z2 = torch.empty_like(V1), torch.empty_like(V1)
+        fd.cheb_filter(m, V1, fd.cheb_coeffs(1, beta, 0.0, 12), alpha, beta, Z1, Z2, nb, stream=stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_sample": True, "copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                          "fused_launches": 10, "fused_algorithmic_bytes": fused_bytes(nnz, D, nb, 8),
+                          "D": D, "nnz": nnz, "nb": nb}), flush=True)
+        return
     V = torch.randn((D, ns), generator=g, dtype=torch.float64, device=dev)
     W = torch.empty_like(V)
     W1 = torch.empty((D, nb), dtype=torch.float64, device=dev)
@@ -193,19 +210,22 @@ def main():
     # ---------------------------------------------------------- sweep ----
     if not args.no_sweep:
         sweep = []
-        # device copy (STREAM-like): torch's elementwise copy on 4 GB
-        a = torch.empty((D, 64), dtype=torch.float64, device=dev).normal_()
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(10):
-            b.copy_(a)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        out["stream_copy_GBs"] = round(2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-        del a, b
+        # device STREAM (the paper's b_m measurement): copy and triad on 4 GB arrays
+        a = torch.empty(D * 64, dtype=torch.float64, device=dev).normal_()
+        b = torch.empty_like(a).normal_()
+        c = torch.empty_like(a)
+        for op, name, nbytes in ((0, "stream_copy_GBs", 2), (1, "stream_triad_GBs", 3)):
+            for _ in range(3):
+                fd.stream(op, a, c, b, 0.5, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                fd.stream(op, a, c, b, 0.5, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out[name] = round(nbytes * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        log("STREAM copy %.0f GB/s, triad %.0f GB/s" % (out["stream_copy_GBs"], out["stream_triad_GBs"]))
+        del a, b, c
         for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
             for w in (1, 4, 8, 16, 32, 64):
                 X = torch.empty((D, w), dtype=dt, device=dev).normal_()

@@ -168,6 +168,13 @@ fd_status fd_rotate(int64_t D, int32_t m, int32_t n, double *X_dev, int64_t ldx,
 fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *U_dev,
                   int64_t ldu, void *stream);
 
+/* STREAM-style bandwidth kernels on device arrays of n doubles (n even,
+ * 16-byte aligned): op 0 copies c = a, op 1 is the triad c = a + scalar b.
+ * The paper measures its memory bandwidth b_m with STREAM (Sec. 3.3,
+ * Table 4); these give the same figure for the GPU's HBM.                  */
+fd_status fd_stream(int32_t op, int64_t n, const double *a_dev, const double *b_dev, double *c_dev,
+                    double scalar, void *stream);
+
 /* Outer Jacobi sweeps of the last fd_syev (or internal eigensolve) on this
  * process; a diagnostic for tests and tuning.                               */
 int32_t fd_syev_last_sweeps(void);

@@ -82,6 +82,7 @@ _SIGS = {
     "fd_rayleigh_ritz": [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P],
     "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
     "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32],
+    "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
 }
 
 
@@ -270,6 +271,13 @@ def syev(S, w, U, stream=None) -> None:
 def spmmv_tune(order: int = 0, xcd: int = 1, iters: int = 0, grid: int = 0, nontemporal: int = 0) -> None:
     """Launch shape of the sparse kernels (process-wide; results unchanged)."""
     _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal))
+
+
+def stream(op: int, a, c, b=None, scalar: float = 0.0, stream=None) -> None:
+    """op 0: c = a; op 1: c = a + scalar b (1-D float64 GPU tensors)."""
+    _check(lib().fd_stream(op, a.numel(), C.c_void_p(a.data_ptr()),
+                           C.c_void_p(b.data_ptr()) if b is not None else None,
+                           C.c_void_p(c.data_ptr()), scalar, _stream(stream)))
 
 
 def syev_last_sweeps() -> int:

@@ -425,6 +425,11 @@ fd_status fd_syev(int32_t n, double *S, int64_t lds, double *w, double *U, int64
 
 int32_t fd_syev_last_sweeps(void) { return last_syev_sweeps(); }
 
+fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, double *c, double scalar,
+                    void *stream) {
+    return stream_op(op, n, a, b, c, scalar, (hipStream_t)stream);
+}
+
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal) {
     if (order < 0 || order > 1 || iters < 0 || grid < 0 || grid > (1 << 24))
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");

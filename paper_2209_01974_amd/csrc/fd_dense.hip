@@ -836,7 +836,31 @@ __global__ void k_symmetrize(int n, double *H) {
 
 unsigned nblocks(int64_t tot) { return (unsigned)((tot + 255) / 256); }
 
+// STREAM-style kernels (the paper measures b_m with STREAM): 16-byte loads,
+// non-temporal stores, grid-stride over n/2 pairs of doubles.
+typedef double d2v __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_stream(int op, int64_t n2, const d2v *__restrict__ a,
+                                                const d2v *__restrict__ b, d2v *__restrict__ c, double sc) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (int64_t)gridDim.x * 256) {
+        d2v r = __builtin_nontemporal_load(a + i);
+        if (op == 1) r += sc * __builtin_nontemporal_load(b + i);
+        __builtin_nontemporal_store(r, c + i);
+    }
+}
+
 }  // namespace
+
+fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s) {
+    if (n < 2 || (n & 1) || (op != 0 && op != 1) || !a || !c || (op == 1 && !b) ||
+        ((uintptr_t)a | (uintptr_t)c | (uintptr_t)b) % 16)
+        return fail(FD_ERR_INVALID, "stream: need even n, 16-byte aligned arrays, op 0 or 1");
+    const int64_t n2 = n / 2;
+    const int64_t g = std::min<int64_t>((n2 + 255) / 256, 256 * 32);
+    hipLaunchKernelGGL(k_stream, dim3((unsigned)g), dim3(256), 0, s, op, n2, (const d2v *)a, (const d2v *)b,
+                       (d2v *)c, sc);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
 
 fd_status fill_normal(int64_t D, int n, double *V, int64_t ldv, uint64_t seed, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_normal, dim3(nblocks(D * n)), dim3(256), 0, s, D, n, V, ldv, (const int *)nullptr,

@@ -138,6 +138,7 @@ fd_status convert_f32_f64(int64_t D, int n, const float *src, int64_t lds, doubl
 fd_status gather_cols(int64_t D, int n, const double *src, int64_t lds, const int *idx,
                       double *dst, int64_t ldd, hipStream_t s);
 fd_status symmetrize(int n, double *H, hipStream_t s);
+fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s);
 
 // Process-wide device workspace for the small dense steps.
 void *workspace(size_t bytes, int slot);

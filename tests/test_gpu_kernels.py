@@ -242,3 +242,40 @@ def test_rayleigh_ritz_parity(name, nb, ns):
     Vn = Vd.cpu().numpy()
     fresh = np.linalg.norm(O.spmmv(A, Vn) - Vn * th, axis=0)
     assert np.abs(fresh - rho).max() <= 1e-11 * normH
+
+
+def test_stream_kernels_exact():
+    n = 1 << 20
+    a = torch.arange(n, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 3.0, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    fd.stream(0, a, c)
+    assert torch.equal(c, a)
+    fd.stream(1, a, c, b, 0.5)
+    assert torch.equal(c, a + 1.5)
+
+
+@pytest.mark.parametrize("order,xcd,iters,grid,nt", [(0, 1, 0, 0, 0), (0, 0, 4, 0, 1), (1, 1, 0, 1024, 1),
+                                                     (1, 0, 0, 96, 0)])
+def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt):
+    """Every launch shape computes each row the same way: bitwise equal."""
+    m, A = build("hub8", "sell", 32, 256)
+    X = dev(start_block(A.D, 16, 1))
+    Y0 = torch.empty_like(X)
+    fd.spmmv(m, X, Y0)
+    try:
+        fd.spmmv_tune(order, xcd, iters, grid, nt)
+        Y1 = torch.empty_like(X)
+        fd.spmmv(m, X, Y1)
+        lo, hi = O.gershgorin(A)
+        alpha, beta = O.scaling(lo, hi)
+        mu = O.cheb_coeffs(0, -0.2, 0.2, 9)
+        V = dev(start_block(A.D, 32, 2))
+        W1 = torch.empty_like(V)
+        W2 = torch.empty_like(V)
+        fd.cheb_filter(m, V, mu, alpha, beta, W1, W2, 16)
+        torch.cuda.synchronize()
+    finally:
+        fd.spmmv_tune()
+    assert torch.equal(Y0, Y1)
+    assert relerr(V.cpu().numpy(), O.cheb_filter(A, start_block(A.D, 32, 2), mu, alpha, beta)) <= 1e-12
