@@ -140,6 +140,8 @@ def main():
                           "fused_launches": 10, "fused_algorithmic_bytes": fused_bytes(nnz, D, nb, 8),
                           "D": D, "nnz": nnz, "nb": nb}), flush=True)
         return
+    shape = fd.autotune(m, "f64", nb, stream=stream)
+    log("autotuned launch shape (order, xcd, iters, grid, nontemporal): %s" % (shape,))
     V = torch.randn((D, ns), generator=g, dtype=torch.float64, device=dev)
     W = torch.empty_like(V)
     W1 = torch.empty((D, nb), dtype=torch.float64, device=dev)
@@ -203,7 +205,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "anderson3d_L%d_W16.5_seed1" % L, "D": D, "nnz": nnz,
                       "n_search": ns, "nb": nb, "degree": degree, "format": args.fmt,
-                      "target": "128 pairs nearest E=0 (damped delta)", "parallelism": "single GPU"},
+                      "target": "128 pairs nearest E=0 (damped delta)", "parallelism": "single GPU",
+                      "launch_shape": list(shape)},
            "roofline": roofline,
            "hbm_frac_of_step": round(value / HBM_PEAK_GBS, 4)}
 
@@ -228,6 +231,7 @@ def main():
         del a, b, c
         for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
             for w in (1, 4, 8, 16, 32, 64):
+                fd.autotune(m, "f64" if sv == 8 else "f32", w, stream=stream)
                 X = torch.empty((D, w), dtype=dt, device=dev).normal_()
                 Y = torch.empty_like(X)
                 for _ in range(3):

@@ -168,6 +168,13 @@ fd_status fd_rotate(int64_t D, int32_t m, int32_t n, double *X_dev, int64_t ldx,
 fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *U_dev,
                   int64_t ldu, void *stream);
 
+/* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
+ * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
+ * D x nb (allocated and freed here) and keeps the fastest in the handle for
+ * (dtype, nb); later calls on this matrix use it.  shape (5 ints, may be
+ * NULL) receives order, xcd, iters, grid, nontemporal.  Synchronizes.      */
+fd_status fd_autotune(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
+
 /* STREAM-style bandwidth kernels on device arrays of n doubles (n even,
  * 16-byte aligned): op 0 copies c = a, op 1 is the triad c = a + scalar b.
  * The paper measures its memory bandwidth b_m with STREAM (Sec. 3.3,
@@ -182,8 +189,12 @@ int32_t fd_syev_last_sweeps(void);
 /* Launch shape of the sparse kernels, process-wide (tuning; results do not
  * depend on it).  order 0: each block walks `iters` consecutive groups of
  * rows (0 = automatic); order 1: grid-stride over `grid` blocks per bundle
- * (0 = automatic).  xcd != 0: every XCD owns a contiguous eighth of the rows.
- * nontemporal != 0: operands that are streamed once bypass the caches.     */
+ * (0 = automatic).  xcd 1: every XCD owns a contiguous eighth of the rows;
+ * xcd 2 (order 0 only): XCD x owns the row chunks x, x+8, x+16, ... of
+ * `grid` rows each (0 = 1024).  nontemporal != 0: operands that are streamed
+ * once bypass the caches.  Default: order 0, xcd 2, iters 1, grid 1024,
+ * nontemporal 1.  A shape chosen by fd_autotune for a matrix takes
+ * precedence for that matrix.                                              */
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal);
 
 #define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */

@@ -83,6 +83,7 @@ _SIGS = {
     "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
     "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32],
     "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
+    "fd_autotune": [_P, C.c_int, _I32, _P, _P],
 }
 
 
@@ -268,9 +269,16 @@ def syev(S, w, U, stream=None) -> None:
     _check(lib().fd_syev(S.shape[0], ps, lds, C.c_void_p(w.data_ptr()), pu, ldu, _stream(stream)))
 
 
-def spmmv_tune(order: int = 0, xcd: int = 1, iters: int = 0, grid: int = 0, nontemporal: int = 0) -> None:
+def spmmv_tune(order: int = 0, xcd: int = 2, iters: int = 1, grid: int = 1024, nontemporal: int = 1) -> None:
     """Launch shape of the sparse kernels (process-wide; results unchanged)."""
     _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal))
+
+
+def autotune(m: "Matrix", dtype: str = "f64", nb: int = 64, stream=None) -> tuple:
+    """Pick the fastest launch shape of the fused step for (m, dtype, nb)."""
+    shape = (C.c_int32 * 5)()
+    _check(lib().fd_autotune(m.handle, FD_F64 if dtype == "f64" else FD_F32, nb, shape, _stream(stream)))
+    return tuple(shape)
 
 
 def stream(op: int, a, c, b=None, scalar: float = 0.0, stream=None) -> None:

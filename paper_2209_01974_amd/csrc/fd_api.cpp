@@ -425,17 +425,33 @@ fd_status fd_syev(int32_t n, double *S, int64_t lds, double *w, double *U, int64
 
 int32_t fd_syev_last_sweeps(void) { return last_syev_sweeps(); }
 
+fd_status fd_autotune(fd_matrix m, fd_dtype dt, int32_t nb, int32_t *shape, void *stream) {
+    FD_TRY(need_device(m));
+    if ((dt != FD_F64 && dt != FD_F32) || !nb_ok(nb)) return fail(FD_ERR_INVALID, "fd_autotune: bad dtype or nb");
+    SpmmvTune t;
+    FD_TRY(autotune(m->dev, dt, nb, (hipStream_t)stream, &t));
+    if (shape) {
+        shape[0] = t.order;
+        shape[1] = t.xcd;
+        shape[2] = t.iters;
+        shape[3] = t.grid;
+        shape[4] = t.nontemporal;
+    }
+    return FD_OK;
+}
+
 fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, double *c, double scalar,
                     void *stream) {
     return stream_op(op, n, a, b, c, scalar, (hipStream_t)stream);
 }
 
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal) {
-    if (order < 0 || order > 1 || iters < 0 || grid < 0 || grid > (1 << 24))
+    if (order < 0 || order > 1 || xcd < 0 || xcd > 2 || (order == 1 && xcd == 2) || iters < 0 || grid < 0 ||
+        grid > (1 << 24))
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
     SpmmvTune &t = spmmv_tune();
     t.order = order;
-    t.xcd = xcd != 0;
+    t.xcd = xcd;
     t.iters = iters;
     t.grid = grid;
     t.nontemporal = nontemporal != 0;
@@ -507,6 +523,13 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         FD_HIP(hipMemcpy(Vd, V0, (size_t)D * ns * 8, hipMemcpyHostToDevice));
     } else {
         FD_TRY(fill_normal(D, ns, Vd, ns, P->seed, s));
+    }
+    // pick the sparse kernels' launch shape for this matrix once (large
+    // matrices only: small ones are bound by launch latency)
+    if (D >= (1 << 20)) {
+        const int di = 0, lg = __builtin_ctz((unsigned)nb);
+        if (!m->dev.tuned[di][lg]) FD_TRY(autotune(m->dev, FD_F64, nb, s, nullptr));
+        if (P->precision == 1 && !m->dev.tuned[1][lg]) FD_TRY(autotune(m->dev, FD_F32, nb, s, nullptr));
     }
     std::vector<double> th(ns), rho(ns);
     std::vector<int> sel;

@@ -54,6 +54,20 @@ void gershgorin(const HostCSR &A, double &lo, double &hi);
 fd_status cheb_coeffs(int kind, double a, double b, int n, double *mu);
 
 // --------------------------------------------------------- device matrix --
+// Defaults from sweeps on MI355X (Anderson L=200, nb 1..64, FP64/FP32): one
+// row group per block keeps the rows in flight in one compact window, so the
+// far neighbours of the gather (+-L^2) are still in the Infinity Cache; the
+// blocks are spread over the 8 XCDs in chunks of 1024 consecutive rows, so
+// that near neighbours (+-1, +-L) are in the same XCD's L2.  Contiguous
+// per-XCD eighths (8 windows) overflowed the Infinity Cache at nb = 64.
+struct SpmmvTune {
+    int order = 0;        // 0: consecutive row groups per block; 1: grid-stride
+    int xcd = 2;          // 1: contiguous eighth per XCD; 2: interleaved row chunks
+    int iters = 1;        // order 0: row groups per block (0: automatic)
+    int grid = 1024;      // order 1: blocks per bundle; xcd 2: rows per chunk
+    int nontemporal = 1;  // 1: streamed operands bypass the caches
+};
+
 // One layout serves CSR and SELL: "slot" s of the device format belongs to
 // chunk s >> cshift; its entries start at ptr[chunk] + (s & (C-1)) and step
 // by C; the chunk length is (ptr[chunk+1] - ptr[chunk]) >> cshift.  CSR is
@@ -68,6 +82,9 @@ struct DevMatrix {
     double *val64 = nullptr;   // stored
     float *val32 = nullptr;    // stored
     int32_t *perm = nullptr;   // nslots (SELL) or null (CSR); -1 for padding slots
+    // launch shapes chosen by fd_autotune, per dtype and log2(nb)
+    bool tuned[2][7] = {};
+    SpmmvTune tune[2][7];
 };
 
 }  // namespace fd
@@ -99,20 +116,8 @@ struct SpmmvCall {
 };
 fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s);
 
-// Tunables of the sparse kernels (rows per block and XCD mapping).
-// Defaults from a sweep on MI355X (Anderson L=200, nb 1..64, FP64/FP32):
-// one row group per block with the hardware's own block order keeps the rows
-// in flight in one compact window, so the +-L and +-L^2 neighbours of the
-// gather are still in L2 / Infinity Cache; per-XCD row ranges (8 windows)
-// overflowed the Infinity Cache at nb = 64.
-struct SpmmvTune {
-    int order = 0;        // 0: consecutive row groups per block; 1: grid-stride
-    int xcd = 0;          // 1: each XCD owns a contiguous eighth of the rows
-    int iters = 1;        // order 0: row groups per block (0: automatic)
-    int grid = 0;         // order 1: blocks per bundle (0: automatic)
-    int nontemporal = 1;  // 1: streamed operands bypass the caches
-};
 SpmmvTune &spmmv_tune();
+fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *best);
 
 // Dense kernels (fd_dense.hip).
 fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const double *Y,

@@ -17,6 +17,8 @@
 // so that the gathered neighbours of a row are found in L2 / Infinity Cache;
 // the streamed operands (y, v, z) use non-temporal loads and stores.  A
 // per-XCD row partition and a grid-stride order are available as tunables.
+#include <type_traits>
+
 #include "fd_internal.h"
 
 namespace fd {
@@ -42,6 +44,7 @@ struct KArgs {
     int32_t iters;
     int32_t xcd;
     int32_t order;     // 0: a block walks `iters` consecutive groups; 1: grid-stride
+    int32_t sg;        // xcd == 2: logical blocks per super-group
     const T *x; int64_t ldx, bx;
     T *y; int64_t ldy, by;
     const T *z; int64_t ldz, bz;
@@ -78,9 +81,14 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     int64_t g0, g1, gstep;
     if (p.order == 0) {
         int64_t blk = blockIdx.x;
-        if (p.xcd) {
+        if (p.xcd == 1) {
             const int64_t per = (p.nblk + 7) >> 3;
             blk = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        } else if (p.xcd == 2) {
+            // XCD x owns super-groups x, x + 8, x + 16, ... of sg blocks each:
+            // one compact window of rows overall, neighbouring rows on one XCD
+            const int64_t j = blockIdx.x >> 3;
+            blk = ((j / p.sg) * 8 + (blockIdx.x & 7)) * p.sg + (j % p.sg);
         }
         if (blk >= p.nblk) return;
         g0 = blk * p.iters;
@@ -173,7 +181,9 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     p.nslots = M.nslots;
     p.cshift = M.cshift;
     constexpr int RPB = 256 / G;
-    const SpmmvTune &tn = spmmv_tune();
+    const int lg = __builtin_ctz((unsigned)c.nb);
+    const int di = std::is_same<T, double>::value ? 0 : 1;
+    const SpmmvTune &tn = M.tuned[di][lg] ? M.tune[di][lg] : spmmv_tune();
     p.ngroups = (M.nslots + RPB - 1) / RPB;
     p.order = tn.order;
     p.xcd = tn.xcd;
@@ -187,10 +197,19 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
         }
         p.iters = iters;
         p.nblk = (p.ngroups + iters - 1) / iters;
-        gx = p.xcd ? ((p.nblk + 7) / 8) * 8 : p.nblk;
+        p.sg = 1;
+        if (p.xcd == 2) {
+            const int64_t rows = tn.grid > 0 ? tn.grid : 1024;  // super-group size in rows
+            p.sg = (int32_t)std::max<int64_t>(1, rows / ((int64_t)RPB * iters));
+            const int64_t q = 8LL * p.sg;
+            gx = (p.nblk + q - 1) / q * q;
+        } else {
+            gx = p.xcd ? ((p.nblk + 7) / 8) * 8 : p.nblk;
+        }
     } else {
         p.iters = 0;
         p.nblk = 0;
+        p.sg = 1;
         int64_t want = tn.grid > 0 ? tn.grid : 2048;
         gx = std::min<int64_t>(want, std::max<int64_t>(8, p.ngroups));
         gx = (gx + 7) / 8 * 8;
@@ -229,6 +248,64 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
 SpmmvTune &spmmv_tune() {
     static SpmmvTune t;
     return t;
+}
+
+// Launch-shape autotuner: time the fused Chebyshev step (the kernel the
+// filter repeats) for a few shapes on scratch blocks and keep the fastest
+// for this matrix, dtype and nb.
+fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *best_out) {
+    const size_t es = dt == FD_F64 ? 8 : 4;
+    const size_t bytes = (size_t)M.D * nb * es;
+    void *buf = nullptr;
+    FD_HIP(hipMalloc(&buf, 3 * bytes));
+    FD_HIP(hipMemsetAsync(buf, 0, 3 * bytes, s));
+    hipEvent_t e0, e1;
+    FD_HIP(hipEventCreate(&e0));
+    FD_HIP(hipEventCreate(&e1));
+    const SpmmvTune cands[] = {
+        {0, 2, 1, 512, 1}, {0, 2, 1, 1024, 1}, {0, 2, 1, 2048, 1}, {0, 2, 1, 8192, 1},
+        {0, 2, 2, 2048, 1}, {0, 0, 1, 0, 1},   {0, 1, 1, 0, 1},    {1, 1, 1, 4096, 1},
+    };
+    const int lg = __builtin_ctz((unsigned)nb);
+    const int di = dt == FD_F64 ? 0 : 1;
+    SpmmvCall c;
+    c.mode = 3;
+    c.nb = nb;
+    c.x = buf; c.ldx = nb;
+    c.z = (char *)buf + bytes; c.ldz = nb;
+    c.y = (char *)buf + bytes; c.ldy = nb;
+    c.v = (char *)buf + 2 * bytes; c.ldv = nb;
+    c.a = 0.5; c.b = 0.0; c.ct = 0.5;
+    // fewer repetitions for large matrices; at least 3
+    const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(20, (int64_t)4e9 / (int64_t)(bytes + 1)));
+    float best_ms = 1e30f;
+    SpmmvTune best = spmmv_tune();
+    fd_status st = FD_OK;
+    for (const SpmmvTune &t : cands) {
+        M.tune[di][lg] = t;
+        M.tuned[di][lg] = true;
+        st = launch_spmmv(M, dt, c, s);  // warm-up
+        if (st != FD_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(hipErrorUnknown, "autotune event"); break; }
+        for (int r = 0; r < reps && st == FD_OK; r++) st = launch_spmmv(M, dt, c, s);
+        if (st != FD_OK) break;
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    M.tune[di][lg] = best;
+    M.tuned[di][lg] = st == FD_OK;
+    if (best_out) *best_out = best;
+    return st;
 }
 
 fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s) {

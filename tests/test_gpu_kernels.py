@@ -279,3 +279,16 @@ def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt):
         fd.spmmv_tune()
     assert torch.equal(Y0, Y1)
     assert relerr(V.cpu().numpy(), O.cheb_filter(A, start_block(A.D, 32, 2), mu, alpha, beta)) <= 1e-12
+
+
+def test_autotune_keeps_results():
+    m, A = build("and13", "csr", 1, 1)
+    X = dev(start_block(A.D, 8, 3))
+    Y0 = torch.empty_like(X)
+    fd.spmmv(m, X, Y0)
+    shape = fd.autotune(m, "f64", 8)
+    assert shape[0] in (0, 1) and shape[1] in (0, 1, 2) and shape[4] in (0, 1)
+    Y1 = torch.empty_like(X)
+    fd.spmmv(m, X, Y1)
+    torch.cuda.synchronize()
+    assert torch.equal(Y0, Y1)
