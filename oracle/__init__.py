@@ -191,6 +191,57 @@ def spmmv(A: CSR, X: np.ndarray) -> np.ndarray:
     return Y
 
 
+def spmmv_rows(A: CSR, X: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """(A X)[rows] row by row from the definition y_i = sum_k A_ik x_k, in CSR
+    order (for checking sampled rows of a product too large for the oracle)."""
+    out = np.empty((rows.size, X.shape[1]))
+    for t, i in enumerate(rows):
+        a, b = A.rowptr[i], A.rowptr[i + 1]
+        acc = np.zeros(X.shape[1])
+        for k in range(a, b):
+            acc += A.val[k] * X[A.col[k]]
+        out[t] = acc
+    return out
+
+
+def cheb_filter_rows(A: CSR, V: np.ndarray, mu: np.ndarray, alpha: float, beta: float,
+                     rows: np.ndarray) -> np.ndarray:
+    """(p[alpha A + beta] V)[rows]: the same recurrence as cheb_filter, carried
+    only on the rows each step needs (row set of step k = rows of step k+1
+    plus their neighbours), so that sampled rows of a large filter can be
+    computed exactly as the definition states."""
+    n = mu.size - 1
+    sets = [np.unique(rows)]
+    for _ in range(n):
+        r = sets[-1]
+        nbr = np.concatenate([A.col[A.rowptr[i]:A.rowptr[i + 1]].astype(np.int64) for i in r])
+        sets.append(np.union1d(r, nbr))
+    sets = sets[::-1]  # sets[k]: rows where T_k is needed (T_k on sets[k])
+
+    def take(T, have, want):
+        return T[np.searchsorted(have, want)]
+
+    def apply_B(T, have, want):  # (alpha A + beta) T on rows `want`
+        out = np.empty((want.size, T.shape[1]))
+        for t, i in enumerate(want):
+            acc = np.zeros(T.shape[1])
+            for k in range(A.rowptr[i], A.rowptr[i + 1]):
+                acc += A.val[k] * T[np.searchsorted(have, A.col[k])]
+            out[t] = alpha * acc + beta * T[np.searchsorted(have, i)]
+        return out
+
+    final = sets[-1]
+    T0 = V[sets[0]].astype(np.float64)
+    T1 = apply_B(T0, sets[0], sets[1])
+    S = mu[0] * take(T0, sets[0], final) + mu[1] * take(T1, sets[1], final)
+    prev, prevset, cur, curset = T0, sets[0], T1, sets[1]
+    for k in range(2, n + 1):
+        nxt = 2.0 * apply_B(cur, curset, sets[k]) - take(prev, prevset, sets[k])
+        S += mu[k] * take(nxt, sets[k], final)
+        prev, prevset, cur, curset = cur, curset, nxt, sets[k]
+    return S[np.searchsorted(final, rows)]
+
+
 def gershgorin(A: CSR) -> tuple[float, float]:
     lo = C.c_double()
     hi = C.c_double()

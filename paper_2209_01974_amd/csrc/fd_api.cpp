@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -537,6 +539,9 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     std::memset(&st, 0, sizeof(st));
     st.norm_H = normH;
     bool fp32 = P->precision == 1;
+    // FD_TRACE=1: one JSON line per outer iteration on stderr
+    const char *tr = std::getenv("FD_TRACE");
+    const bool trace = tr && tr[0] == '1';
     double prev_max = INFINITY;
     const double tol = P->tol * normH;
     bool converged = false;
@@ -563,6 +568,15 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         for (int j = 0; j < ns; j++)
             if ((P->tau_hi <= P->tau_lo || (th[j] >= P->tau_lo && th[j] <= P->tau_hi)) && rho[j] <= tol) st.n_conv++;
         converged = (int)sel.size() == nt && mx <= tol;
+        if (trace) {
+            std::fprintf(stderr,
+                         "{\"fd_iter\": %d, \"max_resid_rel\": %.3e, \"n_in_window\": %d, \"n_conv\": %d, "
+                         "\"next_fp32\": %d, \"spmmv\": %lld, \"t_filter\": %.3f, \"t_orthog\": %.3f, "
+                         "\"t_rr\": %.3f, \"t\": %.3f}\n",
+                         it, mx / normH, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count,
+                         st.t_filter, st.t_orthog, st.t_rr, now() - t0);
+            std::fflush(stderr);
+        }
         if (converged || it >= P->max_iter) break;
         // mixed precision: leave FP32 once the residual is near what an FP32
         // filter can deliver (1e-5 ||H||), or once it stalls (under 10 %

@@ -185,3 +185,15 @@ def test_fd_hubbard8_vs_dense():
     assert r.resid.max() <= 1e-9 * r.norm_H
     fresh = np.linalg.norm(O.spmmv(A, r.evecs) - r.evecs * r.evals, axis=0)
     assert fresh.max() <= 1e-9 * r.norm_H
+
+
+def test_row_sampled_forms_match_full_oracle():
+    A = O.anderson(7, 1.0, 16.5, 2)
+    X = start_block(A.D, 5, 1)
+    rows = np.array([0, 3, 100, 342, 17, 17 * 7 + 2])
+    np.testing.assert_array_equal(O.spmmv_rows(A, X, rows), O.spmmv(A, X)[rows])
+    lo, hi = O.gershgorin(A)
+    alpha, beta = O.scaling(lo, hi)
+    mu = O.cheb_coeffs(1, 0.1, 0.0, 4)
+    full = O.cheb_filter(A, X, mu, alpha, beta)
+    np.testing.assert_allclose(O.cheb_filter_rows(A, X, mu, alpha, beta, rows), full[rows], rtol=0, atol=1e-13)
