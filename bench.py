@@ -80,6 +80,40 @@ def traffic_from_profile(kernel_src: str):
     return prof.get("hbm_bytes_per_launch")
 
 
+def fd_runs(args, fd, np):
+    """FD to residual 1e-9 ||H||, FP64 filter vs FP32 filter (mixed), same
+    start block, window, degree and interval rule; eigenpairs per second."""
+    from fd_inputs import start_block
+    fdres = {}
+    # (name, model, window, N_t, N_s, nb, degree)
+    runs = [("hubbard8", dict(L=8, n_up=4, n_dn=4, U=4.0), -0.5, 0.5, 16, 128, 16, 100)]
+    if args.hubbard14:
+        runs.append(("hubbard14", dict(L=14, n_up=7, n_dn=7, U=8.0), -1.0, 1.0, 64, 256, 32, 800))
+    for name, kw, lo, hi, nt, nsr, nbr, deg in runs:
+        mh = fd.build_matrix("hubbard", t=1.0, **kw)
+        V0 = start_block(mh.D, nsr, 0) if mh.D * nsr <= 50_000_000 else None
+        res = {}
+        evs = {}
+        for prec, label in ((0, "fp64"), (1, "mixed")):
+            r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=200, tol=1e-9, precision=prec, V0=V0,
+                         seed=0, want_vectors=False, adapt=1)
+            st = r.stats
+            res[label] = {"converged": r.status == fd.FD_OK, "eigenpairs_per_s": round(nt / st["t_total"], 4),
+                          "t_total_s": round(st["t_total"], 3), "iters": st["iters"],
+                          "iters_fp32": st["iters_fp32"], "spmmv": st["spmmv_count"],
+                          "t_filter_s": round(st["t_filter"], 3), "t_orthog_s": round(st["t_orthog"], 3),
+                          "t_rr_s": round(st["t_rr"], 3), "max_resid_rel": st["max_resid"] / st["norm_H"]}
+            evs[label] = r.evals
+            normH = st["norm_H"]
+            log("FD %s %s: %s" % (name, label, res[label]))
+        res["config"] = {"D": mh.D, "nnz": mh.nnz, "window": [lo, hi], "n_target": nt, "n_search": nsr,
+                         "nb": nbr, "degree": deg, "window_rule": "adaptive"}
+        res["mixed_vs_fp64_max_rel_eval_diff"] = float(np.max(np.abs(evs["mixed"] - evs["fp64"])) / normH)
+        res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
+        fdres[name] = res
+    return fdres
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +130,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the nb / precision sweep")
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
     ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
+    ap.add_argument("--fd-only", action="store_true", help="only the FD eigenpairs/s runs (no Anderson step)")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
@@ -115,6 +150,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+
+    if args.fd_only:
+        print(json.dumps({"fd": fd_runs(args, fd, np)}), flush=True)
+        return
 
     # ---------------------------------------------------------- workload ----
     L, nb, ns, degree = args.L, args.nb, args.ns, args.degree
@@ -266,32 +305,7 @@ def main():
 
     # ---------------------------------------------------- FD eigenpairs/s ----
     if not args.no_fd:
-        from fd_inputs import start_block
-        fdres = {}
-        runs = [("hubbard8", dict(L=8, n_up=4, n_dn=4, U=4.0), -0.5, 0.5, 16, 128, 16, 100)]
-        if args.hubbard14:
-            runs.append(("hubbard14", dict(L=14, n_up=7, n_dn=7, U=8.0), -1.0, 1.0, 64, 256, 32, 800))
-        for name, kw, lo, hi, nt, nsr, nbr, deg in runs:
-            mh = fd.build_matrix("hubbard", t=1.0, **kw)
-            V0 = start_block(mh.D, nsr, 0) if mh.D * nsr <= 50_000_000 else None
-            res = {}
-            for prec, label in ((0, "fp64"), (1, "mixed")):
-                r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=200, tol=1e-9, precision=prec, V0=V0,
-                             seed=0, want_vectors=False)
-                st = r.stats
-                res[label] = {"converged": r.status == fd.FD_OK, "eigenpairs_per_s": round(nt / st["t_total"], 3),
-                              "t_total_s": round(st["t_total"], 3), "iters": st["iters"],
-                              "iters_fp32": st["iters_fp32"], "spmmv": st["spmmv_count"],
-                              "t_filter_s": round(st["t_filter"], 3), "t_orthog_s": round(st["t_orthog"], 3),
-                              "t_rr_s": round(st["t_rr"], 3), "max_resid_rel": st["max_resid"] / st["norm_H"]}
-                res[label + "_evals"] = r.evals
-                normH = st["norm_H"]
-                log("FD %s %s: %s" % (name, label, res[label]))
-            d = np.abs(res.pop("mixed_evals") - res.pop("fp64_evals")) / normH
-            res["mixed_vs_fp64_max_rel_eval_diff"] = float(np.max(d))
-            res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
-            fdres[name] = res
-        out["fd"] = fdres
+        out["fd"] = fd_runs(args, fd, np)
 
     # ------------------------------------------------------- CPU oracle ----
     if not args.no_cpu:

@@ -168,6 +168,17 @@ fd_status fd_rotate(int64_t D, int32_t m, int32_t n, double *X_dev, int64_t ldx,
 fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *U_dev,
                   int64_t ldu, void *stream);
 
+/* Chebyshev moments of the kernel polynomial method (Sec. 4.1 computes the
+ * density of states with KPM; Weisse et al. RMP 2006):
+ *   mu_k = (1 / (nb D)) sum_r <r| T_k(alpha A + beta) |r>,  k = 0 .. nmom-1,
+ * over the nb columns r of the device block R (D x nb, ld ldr; normalised
+ * random vectors give the stochastic trace).  nmom even: nmom/2 SpMMVs with
+ * T_2m = 2 T_m^2 - 1 and T_2m+1 = 2 T_m+1 T_m - T_1.  W1, W2: device
+ * workspaces D x nb (ld ldw).  mu_host: nmom entries.  FP64.  Synchronizes. */
+fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R_dev, int64_t ldr, int32_t nmom,
+                         double alpha, double beta, double *W1_dev, double *W2_dev, int64_t ldw,
+                         double *mu_host, void *stream);
+
 /* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
  * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
  * D x nb (allocated and freed here) and keeps the fastest in the handle for
@@ -229,6 +240,10 @@ typedef struct {
     int32_t precision;     /* 0: FP64 filter; 1: FP32 filter, FP64 rest       */
     int32_t ortho;         /* FD_ORTHO_SVQB2 or FD_ORTHO_CHOLQR2              */
     uint64_t seed;         /* start block when V0 is NULL                     */
+    int32_t adapt;         /* 0: filter for the whole window; 1: each
+                              iteration shrink the filter's window around tau
+                              to the N_t-th nearest Ritz value in the window
+                              (Sec. 2: target interval tracked during FD)   */
 } fd_solve_params;
 
 typedef struct {

@@ -242,6 +242,24 @@ def cheb_filter_rows(A: CSR, V: np.ndarray, mu: np.ndarray, alpha: float, beta: 
     return S[np.searchsorted(final, rows)]
 
 
+def kpm_moments(A: CSR, R: np.ndarray, nmom: int, alpha: float, beta: float) -> np.ndarray:
+    """mu_k = (1/(nR D)) sum_r <r|T_k(alpha A + beta)|r>, k < nmom, by the plain
+    recurrence T_{k+1} r = 2 B T_k r - T_{k-1} r (no doubling)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    D, nr = R.shape
+    mu = np.empty(nmom)
+    T0 = R.copy()
+    T1 = alpha * spmmv(A, T0) + beta * T0
+    mu[0] = np.sum(R * T0) / (nr * D)
+    if nmom > 1:
+        mu[1] = np.sum(R * T1) / (nr * D)
+    for k in range(2, nmom):
+        T2 = 2.0 * (alpha * spmmv(A, T1) + beta * T1) - T0
+        mu[k] = np.sum(R * T2) / (nr * D)
+        T0, T1 = T1, T2
+    return mu
+
+
 def gershgorin(A: CSR) -> tuple[float, float]:
     lo = C.c_double()
     hi = C.c_double()
@@ -347,14 +365,17 @@ class FDResult:
 
 
 def fd_solve(A: CSR, V0: np.ndarray, tau_lo: float, tau_hi: float, n_target: int,
-             degree: int, tol: float = 1e-9, max_iter: int = 50) -> FDResult:
+             degree: int, tol: float = 1e-9, max_iter: int = 50, adapt: bool = False) -> FDResult:
     """Plain FD (Alg. 1 reading) with a fixed degree and fixed target window.
 
     [lam_l, lam_r] = Gershgorin interval; alpha, beta from it; ||H|| =
     max(|lam_l|, |lam_r|).  Loop: V <- SVQB2(V); Rayleigh-Ritz; if the n_target
     pairs nearest tau in the window all have rho <= tol * ||H||, stop; else
     V <- p[A] V with the Jackson-damped indicator of the scaled window (a
-    damped delta at tau when tau_lo == tau_hi).
+    damped delta at tau when tau_lo == tau_hi).  With adapt, the filter's
+    window is shrunk each iteration to tau +- the distance of the n_target-th
+    nearest Ritz value in the window (the target interval is tracked during
+    the iteration, Sec. 2).
     """
     lam_l, lam_r = gershgorin(A)
     alpha, beta = scaling(lam_l, lam_r)
@@ -377,6 +398,13 @@ def fd_solve(A: CSR, V0: np.ndarray, tau_lo: float, tau_hi: float, n_target: int
         if ok or it >= max_iter:
             order = sel[np.argsort(theta[sel], kind="stable")]
             return FDResult(theta[order], V[:, order], rho[order], ok, it, spmv, norm_H, hist)
+        if adapt and tau_hi > tau_lo and sel.size == n_target:
+            tau = 0.5 * (tau_lo + tau_hi)
+            r = abs(theta[sel[-1]] - tau)
+            lo_w, hi_w = max(tau_lo, tau - r), min(tau_hi, tau + r)
+            a = min(1.0, max(-1.0, alpha * lo_w + beta))
+            b = max(a, min(1.0, alpha * hi_w + beta))
+            mu = cheb_coeffs(0, a, b, degree)
         V = cheb_filter(A, V, mu, alpha, beta)
         spmv += degree
         it += 1

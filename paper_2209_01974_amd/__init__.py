@@ -48,7 +48,7 @@ class SolveParams(C.Structure):
     _fields_ = [("tau_lo", C.c_double), ("tau_hi", C.c_double), ("n_target", C.c_int32),
                 ("n_search", C.c_int32), ("nb", C.c_int32), ("degree", C.c_int32),
                 ("max_iter", C.c_int32), ("tol", C.c_double), ("precision", C.c_int32),
-                ("ortho", C.c_int32), ("seed", C.c_uint64)]
+                ("ortho", C.c_int32), ("seed", C.c_uint64), ("adapt", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -84,6 +84,7 @@ _SIGS = {
     "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32],
     "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
     "fd_autotune": [_P, C.c_int, _I32, _P, _P],
+    "fd_kpm_moments": [_P, _I32, _P, _I64, _I32, _D, _D, _P, _P, _I64, _P, _P],
 }
 
 
@@ -274,6 +275,38 @@ def spmmv_tune(order: int = 0, xcd: int = 2, iters: int = 1, grid: int = 1024, n
     _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal))
 
 
+def kpm_moments(m: "Matrix", R, nmom: int, alpha: float, beta: float, stream=None) -> np.ndarray:
+    """KPM moments mu_k = <r|T_k(alpha A + beta)|r> / D averaged over the
+    columns r of the GPU block R (fd_kpm_moments)."""
+    import torch
+    nr = R.shape[1]
+    total = np.zeros(nmom)
+    j = 0
+    while j < nr:  # column chunks of a width the kernels take (1, 2, 4, ..., 64)
+        w = 64
+        while w > nr - j:
+            w //= 2
+        blk = R[:, j:j + w]
+        pr, ldr, dt = _blk(blk, "R")
+        if dt != FD_F64:
+            raise ValueError("R must be float64")
+        W1 = torch.empty((R.shape[0], w), dtype=torch.float64, device=R.device)
+        W2 = torch.empty_like(W1)
+        mu = np.empty(nmom)
+        _check(lib().fd_kpm_moments(m.handle, w, pr, ldr, nmom, alpha, beta, C.c_void_p(W1.data_ptr()),
+                                    C.c_void_p(W2.data_ptr()), W1.stride(0), mu.ctypes.data, _stream(stream)))
+        total += mu * (w / nr)
+        j += w
+    return total
+
+
+def window_count(mu_kpm: np.ndarray, D: int, a: float, b: float) -> float:
+    """Estimated number of eigenvalues in the scaled window [a, b]:
+    D * sum_k c_k g_k mu_k with the Jackson-damped indicator coefficients."""
+    c = cheb_coeffs(0, a, b, mu_kpm.size - 1)
+    return float(D * np.dot(c, mu_kpm))
+
+
 def autotune(m: "Matrix", dtype: str = "f64", nb: int = 64, stream=None) -> tuple:
     """Pick the fastest launch shape of the fused step for (m, dtype, nb)."""
     shape = (C.c_int32 * 5)()
@@ -322,10 +355,11 @@ class SolveResult:
 
 def solve(m: Matrix, tau_lo: float, tau_hi: float, n_target: int, n_search: int, nb: int, degree: int,
           max_iter: int = 50, tol: float = 1e-9, precision: int = 0, ortho: int = FD_ORTHO_SVQB2,
-          seed: int = 0, V0: np.ndarray | None = None, want_vectors: bool = True) -> SolveResult:
+          seed: int = 0, V0: np.ndarray | None = None, want_vectors: bool = True,
+          adapt: int = 0) -> SolveResult:
     """fd_solve; V0 is a host D x n_search float64 array (or None)."""
     import torch
-    p = SolveParams(tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol, precision, ortho, seed)
+    p = SolveParams(tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol, precision, ortho, seed, adapt)
     ev = np.full(n_target, np.nan)
     rs = np.full(n_target, np.nan)
     vecs = torch.empty((m.D, n_target), dtype=torch.float64, device="cuda") if want_vectors else None

@@ -442,6 +442,60 @@ fd_status fd_autotune(fd_matrix m, fd_dtype dt, int32_t nb, int32_t *shape, void
     return FD_OK;
 }
 
+fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R, int64_t ldr, int32_t nmom, double alpha,
+                         double beta, double *W1, double *W2, int64_t ldw, double *mu, void *stream) {
+    FD_TRY(need_device(m));
+    if (!nb_ok(nb) || nmom < 2 || (nmom & 1) || !mu) return fail(FD_ERR_INVALID, "fd_kpm_moments: bad nb or nmom");
+    FD_TRY(check_block(R, ldr, nb, FD_F64, nb, "fd_kpm_moments R"));
+    FD_TRY(check_block(W1, ldw, nb, FD_F64, nb, "fd_kpm_moments W1"));
+    FD_TRY(check_block(W2, ldw, nb, FD_F64, nb, "fd_kpm_moments W2"));
+    const int64_t D = m->dev.D;
+    if (overlap(W1, ldw, W2, ldw, D, 8) || overlap(R, ldr, W1, ldw, D, 8) || overlap(R, ldr, W2, ldw, D, 8))
+        return fail(FD_ERR_INVALID, "fd_kpm_moments: R, W1, W2 overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const int half = nmom / 2;
+    // per column: d[2m] = <T_m|T_m>, d[2m+1] = <T_{m+1}|T_m>, m = 0 .. half-1
+    double *dots = (double *)workspace((size_t)nmom * nb * sizeof(double), 5);
+    if (!dots) return fail(FD_ERR_OOM, "fd_kpm_moments: workspace");
+    FD_TRY(copy_block(D, nb, R, ldr, W2, ldw, s));  // T_0
+    SpmmvCall c;
+    c.nb = nb;
+    c.mode = 1;  // T_1 = B T_0
+    c.x = W2; c.ldx = ldw;
+    c.y = W1; c.ldy = ldw;
+    c.a = alpha; c.b = beta;
+    FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
+    FD_TRY(col_dots(D, nb, W2, ldw, W2, ldw, dots, s));
+    FD_TRY(col_dots(D, nb, W1, ldw, W2, ldw, dots + nb, s));
+    double *cur = W1, *prev = W2;  // T_m, T_{m-1}
+    for (int k = 1; k < half; k++) {
+        c.mode = 4;  // prev <- T_{m+1} = 2 B T_m - T_{m-1}
+        c.x = cur; c.ldx = ldw;
+        c.z = prev; c.ldz = ldw;
+        c.y = prev; c.ldy = ldw;
+        c.a = 2.0 * alpha; c.b = 2.0 * beta;
+        FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
+        FD_TRY(col_dots(D, nb, cur, ldw, cur, ldw, dots + (size_t)(2 * k) * nb, s));
+        FD_TRY(col_dots(D, nb, prev, ldw, cur, ldw, dots + (size_t)(2 * k + 1) * nb, s));
+        std::swap(cur, prev);
+    }
+    std::vector<double> h((size_t)nmom * nb);
+    FD_HIP(hipMemcpyAsync(h.data(), dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    // doubling: T_{2m} = 2 T_m^2 - T_0, T_{2m+1} = 2 T_{m+1} T_m - T_1
+    std::vector<double> d(nmom, 0.0);
+    for (int k = 0; k < nmom; k++)
+        for (int j = 0; j < nb; j++) d[k] += h[(size_t)k * nb + j];
+    const double norm = 1.0 / ((double)nb * (double)D);
+    mu[0] = d[0] * norm;
+    mu[1] = d[1] * norm;
+    for (int k = 1; k < half; k++) {
+        mu[2 * k] = (2.0 * d[2 * k] - d[0]) * norm;
+        mu[2 * k + 1] = (2.0 * d[2 * k + 1] - d[1]) * norm;
+    }
+    return FD_OK;
+}
+
 fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, double *c, double scalar,
                     void *stream) {
     return stream_op(op, n, a, b, c, scalar, (hipStream_t)stream);
@@ -500,15 +554,19 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     const double t0 = now();
     const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
     const double normH = std::max(std::fabs(lo), std::fabs(hi));
+    if (P->adapt != 0 && P->adapt != 1) return fail(FD_ERR_INVALID, "fd_solve: adapt must be 0 or 1");
     std::vector<double> mu(P->degree + 1);
-    if (P->tau_hi > P->tau_lo) {
-        const double a = std::max(-1.0, std::min(1.0, alpha * P->tau_lo + beta));
-        const double b = std::max(a, std::min(1.0, alpha * P->tau_hi + beta));
-        FD_TRY(cheb_coeffs(0, a, b, P->degree, mu.data()));
-    } else {
-        const double a = std::max(-1.0, std::min(1.0, alpha * P->tau_lo + beta));
-        FD_TRY(cheb_coeffs(1, a, 0.0, P->degree, mu.data()));
-    }
+    // coefficients of the filter for the target window [wlo, whi]
+    auto set_coeffs = [&](double wlo, double whi) -> fd_status {
+        if (whi > wlo) {
+            const double a = std::max(-1.0, std::min(1.0, alpha * wlo + beta));
+            const double b = std::max(a, std::min(1.0, alpha * whi + beta));
+            return cheb_coeffs(0, a, b, P->degree, mu.data());
+        }
+        const double a = std::max(-1.0, std::min(1.0, alpha * wlo + beta));
+        return cheb_coeffs(1, a, 0.0, P->degree, mu.data());
+    };
+    FD_TRY(set_coeffs(P->tau_lo, P->tau_hi));
     hipStream_t s = nullptr;
     // Workspaces: all bundles in one launch when W1/W2 for every bundle fit in
     // 512 MB; otherwise bundle by bundle with nb-wide W1/W2.
@@ -579,12 +637,18 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         }
         if (converged || it >= P->max_iter) break;
         // mixed precision: leave FP32 once the residual is near what an FP32
-        // filter can deliver (1e-5 ||H||), or once it stalls (under 10 %
+        // filter can deliver (1e-6 ||H||), or once it stalls (under 10 %
         // progress per iteration) below 1e-3 ||H||
         if (fp32 && std::isfinite(mx) &&
-            (mx <= 1e-5 * normH || (mx > 0.9 * prev_max && mx < 1e-3 * normH)))
+            (mx <= 1e-6 * normH || (mx > 0.9 * prev_max && mx < 1e-3 * normH)))
             fp32 = false;
         prev_max = mx;
+        if (P->adapt == 1 && P->tau_hi > P->tau_lo && (int)sel.size() == nt) {
+            // target window: tau +- distance of the N_t-th nearest Ritz value
+            const double tau = 0.5 * (P->tau_lo + P->tau_hi);
+            const double r = std::fabs(th[sel.back()] - tau);
+            FD_TRY(set_coeffs(std::max(P->tau_lo, tau - r), std::min(P->tau_hi, tau + r)));
+        }
         double tf = now();
         if (fp32) {
             float *V32d = (float *)V32.p;

@@ -769,6 +769,56 @@ fd_status col_resid(int64_t D, int n, const double *V, const double *W, int64_t 
     return FD_OK;
 }
 
+// ------------------------------------------------------ column dots ----
+namespace {
+__global__ __launch_bounds__(256) void k_coldot_part(int64_t D, int n, const double *__restrict__ A, int64_t lda,
+                                                     const double *__restrict__ B, int64_t ldb, int64_t rpb,
+                                                     double *__restrict__ P) {
+    const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = min(D, r0 + rpb);
+    for (int j = threadIdx.x; j < n; j += 256) {
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; r++) s += A[r * lda + j] * B[r * ldb + j];
+        P[(int64_t)blockIdx.x * n + j] = s;
+    }
+}
+
+__global__ void k_coldot_final(int nblk, int n, const double *P, double *out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) s += P[(int64_t)b * n + j];
+    out[j] = s;
+}
+
+__global__ void k_copy_block(int64_t D, int n, const double *__restrict__ a, int64_t la, double *__restrict__ b,
+                             int64_t lb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D * n) return;
+    const int64_t i = e / n;
+    const int j = (int)(e % n);
+    b[i * lb + j] = a[i * la + j];
+}
+}  // namespace
+
+fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
+                   hipStream_t s) {
+    int64_t rpb = std::max<int64_t>(64, (D + 2047) / 2048);
+    int nblk = (int)((D + rpb - 1) / rpb);
+    double *P = (double *)workspace((size_t)nblk * n * sizeof(double), 2);
+    if (!P) return fail(FD_ERR_OOM, "col_dots: workspace");
+    hipLaunchKernelGGL(k_coldot_part, dim3(nblk), dim3(256), 0, s, D, n, A, lda, B, ldb, rpb, P);
+    FD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_coldot_final, dim3((n + 255) / 256), dim3(256), 0, s, nblk, n, P, out);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_block, dim3((unsigned)((D * n + 255) / 256)), dim3(256), 0, s, D, n, src, lds, dst, ldd);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
 // --------------------------------------------------- element-wise kernels --
 namespace {
 

@@ -103,7 +103,8 @@ namespace fd {
 // -------------------------------------------------------- kernel launchers --
 // Sparse kernels (fd_spmmv.hip).  mode: 0 y = A x; 1 y = a A x + b x;
 // 2 t = a A x + b x - v, y = t, v = cv v + cx x + ct t;
-// 3 t = a A x + b x - z, y = t (y may alias z), v = v + ct t.
+// 3 t = a A x + b x - z, y = t (y may alias z), v = v + ct t;
+// 4 t = a A x + b x - z, y = t (y may alias z).
 struct SpmmvCall {
     int mode = 0;
     int nb = 1;
@@ -143,6 +144,10 @@ fd_status convert_f32_f64(int64_t D, int n, const float *src, int64_t lds, doubl
 fd_status gather_cols(int64_t D, int n, const double *src, int64_t lds, const int *idx,
                       double *dst, int64_t ldd, hipStream_t s);
 fd_status symmetrize(int n, double *H, hipStream_t s);
+// out[off + j] = sum_i A[i][j] B[i][j] for j < n (two-stage, fixed order)
+fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
+                   hipStream_t s);
+fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s);
 fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s);
 
 // Process-wide device workspace for the small dense steps.

@@ -159,13 +159,17 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
                 t -= vi;
                 sts<V, NT>(yr, t);
                 sts<V, NT>(vr, p.cv * vi + p.cx * xi + p.ct * t);
-            } else {
+            } else if constexpr (MODE == 3) {
                 const V zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
                 t -= zi;
                 sts<V, NT>(yr, t);
                 T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
                 V vi = lds<V, NT>(vr);
                 sts<V, NT>(vr, vi + p.ct * t);
+            } else {  // MODE 4: recurrence only (moments of the kernel polynomial method)
+                const V zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+                t -= zi;
+                sts<V, NT>(yr, t);
             }
         }
     }
@@ -235,6 +239,8 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
         case 5: FD_L2(2, true); break;
         case 6: FD_L2(3, false); break;
         case 7: FD_L2(3, true); break;
+        case 8: FD_L2(4, false); break;
+        case 9: FD_L2(4, true); break;
         default: return fail(FD_ERR_INVALID, "SpMMV: bad mode");
     }
 #undef FD_L2

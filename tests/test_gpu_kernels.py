@@ -292,3 +292,25 @@ def test_autotune_keeps_results():
     fd.spmmv(m, X, Y1)
     torch.cuda.synchronize()
     assert torch.equal(Y0, Y1)
+
+
+@pytest.mark.parametrize("name,nb,nmom", [("hub8", 16, 64), ("and13", 8, 32), ("hub7", 1, 10)])
+def test_kpm_moments_parity(name, nb, nmom):
+    m, A = build(name, "csr", 1, 1)
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    R = start_block(A.D, nb, 31)
+    mu = fd.kpm_moments(m, dev(R), nmom, alpha, beta)
+    ref = O.kpm_moments(A, R, nmom, alpha, beta)
+    # doubling vs direct recurrence: equal up to rounding
+    assert np.abs(mu - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_kpm_window_count_exact_basis():
+    A = O.hubbard(6, 3, 3, 1.0, 4.0)
+    lam = np.linalg.eigvalsh(A.dense())
+    m = fd.build_matrix("hubbard", L=6, n_up=3, n_dn=3, t=1.0, U=4.0)
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    mu = fd.kpm_moments(m, dev(np.sqrt(A.D) * np.eye(A.D)), 400, alpha, beta)  # exact trace
+    est = fd.window_count(mu, A.D, alpha * -2.0 + beta, alpha * 2.0 + beta)
+    true = np.sum((lam >= -2.0) & (lam <= 2.0))
+    assert abs(est - true) <= 0.05 * true + 3

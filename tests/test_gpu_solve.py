@@ -137,3 +137,35 @@ def test_solve_errors_and_not_converged():
     assert r.status == fd.FD_ERR_NOT_CONVERGED
     assert r.stats["iters"] == 1 and np.all(np.isfinite(r.evals))
     assert r.stats["spmmv_count"] == 2 * (32 // 8) + 60 * (32 // 8)
+
+
+def test_hubbard8_adaptive_window_vs_dense():
+    A = O.hubbard(8, 4, 4, 1.0, 4.0)
+    ev = dense_spectrum("hub8", A)
+    m = fd.build_matrix("hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0)
+    for prec in (0, 1):
+        r = fd.solve(m, -0.5, 0.5, 16, 128, 16, 100, max_iter=80, tol=1e-9, precision=prec,
+                     V0=start_block(A.D, 128, 0), adapt=1)
+        assert r.status == fd.FD_OK, r.stats
+        check_pairs(A, r, nearest(ev, -0.5, 0.5, 16), r.stats["norm_H"])
+
+
+def test_hubbard10_adaptive_vs_oracle_fd():
+    """Hubbard L=10 (D = 63,504): beyond dense size; against the oracle's FD
+    (tests/golden/hubbard10_fd_oracle.txt, written by make_hubbard10_fd.py),
+    with fresh FP64 residual certificates."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "hubbard10_fd_oracle.txt")
+    want = np.array([float(x) for x in open(path) if x.strip() and not x.startswith("#")])
+    A = O.hubbard(10, 5, 5, 1.0, 8.0)
+    m = fd.build_matrix("hubbard", L=10, n_up=5, n_dn=5, t=1.0, U=8.0)
+    for prec in (0, 1):
+        r = fd.solve(m, -1.0, 1.0, 16, 64, 16, 300, max_iter=60, tol=1e-9, precision=prec,
+                     V0=start_block(A.D, 64, 0), adapt=1)
+        assert r.status == fd.FD_OK, r.stats
+        normH = r.stats["norm_H"]
+        assert np.abs(r.evals - want).max() <= 1e-10 * normH
+        X = r.evecs.cpu().numpy()
+        fresh = np.linalg.norm(O.spmmv(A, X) - X * r.evals, axis=0)
+        assert fresh.max() <= 1e-9 * normH
+        assert np.min(np.abs(r.evals)) < 1e-10 * normH  # the exact E = 0 level

@@ -197,3 +197,17 @@ def test_row_sampled_forms_match_full_oracle():
     mu = O.cheb_coeffs(1, 0.1, 0.0, 4)
     full = O.cheb_filter(A, X, mu, alpha, beta)
     np.testing.assert_allclose(O.cheb_filter_rows(A, X, mu, alpha, beta, rows), full[rows], rtol=0, atol=1e-13)
+
+
+def test_kpm_moments_exact_trace():
+    """With the full unit basis scaled by sqrt(D) (so that the average of r r^t
+    is I, as for N(0,1) vectors) the stochastic trace is exact:
+    mu_k = (1/D) sum_i T_k(alpha lambda_i + beta)."""
+    A = O.hubbard(6, 2, 3, 1.0, 2.0)
+    lam = np.linalg.eigvalsh(A.dense())
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    x = alpha * lam + beta
+    mu = O.kpm_moments(A, np.sqrt(A.D) * np.eye(A.D), 12, alpha, beta)
+    want = [np.mean(np.cos(k * np.arccos(np.clip(x, -1, 1)))) for k in range(12)]
+    np.testing.assert_allclose(mu, want, atol=1e-13)
+    assert abs(mu[0] - 1.0) < 1e-15
