@@ -179,6 +179,44 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R_dev, int64_t l
                          double alpha, double beta, double *W1_dev, double *W2_dev, int64_t ldw,
                          double *mu_host, void *stream);
 
+/* Degree picker network (north of the plain rule): an MLP with FD_MLP_IN
+ * inputs (64 Jackson-damped KPM moments of the scaled matrix, then the scaled
+ * target window [a, b]), three ReLU layers of FD_MLP_HIDDEN and FD_MLP_OUT
+ * outputs (log2 of the degree relative to the KPM rule; log2 of the first
+ * filter window's half-width relative to the rule's), FP32.  Parameters: one
+ * flat array of FD_MLP_NPARAMS floats, per layer W (out x in, row-major) then
+ * b.  All pointers are device pointers; X is B x FD_MLP_IN, outputs B x
+ * FD_MLP_OUT, row-major.                                                   */
+#define FD_MLP_IN 66
+#define FD_MLP_HIDDEN 128
+#define FD_MLP_OUT 2
+#define FD_MLP_NPARAMS (FD_MLP_HIDDEN * FD_MLP_IN + FD_MLP_HIDDEN + 2 * (FD_MLP_HIDDEN * FD_MLP_HIDDEN + FD_MLP_HIDDEN) + \
+                        FD_MLP_OUT * FD_MLP_HIDDEN + FD_MLP_OUT)
+fd_status fd_mlp_forward(const float *params_dev, int32_t B, const float *X_dev, float *out_dev, void *stream);
+/* Gradient of loss = (1/B) sum_i sum_j w_j (out_ij - Y_ij)^2 with respect to
+ * the parameters (G_dev, FD_MLP_NPARAMS floats) and the loss (device float). */
+fd_status fd_mlp_grad(const float *params_dev, int32_t B, const float *X_dev, const float *Y_dev,
+                      const float *w_dev, float *G_dev, float *loss_dev, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * with decoupled weight decay wd (p -= lr wd p) on params with gradient G
+ * and moment arrays M, V (all FD_MLP_NPARAMS).                             */
+fd_status fd_mlp_adam(float *params_dev, const float *G_dev, float *M_dev, float *V_dev, int32_t step,
+                      float lr, float wd, void *stream);
+
+/* Filter degree for fd_solve from KPM moments (16 N(0,1) vectors drawn from
+ * `seed`, 256 moments): the Jackson-damped counting function gives the
+ * radii r_t, r_s around tau = (tau_lo + tau_hi)/2 that hold N_t and N_s
+ * eigenvalues; the rule takes the degree whose Jackson broadening
+ * pi (lam_r - lam_l) / (2 (n + 1)) is half of r_s - r_t (the search margin of
+ * Sec. 2, Fig. 2) and r_t as the first filter window.  With params_dev
+ * (degree-picker parameters) the network's two outputs scale the rule's
+ * degree and window by 2^out (clamped to 2^[-3, 3]); the rule is the
+ * fallback.  degree in [20, 20000].  features_host (FD_MLP_IN floats, may be
+ * NULL) receives the network inputs.  Synchronizes.                        */
+fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_target, int32_t n_search,
+                         const float *params_dev, uint64_t seed, int32_t *degree, double *radius,
+                         float *features_host, void *stream);
+
 /* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
  * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
  * D x nb (allocated and freed here) and keeps the fastest in the handle for
@@ -234,7 +272,7 @@ typedef struct {
     int32_t n_target;      /* N_t                                             */
     int32_t n_search;      /* N_s, a multiple of nb, N_t <= N_s <= 512        */
     int32_t nb;            /* bundle width for the filter and SpMMV           */
-    int32_t degree;        /* filter degree n >= 2                            */
+    int32_t degree;        /* filter degree n >= 2; 0: fd_pick_degree         */
     int32_t max_iter;      /* outer iterations (filter applications)          */
     double tol;            /* converged when rho <= tol * ||H||               */
     int32_t precision;     /* 0: FP64 filter; 1: FP32 filter, FP64 rest       */
@@ -244,6 +282,8 @@ typedef struct {
                               iteration shrink the filter's window around tau
                               to the N_t-th nearest Ritz value in the window
                               (Sec. 2: target interval tracked during FD)   */
+    const float *picker_dev; /* degree 0: degree-picker parameters (device,
+                              FD_MLP_NPARAMS) or NULL for the KPM rule     */
 } fd_solve_params;
 
 typedef struct {
@@ -254,6 +294,7 @@ typedef struct {
     double t_filter, t_orthog, t_rr, t_total; /* seconds                      */
     double norm_H;        /* max(|lam_lo|, |lam_hi|) of the Gershgorin bound  */
     double max_resid;     /* largest rho among the returned pairs             */
+    int32_t degree;       /* filter degree used                               */
 } fd_solve_stats;
 
 /* Plain FD (Alg. 1 caption): Gershgorin inclusion interval, alpha and beta,

@@ -48,14 +48,14 @@ class SolveParams(C.Structure):
     _fields_ = [("tau_lo", C.c_double), ("tau_hi", C.c_double), ("n_target", C.c_int32),
                 ("n_search", C.c_int32), ("nb", C.c_int32), ("degree", C.c_int32),
                 ("max_iter", C.c_int32), ("tol", C.c_double), ("precision", C.c_int32),
-                ("ortho", C.c_int32), ("seed", C.c_uint64), ("adapt", C.c_int32)]
+                ("ortho", C.c_int32), ("seed", C.c_uint64), ("adapt", C.c_int32), ("picker_dev", C.c_void_p)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_conv", C.c_int32), ("iters_fp32", C.c_int32),
                 ("spmmv_count", C.c_int64), ("t_filter", C.c_double), ("t_orthog", C.c_double),
                 ("t_rr", C.c_double), ("t_total", C.c_double), ("norm_H", C.c_double),
-                ("max_resid", C.c_double)]
+                ("max_resid", C.c_double), ("degree", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +85,10 @@ _SIGS = {
     "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
     "fd_autotune": [_P, C.c_int, _I32, _P, _P],
     "fd_kpm_moments": [_P, _I32, _P, _I64, _I32, _D, _D, _P, _P, _I64, _P, _P],
+    "fd_pick_degree": [_P, _D, _D, _I32, _I32, _P, C.c_uint64, C.POINTER(_I32), C.POINTER(_D), _P, _P],
+    "fd_mlp_forward": [_P, _I32, _P, _P, _P],
+    "fd_mlp_grad": [_P, _I32, _P, _P, _P, _P, _P, _P],
+    "fd_mlp_adam": [_P, _P, _P, _P, _I32, C.c_float, C.c_float, _P],
 }
 
 
@@ -300,6 +304,38 @@ def kpm_moments(m: "Matrix", R, nmom: int, alpha: float, beta: float, stream=Non
     return total
 
 
+MLP_IN, MLP_HIDDEN, MLP_OUT = 66, 128, 2
+MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + 2 * (MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN) + MLP_OUT * MLP_HIDDEN + MLP_OUT
+
+
+def pick_degree(m: "Matrix", tau_lo: float, tau_hi: float, n_target: int, n_search: int, picker=None,
+                seed: int = 0):
+    """(degree, first window half-width, network inputs) from fd_pick_degree."""
+    deg = _I32()
+    rad = _D()
+    feat = np.empty(MLP_IN, np.float32)
+    _check(lib().fd_pick_degree(m.handle, tau_lo, tau_hi, n_target, n_search,
+                                C.c_void_p(picker.data_ptr()) if picker is not None else None, seed,
+                                C.byref(deg), C.byref(rad), feat.ctypes.data, _stream(None)))
+    return deg.value, rad.value, feat
+
+
+def mlp_forward(params, X, out, stream=None) -> None:
+    _check(lib().fd_mlp_forward(C.c_void_p(params.data_ptr()), X.shape[0], C.c_void_p(X.data_ptr()),
+                                C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def mlp_grad(params, X, Y, w, G, loss, stream=None) -> None:
+    _check(lib().fd_mlp_grad(C.c_void_p(params.data_ptr()), X.shape[0], C.c_void_p(X.data_ptr()),
+                             C.c_void_p(Y.data_ptr()), C.c_void_p(w.data_ptr()), C.c_void_p(G.data_ptr()),
+                             C.c_void_p(loss.data_ptr()), _stream(stream)))
+
+
+def mlp_adam(params, G, M, V, step: int, lr: float, wd: float = 0.0, stream=None) -> None:
+    _check(lib().fd_mlp_adam(C.c_void_p(params.data_ptr()), C.c_void_p(G.data_ptr()), C.c_void_p(M.data_ptr()),
+                             C.c_void_p(V.data_ptr()), step, lr, wd, _stream(stream)))
+
+
 def window_count(mu_kpm: np.ndarray, D: int, a: float, b: float) -> float:
     """Estimated number of eigenvalues in the scaled window [a, b]:
     D * sum_k c_k g_k mu_k with the Jackson-damped indicator coefficients."""
@@ -356,10 +392,13 @@ class SolveResult:
 def solve(m: Matrix, tau_lo: float, tau_hi: float, n_target: int, n_search: int, nb: int, degree: int,
           max_iter: int = 50, tol: float = 1e-9, precision: int = 0, ortho: int = FD_ORTHO_SVQB2,
           seed: int = 0, V0: np.ndarray | None = None, want_vectors: bool = True,
-          adapt: int = 0) -> SolveResult:
-    """fd_solve; V0 is a host D x n_search float64 array (or None)."""
+          adapt: int = 0, picker=None) -> SolveResult:
+    """fd_solve; V0 is a host D x n_search float64 array (or None).  degree 0
+    picks the degree from KPM moments (picker: GPU float32 parameter tensor
+    of the degree-picker network, or None for the plain rule)."""
     import torch
-    p = SolveParams(tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol, precision, ortho, seed, adapt)
+    p = SolveParams(tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol, precision, ortho, seed, adapt,
+                    C.c_void_p(picker.data_ptr()) if picker is not None else None)
     ev = np.full(n_target, np.nan)
     rs = np.full(n_target, np.nan)
     vecs = torch.empty((m.D, n_target), dtype=torch.float64, device="cuda") if want_vectors else None

@@ -277,6 +277,31 @@ std::vector<int> select_targets(const std::vector<double> &th, double lo, double
     return idx;
 }
 
+// KPM counting function: estimated number of eigenvalues in tau +- r
+double kpm_count(const std::vector<double> &mu, int64_t D, double alpha, double beta, double lo, double hi) {
+    const int M = (int)mu.size();
+    std::vector<double> c(M);
+    const double a = std::max(-1.0, std::min(1.0, alpha * lo + beta));
+    const double b = std::max(a, std::min(1.0, alpha * hi + beta));
+    if (cheb_coeffs(0, a, b, M - 1, c.data()) != FD_OK) return 0.0;
+    double n = 0.0;
+    for (int k = 0; k < M; k++) n += c[k] * mu[k];
+    return n * (double)D;
+}
+
+// smallest radius r (bisection) with count(tau +- r, clipped to [lo, hi]) >= want
+double kpm_radius(const std::vector<double> &mu, int64_t D, double alpha, double beta, double tau, double lo,
+                  double hi, double want) {
+    double r0 = 0.0, r1 = std::max(tau - lo, hi - tau);
+    if (kpm_count(mu, D, alpha, beta, lo, hi) < want) return r1;
+    for (int it = 0; it < 60; it++) {
+        const double r = 0.5 * (r0 + r1);
+        if (kpm_count(mu, D, alpha, beta, std::max(lo, tau - r), std::min(hi, tau + r)) >= want) r1 = r;
+        else r0 = r;
+    }
+    return r1;
+}
+
 struct DevBuf {
     void *p = nullptr;
     ~DevBuf() {
@@ -496,6 +521,76 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R, int64_t ldr, 
     return FD_OK;
 }
 
+fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t nt, int32_t ns, const float *params,
+                         uint64_t seed, int32_t *degree, double *radius, float *features, void *stream) {
+    FD_TRY(need_device(m));
+    const double lo = m->lam_lo, hi = m->lam_hi;
+    if (!degree || nt < 1 || ns < nt || !(tau_lo <= tau_hi) || tau_lo < lo || tau_hi > hi || !(hi > lo))
+        return fail(FD_ERR_INVALID, "fd_pick_degree: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t D = m->dev.D;
+    const int R = 16, M = 256;
+    const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
+    DevBuf blk;
+    FD_TRY(blk.alloc((size_t)D * R * 8 * 3, "KPM blocks"));
+    double *Rv = (double *)blk.p, *W1 = Rv + (size_t)D * R, *W2 = W1 + (size_t)D * R;
+    FD_TRY(fill_normal(D, R, Rv, R, seed, s));
+    std::vector<double> mu(M);
+    FD_TRY(fd_kpm_moments(m, R, Rv, R, M, alpha, beta, W1, W2, R, mu.data(), s));
+    // counting function D sum_k g_k c_k mu_k: the window coefficients carry
+    // the Jackson factors g_k already
+    const std::vector<double> &dm = mu;
+    const double tau = 0.5 * (tau_lo + tau_hi);
+    const double wlo = tau_hi > tau_lo ? tau_lo : lo, whi = tau_hi > tau_lo ? tau_hi : hi;
+    const double rt = kpm_radius(dm, D, alpha, beta, tau, wlo, whi, nt);
+    const double rs = kpm_radius(dm, D, alpha, beta, tau, lo, hi, ns);
+    // Jackson broadening pi (lam_r - lam_l) / (2 (n + 1)) about half the gap
+    // between the N_t-th and the N_s-th nearest eigenvalue
+    const double gap = std::max(rs - rt, 1e-12 * (hi - lo));
+    double n = std::ceil(2.0 * M_PI * (hi - lo) / (2.0 * gap));
+    double r = rt;
+    if (features || params) {
+        std::vector<float> f(FD_MLP_IN);
+        std::vector<double> g64(64);  // (2 - delta_k0) g_k T_k(1), Jackson for 64 moments
+        FD_TRY(cheb_coeffs(1, 1.0, 0.0, 63, g64.data()));
+        for (int k = 0; k < 64; k++) f[k] = (float)(mu[k] * g64[k] / (k == 0 ? 1.0 : 2.0));
+        f[64] = (float)(alpha * tau_lo + beta);
+        f[65] = (float)(alpha * tau_hi + beta);
+        if (features) std::copy(f.begin(), f.end(), features);
+        if (params) {
+            DevBuf io;
+            FD_TRY(io.alloc((FD_MLP_IN + FD_MLP_OUT) * sizeof(float), "picker input"));
+            float *xin = (float *)io.p, *yout = xin + FD_MLP_IN;
+            FD_HIP(hipMemcpyAsync(xin, f.data(), FD_MLP_IN * sizeof(float), hipMemcpyHostToDevice, s));
+            FD_TRY(mlp_forward(params, 1, xin, yout, s));
+            float o[FD_MLP_OUT];
+            FD_HIP(hipMemcpyAsync(o, yout, sizeof(o), hipMemcpyDeviceToHost, s));
+            FD_HIP(hipStreamSynchronize(s));
+            if (std::isfinite(o[0]) && std::isfinite(o[1])) {  // else keep the rule
+                n *= std::exp2(std::max(-3.0f, std::min(3.0f, o[0])));
+                r *= std::exp2(std::max(-3.0f, std::min(3.0f, o[1])));
+            }
+        }
+    }
+    *degree = (int32_t)std::max(20.0, std::min(20000.0, n));
+    if (radius) *radius = r;
+    return FD_OK;
+}
+
+fd_status fd_mlp_forward(const float *P, int32_t B, const float *X, float *out, void *stream) {
+    return mlp_forward(P, B, X, out, (hipStream_t)stream);
+}
+
+fd_status fd_mlp_grad(const float *P, int32_t B, const float *X, const float *Y, const float *w, float *G,
+                      float *loss, void *stream) {
+    return mlp_grad(P, B, X, Y, w, G, loss, (hipStream_t)stream);
+}
+
+fd_status fd_mlp_adam(float *P, const float *G, float *M, float *V, int32_t step, float lr, float wd,
+                      void *stream) {
+    return mlp_adam(P, G, M, V, step, lr, wd, (hipStream_t)stream);
+}
+
 fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, double *c, double scalar,
                     void *stream) {
     return stream_op(op, n, a, b, c, scalar, (hipStream_t)stream);
@@ -542,7 +637,7 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     const int nb = P->nb, ns = P->n_search, nt = P->n_target;
     if (!nb_ok(nb) || ns < nb || ns % nb || ns > 512 || nt < 1 || nt > ns)
         return fail(FD_ERR_INVALID, "fd_solve: need nb in {1..64}, N_s a multiple of nb, N_t <= N_s <= 512");
-    if (P->degree < 2) return fail(FD_ERR_INVALID, "fd_solve: degree must be >= 2");
+    if (P->degree < 2 && P->degree != 0) return fail(FD_ERR_INVALID, "fd_solve: degree must be >= 2 (or 0)");
     if (P->max_iter < 0 || !(P->tol > 0)) return fail(FD_ERR_INVALID, "fd_solve: bad max_iter or tol");
     if (P->precision != 0 && P->precision != 1) return fail(FD_ERR_INVALID, "fd_solve: precision must be 0 or 1");
     const double lo = m->lam_lo, hi = m->lam_hi;
@@ -555,18 +650,28 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
     const double normH = std::max(std::fabs(lo), std::fabs(hi));
     if (P->adapt != 0 && P->adapt != 1) return fail(FD_ERR_INVALID, "fd_solve: adapt must be 0 or 1");
-    std::vector<double> mu(P->degree + 1);
+    int degree = P->degree;
+    double r0 = -1.0;
+    if (degree == 0)
+        FD_TRY(fd_pick_degree(m, P->tau_lo, P->tau_hi, nt, ns, P->picker_dev, P->seed ^ 0x5EEDULL, &degree, &r0,
+                              nullptr, nullptr));
+    std::vector<double> mu(degree + 1);
     // coefficients of the filter for the target window [wlo, whi]
     auto set_coeffs = [&](double wlo, double whi) -> fd_status {
         if (whi > wlo) {
             const double a = std::max(-1.0, std::min(1.0, alpha * wlo + beta));
             const double b = std::max(a, std::min(1.0, alpha * whi + beta));
-            return cheb_coeffs(0, a, b, P->degree, mu.data());
+            return cheb_coeffs(0, a, b, degree, mu.data());
         }
         const double a = std::max(-1.0, std::min(1.0, alpha * wlo + beta));
-        return cheb_coeffs(1, a, 0.0, P->degree, mu.data());
+        return cheb_coeffs(1, a, 0.0, degree, mu.data());
     };
-    FD_TRY(set_coeffs(P->tau_lo, P->tau_hi));
+    if (r0 > 0.0 && P->tau_hi > P->tau_lo) {
+        const double tau = 0.5 * (P->tau_lo + P->tau_hi);
+        FD_TRY(set_coeffs(std::max(P->tau_lo, tau - r0), std::min(P->tau_hi, tau + r0)));
+    } else {
+        FD_TRY(set_coeffs(P->tau_lo, P->tau_hi));
+    }
     hipStream_t s = nullptr;
     // Workspaces: all bundles in one launch when W1/W2 for every bundle fit in
     // 512 MB; otherwise bundle by bundle with nb-wide W1/W2.
@@ -596,6 +701,7 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     fd_solve_stats st;
     std::memset(&st, 0, sizeof(st));
     st.norm_H = normH;
+    st.degree = degree;
     bool fp32 = P->precision == 1;
     // FD_TRACE=1: one JSON line per outer iteration on stderr
     const char *tr = std::getenv("FD_TRACE");
@@ -653,17 +759,17 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         if (fp32) {
             float *V32d = (float *)V32.p;
             FD_TRY(convert_f64_f32(D, ns, Vd, ns, V32d, ns, s));
-            FD_TRY(cheb_filter_impl(m, FD_F32, nb, ns / nb, V32d, ns, mu.data(), P->degree, alpha, beta, W1.p,
+            FD_TRY(cheb_filter_impl(m, FD_F32, nb, ns / nb, V32d, ns, mu.data(), degree, alpha, beta, W1.p,
                                     W2.p, ldw, s));
             FD_TRY(convert_f32_f64(D, ns, V32d, ns, Vd, ns, s));
             st.iters_fp32++;
         } else {
-            FD_TRY(cheb_filter_impl(m, FD_F64, nb, ns / nb, Vd, ns, mu.data(), P->degree, alpha, beta, W1.p,
+            FD_TRY(cheb_filter_impl(m, FD_F64, nb, ns / nb, Vd, ns, mu.data(), degree, alpha, beta, W1.p,
                                     W2.p, ldw, s));
         }
         FD_HIP(hipStreamSynchronize(s));
         st.t_filter += now() - tf;
-        st.spmmv_count += (int64_t)P->degree * (ns / nb);
+        st.spmmv_count += (int64_t)degree * (ns / nb);
         it++;
     }
     st.iters = it;

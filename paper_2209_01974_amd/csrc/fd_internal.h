@@ -150,6 +150,12 @@ fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double 
 fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s);
 fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s);
 
+// Degree-picker network (fd_mlp.hip).
+fd_status mlp_forward(const float *P, int B, const float *X, float *out, hipStream_t s);
+fd_status mlp_grad(const float *P, int B, const float *X, const float *Y, const float *wj, float *G,
+                   float *loss_dev, hipStream_t s);
+fd_status mlp_adam(float *P, const float *G, float *M, float *V, int step, float lr, float wd, hipStream_t s);
+
 // Process-wide device workspace for the small dense steps.
 void *workspace(size_t bytes, int slot);
 

@@ -1,0 +1,230 @@
+"""Degree picker: data from the solver's own FD runs, training on the GPU with
+libfd's MLP kernels (fd_mlp_grad / fd_mlp_adam), and evaluation against the
+plain KPM rule of fd_pick_degree, which stays the fallback.
+
+  python -m paper_2209_01974_amd.picker gen   --n 200 --out DATA.npz
+  python -m paper_2209_01974_amd.picker train --data DATA.npz --out PARAMS.npy
+  python -m paper_2209_01974_amd.picker eval  --params PARAMS.npy --n 16
+
+Instances: Hubbard rings (L = 8, 10, half filling, U in [2, 10]) and 3D
+Anderson lattices (L in [10, 22], W in [2, 20]); target: the N_t = 8
+eigenpairs nearest tau inside [tau - 1, tau + 1], N_s = 32, nb = 16, FP64,
+residual 1e-9 ||H||, target window tracked during the iteration.  Labels:
+log2 of the degree factor (relative to the rule) with the fewest SpMMVs to
+convergence over a sweep, and log2 of the true N_t-th distance over the
+rule's estimate.  Evaluation instances are larger (Hubbard L = 12, Anderson
+L in [32, 48]) and not seen in training.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import FD_OK, MLP_NPARAMS, build_matrix, mlp_adam, mlp_forward, mlp_grad, pick_degree, solve
+
+FACTORS = np.array([0.5, 0.71, 1.0, 1.41, 2.0])
+NT, NS, NB = 8, 32, 16
+
+
+def log(*a):
+    print("[picker]", *a, file=sys.stderr, flush=True)
+
+
+def sample(rng, big: bool):
+    if rng.uniform() < 0.5:
+        L = 12 if big else int(rng.choice([8, 10]))
+        kw = dict(model="hubbard", L=L, n_up=L // 2, n_dn=L // 2, t=1.0, U=float(rng.uniform(2.0, 10.0)))
+    else:
+        L = int(rng.integers(32, 49)) if big else int(rng.integers(10, 23))
+        kw = dict(model="anderson", L=L, t=1.0, W=float(rng.uniform(2.0, 20.0)), seed=int(rng.integers(1, 2**31)))
+    return kw
+
+
+def instance(rng, big: bool, max_degree: int):
+    """A matrix and a target window whose rule degree stays below max_degree."""
+    for _ in range(20):
+        kw = sample(rng, big)
+        m = build_matrix(**kw)
+        lo, hi = m.lam_lo, m.lam_hi
+        for _ in range(6):
+            tau = float(rng.uniform(lo + 0.15 * (hi - lo), hi - 0.15 * (hi - lo)))
+            wl, wh = max(lo, tau - 1.0), min(hi, tau + 1.0)
+            deg, r0, feat = pick_degree(m, wl, wh, NT, NS, seed=11)
+            # a valid problem: the window holds at least 2 N_t eigenvalues
+            # (KPM count from the same moments the features come from)
+            if deg <= max_degree and window_count_from_features(feat, m.D) >= 2 * NT:
+                return kw, m, (wl, wh), deg, r0, feat
+    raise RuntimeError("no instance found")
+
+
+def window_count_from_features(feat, D: int) -> float:
+    """KPM estimate of the eigenvalue count in the scaled window [a, b] = feat[64:66]
+    from the 64 Jackson-damped moments feat[:64] (g_k mu_k)."""
+    a, b = float(feat[64]), float(feat[65])
+    k = np.arange(64)
+    ta, tb = np.arccos(np.clip(a, -1, 1)), np.arccos(np.clip(b, -1, 1))
+    c = np.where(k == 0, (ta - tb) / np.pi, 2.0 * (np.sin(k * ta) - np.sin(k * tb)) / (np.maximum(k, 1) * np.pi))
+    return float(D * np.dot(c, feat[:64].astype(np.float64)))
+
+
+def run(m, win, degree, picker=None, max_iter=30):
+    r = solve(m, win[0], win[1], NT, NS, NB, degree, max_iter=max_iter, tol=1e-9, precision=0, seed=3,
+              want_vectors=False, adapt=1, picker=picker)
+    return r
+
+
+def gen(n: int, out: str, seed: int):
+    rng = np.random.default_rng(seed)
+    rows = []
+    t0 = time.time()
+    for k in range(n):
+        kw, m, win, deg, r0, feat = instance(rng, False, 2500)
+        tau = 0.5 * (win[0] + win[1])
+        res = []
+        for f in FACTORS:
+            r = run(m, win, max(20, int(round(f * deg))))
+            ok = r.status == FD_OK
+            res.append((ok, r.stats["spmmv_count"], r.stats["t_total"], r.evals))
+        okk = [i for i, x in enumerate(res) if x[0]]
+        if not okk:
+            log("instance %d %s: no degree converged" % (k, kw))
+            continue
+        best = min(okk, key=lambda i: (res[i][1], i))
+        rtrue = float(np.max(np.abs(res[best][3] - tau)))
+        rows.append(dict(x=feat.tolist(), y=[float(np.log2(FACTORS[best])), float(np.log2(max(rtrue, 1e-6) / r0))],
+                         kw=kw, win=win, rule_degree=deg, r0=r0, spmmv=[x[1] for x in res],
+                         ok=[bool(x[0]) for x in res], t=[x[2] for x in res]))
+        log("instance %d/%d (%.0fs): %s deg %d best factor %.2f spmmv %s" %
+            (k + 1, n, time.time() - t0, kw["model"], deg, FACTORS[best], [x[1] for x in res]))
+        if (k + 1) % 20 == 0 or k + 1 == n:
+            np.savez(out, X=np.array([r["x"] for r in rows], np.float32), Y=np.array([r["y"] for r in rows], np.float32),
+                     meta=json.dumps(rows))
+
+
+DIMS = [66, 128, 128, 128, 2]
+
+
+def degree_label(spmmv, ok) -> float:
+    """log2 of the degree factor at the minimum of a parabola fitted to
+    log(SpMMVs to convergence) over log2(factor) (runs that did not converge
+    count as twice the worst converged one), clipped to the swept range."""
+    x = np.log2(FACTORS)
+    c = np.array(spmmv, float)
+    okm = np.array(ok, bool)
+    c = np.where(okm, c, 2.0 * c[okm].max())
+    a2, a1, _ = np.polyfit(x, np.log(c), 2)
+    if a2 > 0:
+        return float(np.clip(-a1 / (2 * a2), x[0], x[-1]))
+    return float(x[int(np.argmin(c))])
+
+
+def load_data(paths: str):
+    """Features and labels from one or more files written by gen (comma list)."""
+    X, Y = [], []
+    for path in paths.split(","):
+        z = np.load(path)
+        for row in json.loads(str(z["meta"])):
+            X.append(row["x"])
+            Y.append([degree_label(row["spmmv"], row["ok"]), row["y"][1]])
+    return np.array(X, np.float32), np.array(Y, np.float32)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal hidden weights, zero biases and a zero output layer: the
+    untrained network outputs 0, i.e. reproduces the plain rule."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k in range(4):
+        W = rng.standard_normal((DIMS[k + 1], DIMS[k])) * np.sqrt(2.0 / DIMS[k])
+        if k == 3:
+            W[:] = 0.0
+        parts += [W.ravel(), np.zeros(DIMS[k + 1])]
+    return np.concatenate(parts)
+
+
+def train(data: str, out: str, steps: int, lr: float, seed: int, wd: float = 1e-2):
+    import torch
+
+    X, Y = load_data(data)
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    nv = max(1, n // 5)
+    va, tr = perm[:nv], perm[nv:]
+    p0 = init_params(seed).astype(np.float32)
+    assert p0.size == MLP_NPARAMS
+    P = torch.from_numpy(p0).cuda()
+    G, M, V = torch.zeros_like(P), torch.zeros_like(P), torch.zeros_like(P)
+    w = torch.tensor([1.0, 0.5], dtype=torch.float32, device="cuda")
+    Xt, Yt = torch.from_numpy(X[tr]).cuda(), torch.from_numpy(Y[tr]).cuda()
+    Xv, Yv = torch.from_numpy(X[va]).cuda(), torch.from_numpy(Y[va]).cuda()
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    Gv = torch.empty_like(P)
+    best, best_p = None, None
+    for s in range(1, steps + 1):
+        mlp_grad(P, Xt, Yt, w, G, loss)
+        mlp_adam(P, G, M, V, s, lr, wd)
+        if s % 50 == 0 or s == steps:
+            mlp_grad(P, Xv, Yv, w, Gv, loss)
+            lv = float(loss.item())
+            if best is None or lv < best:
+                best, best_p = lv, P.clone()
+            if s % 500 == 0 or s == steps:
+                log("step %d: validation loss %.4f (best %.4f)" % (s, lv, best))
+    base = float(np.mean(np.sum(np.array([1.0, 0.5]) * Y[va] ** 2, axis=1)))
+    log("validation loss: network %.4f, plain rule (all-zero output) %.4f" % (best, base))
+    np.save(out, best_p.cpu().numpy())
+    return best, base
+
+
+def evaluate(params: str, n: int, seed: int):
+    import torch
+    P = torch.from_numpy(np.load(params).astype(np.float32)).cuda()
+    rng = np.random.default_rng(seed)
+    rows = []
+    for k in range(n):
+        kw, m, win, deg, r0, feat = instance(rng, True, 6000)
+        rr = run(m, win, 0, None, 40)
+        rp = run(m, win, 0, P, 40)
+        row = dict(model=kw["model"], L=kw["L"], D=m.D, rule=dict(ok=rr.status == FD_OK, degree=rr.stats["degree"],
+                   spmmv=rr.stats["spmmv_count"], t=rr.stats["t_total"], resid=rr.stats["max_resid"] / rr.stats["norm_H"]),
+                   picker=dict(ok=rp.status == FD_OK, degree=rp.stats["degree"], spmmv=rp.stats["spmmv_count"],
+                               t=rp.stats["t_total"], resid=rp.stats["max_resid"] / rp.stats["norm_H"]))
+        rows.append(row)
+        log("eval %d/%d %s L=%d: rule %s | picker %s" % (k + 1, n, kw["model"], kw["L"], row["rule"], row["picker"]))
+    both = [r for r in rows if r["rule"]["ok"] and r["picker"]["ok"]]
+    summary = dict(instances=n, rule_converged=sum(r["rule"]["ok"] for r in rows),
+                   picker_converged=sum(r["picker"]["ok"] for r in rows),
+                   spmmv_rule=int(sum(r["rule"]["spmmv"] for r in both)),
+                   spmmv_picker=int(sum(r["picker"]["spmmv"] for r in both)),
+                   t_rule=float(sum(r["rule"]["t"] for r in both)), t_picker=float(sum(r["picker"]["t"] for r in both)))
+    print(json.dumps(dict(summary=summary, rows=rows)), flush=True)
+    return summary
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["gen", "train", "eval"])
+    ap.add_argument("--n", type=int, default=200)
+    ap.add_argument("--out", default="picker_data.npz")
+    ap.add_argument("--data", default="picker_data.npz")
+    ap.add_argument("--params", default="picker_params.npy")
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--wd", type=float, default=1e-2)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args()
+    if a.cmd == "gen":
+        gen(a.n, a.out, a.seed)
+    elif a.cmd == "train":
+        train(a.data, a.out, a.steps, a.lr, a.seed, a.wd)
+    else:
+        evaluate(a.params, a.n, a.seed + 1000)
+
+
+if __name__ == "__main__":
+    main()

@@ -314,3 +314,55 @@ def test_kpm_window_count_exact_basis():
     est = fd.window_count(mu, A.D, alpha * -2.0 + beta, alpha * 2.0 + beta)
     true = np.sum((lam >= -2.0) & (lam <= 2.0))
     assert abs(est - true) <= 0.05 * true + 3
+
+
+def test_mlp_forward_and_gradient_vs_oracle():
+    from oracle import mlp
+    rng = np.random.default_rng(7)
+    p = mlp.init(2, out_scale=0.5)
+    X = rng.uniform(-1, 1, (37, 66))
+    Y = rng.standard_normal((37, 2))
+    w = np.array([1.0, 0.3])
+    P = torch.from_numpy(p.astype(np.float32)).cuda()
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    out = torch.empty((37, 2), dtype=torch.float32, device="cuda")
+    fd.mlp_forward(P, Xd, out)
+    ref, _, _ = mlp.forward(p.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    G = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    fd.mlp_grad(P, Xd, torch.from_numpy(Y.astype(np.float32)).cuda(), torch.from_numpy(w.astype(np.float32)).cuda(),
+                G, loss)
+    lref, gref = mlp.loss_and_grad(p.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64),
+                                   Y.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64))
+    assert abs(float(loss.item()) - lref) <= 1e-4 * max(1.0, lref)
+    gn = G.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gn - gref) <= 1e-3 * np.linalg.norm(gref)
+
+
+def test_mlp_adam_step_matches_formula():
+    n = 41858
+    rng = np.random.default_rng(1)
+    p0 = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    P, G = torch.from_numpy(p0.copy()).cuda(), torch.from_numpy(g).cuda()
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    fd.mlp_adam(P, G, M, V, 1, 1e-2, 0.1)
+    m1 = 0.1 * g
+    v1 = 0.001 * g * g
+    want = p0 - 1e-2 * ((m1 / 0.1) / (np.sqrt(v1 / 0.001) + 1e-8) + 0.1 * p0)
+    np.testing.assert_allclose(P.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
+
+
+def test_pick_degree_rule_hubbard8():
+    """The KPM rule's radii bracket the dense N_t-th and N_s-th nearest
+    eigenvalue distances, and fd_solve with degree 0 converges."""
+    A = O.hubbard(8, 4, 4, 1.0, 4.0)
+    ev = np.sort(np.abs(np.linalg.eigvalsh(A.dense())))
+    m = fd.build_matrix("hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0)
+    deg, r, feat = fd.pick_degree(m, -0.5, 0.5, 16, 128, seed=1)
+    assert 20 <= deg <= 20000 and feat.shape == (66,)
+    assert 0.5 * ev[15] <= r <= 2.0 * ev[15] + 0.1
+    res = fd.solve(m, -0.5, 0.5, 16, 128, 16, 0, max_iter=80, tol=1e-9, V0=start_block(A.D, 128, 0), adapt=1)
+    assert res.status == fd.FD_OK
+    assert 0.7 * deg <= res.stats["degree"] <= 1.4 * deg  # its own KPM draw

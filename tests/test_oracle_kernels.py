@@ -211,3 +211,21 @@ def test_kpm_moments_exact_trace():
     want = [np.mean(np.cos(k * np.arccos(np.clip(x, -1, 1)))) for k in range(12)]
     np.testing.assert_allclose(mu, want, atol=1e-13)
     assert abs(mu[0] - 1.0) < 1e-15
+
+
+def test_mlp_oracle_gradient_by_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    p = mlp.init(1, out_scale=1.0)
+    X = rng.uniform(-1, 1, (6, 66))
+    Y = rng.standard_normal((6, 2))
+    w = np.array([1.0, 0.5])
+    loss, g = mlp.loss_and_grad(p, X, Y, w)
+    idx = rng.choice(p.size, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        num = (mlp.loss_and_grad(p + e, X, Y, w)[0] - mlp.loss_and_grad(p - e, X, Y, w)[0]) / (2 * h)
+        assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
+    assert p.size == 41858
