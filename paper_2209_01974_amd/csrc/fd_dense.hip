@@ -886,12 +886,27 @@ __global__ void k_symmetrize(int n, double *H) {
 
 unsigned nblocks(int64_t tot) { return (unsigned)((tot + 255) / 256); }
 
-// STREAM-style kernels (the paper measures b_m with STREAM): 16-byte loads,
-// non-temporal stores, grid-stride over n/2 pairs of doubles.
+// STREAM-style kernels (the paper measures b_m with STREAM): 16-byte
+// non-temporal loads and stores, four per thread in flight, grid-stride over
+// n/2 pairs of doubles (a probe of copy variants on MI355X found this shape
+// fastest).
 typedef double d2v __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void k_stream(int op, int64_t n2, const d2v *__restrict__ a,
                                                 const d2v *__restrict__ b, d2v *__restrict__ c, double sc) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (int64_t)gridDim.x * 256) {
+    const int64_t stride = (int64_t)gridDim.x * 256 * 4;
+    int64_t i = (int64_t)blockIdx.x * 256 * 4 + threadIdx.x;
+    for (; i + 3 * 256 < n2; i += stride) {
+        d2v r[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) r[u] = __builtin_nontemporal_load(a + i + u * 256);
+        if (op == 1) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) r[u] += sc * __builtin_nontemporal_load(b + i + u * 256);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) __builtin_nontemporal_store(r[u], c + i + u * 256);
+    }
+    for (; i < n2; i += 256) {  // tail: the remaining elements of this block's last tile
         d2v r = __builtin_nontemporal_load(a + i);
         if (op == 1) r += sc * __builtin_nontemporal_load(b + i);
         __builtin_nontemporal_store(r, c + i);
@@ -905,7 +920,7 @@ fd_status stream_op(int op, int64_t n, const double *a, const double *b, double 
         ((uintptr_t)a | (uintptr_t)c | (uintptr_t)b) % 16)
         return fail(FD_ERR_INVALID, "stream: need even n, 16-byte aligned arrays, op 0 or 1");
     const int64_t n2 = n / 2;
-    const int64_t g = std::min<int64_t>((n2 + 255) / 256, 256 * 32);
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((n2 + 1023) / 1024, 16384));
     hipLaunchKernelGGL(k_stream, dim3((unsigned)g), dim3(256), 0, s, op, n2, (const d2v *)a, (const d2v *)b,
                        (d2v *)c, sc);
     FD_HIP(hipGetLastError());

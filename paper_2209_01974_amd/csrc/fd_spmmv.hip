@@ -120,6 +120,14 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
         const uint32_t base = p0 + (uint32_t)(s & (step - 1));
         const int64_t row = PERM ? (int64_t)p.perm[s] : s;
         if (row < 0) continue;  // padding slot past D
+        // streamed operands first: their latency overlaps the gather chain
+        V zi = (V)0, vi = (V)0;
+        T *vr = nullptr;
+        if constexpr (MODE >= 2) {
+            vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
+            if constexpr (MODE == 3 || MODE == 4) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+            if constexpr (MODE == 2 || MODE == 3) vi = lds<V, NT>(vr);
+        }
         const T *xq = x + q * VEC;
         V acc0 = (V)0, acc1 = (V)0;
         uint32_t j = 0;
@@ -154,20 +162,14 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             if constexpr (MODE == 1) {
                 sts<V, NT>(yr, t);
             } else if constexpr (MODE == 2) {
-                T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
-                V vi = lds<V, NT>(vr);
                 t -= vi;
                 sts<V, NT>(yr, t);
                 sts<V, NT>(vr, p.cv * vi + p.cx * xi + p.ct * t);
             } else if constexpr (MODE == 3) {
-                const V zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
                 t -= zi;
                 sts<V, NT>(yr, t);
-                T *vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
-                V vi = lds<V, NT>(vr);
                 sts<V, NT>(vr, vi + p.ct * t);
             } else {  // MODE 4: recurrence only (moments of the kernel polynomial method)
-                const V zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
                 t -= zi;
                 sts<V, NT>(yr, t);
             }

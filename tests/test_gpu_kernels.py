@@ -244,8 +244,8 @@ def test_rayleigh_ritz_parity(name, nb, ns):
     assert np.abs(fresh - rho).max() <= 1e-11 * normH
 
 
-def test_stream_kernels_exact():
-    n = 1 << 20
+@pytest.mark.parametrize("n", [1 << 20, (1 << 20) + 6, 2050])
+def test_stream_kernels_exact(n):
     a = torch.arange(n, dtype=torch.float64, device="cuda")
     b = torch.full((n,), 3.0, dtype=torch.float64, device="cuda")
     c = torch.empty_like(a)
