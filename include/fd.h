@@ -221,7 +221,8 @@ fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_ta
  * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
  * D x nb (allocated and freed here) and keeps the fastest in the handle for
  * (dtype, nb); later calls on this matrix use it.  shape (5 ints, may be
- * NULL) receives order, xcd, iters, grid, nontemporal.  Synchronizes.      */
+ * NULL) receives order, xcd, iters, grid, nontemporal, wide (6 ints).
+ * Synchronizes.                                                            */
 fd_status fd_autotune(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
 
 /* STREAM-style bandwidth kernels on device arrays of n doubles (n even,
@@ -241,10 +242,12 @@ int32_t fd_syev_last_sweeps(void);
  * (0 = automatic).  xcd 1: every XCD owns a contiguous eighth of the rows;
  * xcd 2 (order 0 only): XCD x owns the row chunks x, x+8, x+16, ... of
  * `grid` rows each (0 = 1024).  nontemporal != 0: operands that are streamed
- * once bypass the caches.  Default: order 0, xcd 2, iters 1, grid 1024,
- * nontemporal 1.  A shape chosen by fd_autotune for a matrix takes
- * precedence for that matrix.                                              */
-fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal);
+ * once bypass the caches.  wide != 0 (nb >= 16): each lane owns 32 bytes of
+ * a row (two 16-byte loads per gathered row) instead of 16.  Default:
+ * order 0, xcd 2, iters 1, grid 1024, nontemporal 1, wide 0.  A shape chosen
+ * by fd_autotune for a matrix takes precedence for that matrix.            */
+fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal,
+                        int32_t wide);
 
 #define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */
 #define FD_ORTHO_CHOLQR2 1 /* two Cholesky-QR passes, SVQB2 if one fails    */

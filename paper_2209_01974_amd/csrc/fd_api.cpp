@@ -463,6 +463,7 @@ fd_status fd_autotune(fd_matrix m, fd_dtype dt, int32_t nb, int32_t *shape, void
         shape[2] = t.iters;
         shape[3] = t.grid;
         shape[4] = t.nontemporal;
+        shape[5] = t.wide;
     }
     return FD_OK;
 }
@@ -596,7 +597,7 @@ fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, dou
     return stream_op(op, n, a, b, c, scalar, (hipStream_t)stream);
 }
 
-fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal) {
+fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal, int32_t wide) {
     if (order < 0 || order > 1 || xcd < 0 || xcd > 2 || (order == 1 && xcd == 2) || iters < 0 || grid < 0 ||
         grid > (1 << 24))
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
@@ -606,6 +607,7 @@ fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid,
     t.iters = iters;
     t.grid = grid;
     t.nontemporal = nontemporal != 0;
+    t.wide = wide != 0;
     return FD_OK;
 }
 

@@ -66,6 +66,7 @@ struct SpmmvTune {
     int iters = 1;        // order 0: row groups per block (0: automatic)
     int grid = 1024;      // order 1: blocks per bundle; xcd 2: rows per chunk
     int nontemporal = 1;  // 1: streamed operands bypass the caches
+    int wide = 0;         // 1: 32 bytes per lane (nb >= 16)
 };
 
 // One layout serves CSR and SELL: "slot" s of the device format belongs to

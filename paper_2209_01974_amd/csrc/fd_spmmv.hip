@@ -30,6 +30,8 @@ template <> struct VecT<double, 2> { typedef double __attribute__((ext_vector_ty
 template <> struct VecT<float, 1> { typedef float type; };
 template <> struct VecT<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
 template <> struct VecT<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VecT<double, 4> { typedef double __attribute__((ext_vector_type(4))) type; };
+template <> struct VecT<float, 8> { typedef float __attribute__((ext_vector_type(8))) type; };
 
 template <typename T>
 struct KArgs {
@@ -271,8 +273,9 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     FD_HIP(hipEventCreate(&e0));
     FD_HIP(hipEventCreate(&e1));
     const SpmmvTune cands[] = {
-        {0, 2, 1, 512, 1}, {0, 2, 1, 1024, 1}, {0, 2, 1, 2048, 1}, {0, 2, 1, 8192, 1},
-        {0, 2, 2, 2048, 1}, {0, 0, 1, 0, 1},   {0, 1, 1, 0, 1},    {1, 1, 1, 4096, 1},
+        {0, 2, 1, 512, 1, 0}, {0, 2, 1, 1024, 1, 0}, {0, 2, 1, 2048, 1, 0}, {0, 2, 1, 8192, 1, 0},
+        {0, 2, 2, 2048, 1, 0}, {0, 0, 1, 0, 1, 0},   {0, 1, 1, 0, 1, 0},    {1, 1, 1, 4096, 1, 0},
+        {0, 2, 1, 1024, 1, 1}, {0, 2, 1, 4096, 1, 1}, {0, 0, 1, 0, 1, 1},
     };
     const int lg = __builtin_ctz((unsigned)nb);
     const int di = dt == FD_F64 ? 0 : 1;
@@ -290,6 +293,7 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     SpmmvTune best = spmmv_tune();
     fd_status st = FD_OK;
     for (const SpmmvTune &t : cands) {
+        if (t.wide && nb < 16) continue;
         M.tune[di][lg] = t;
         M.tuned[di][lg] = true;
         st = launch_spmmv(M, dt, c, s);  // warm-up
@@ -317,6 +321,21 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
 }
 
 fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s) {
+    // wide: 32 bytes per lane (two 16-byte loads per gathered row segment)
+    const int lg = __builtin_ctz((unsigned)std::max(1, c.nb));
+    const int di = dt == FD_F64 ? 0 : 1;
+    const SpmmvTune &tn = M.tuned[di][lg & 7] ? M.tune[di][lg & 7] : spmmv_tune();
+    if (tn.wide) {
+        if (dt == FD_F64) {
+            if (c.nb == 64) return launch_t<double, 4, 16>(M, M.val64, c, s);
+            if (c.nb == 32) return launch_t<double, 4, 8>(M, M.val64, c, s);
+            if (c.nb == 16) return launch_t<double, 4, 4>(M, M.val64, c, s);
+        } else {
+            if (c.nb == 64) return launch_t<float, 8, 8>(M, M.val32, c, s);
+            if (c.nb == 32) return launch_t<float, 8, 4>(M, M.val32, c, s);
+            if (c.nb == 16) return launch_t<float, 8, 2>(M, M.val32, c, s);
+        }
+    }
     if (dt == FD_F64) {
         switch (c.nb) {
             case 1: return launch_t<double, 1, 1>(M, M.val64, c, s);

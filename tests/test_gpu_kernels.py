@@ -255,16 +255,17 @@ def test_stream_kernels_exact(n):
     assert torch.equal(c, a + 1.5)
 
 
-@pytest.mark.parametrize("order,xcd,iters,grid,nt", [(0, 1, 0, 0, 0), (0, 0, 4, 0, 1), (1, 1, 0, 1024, 1),
-                                                     (1, 0, 0, 96, 0)])
-def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt):
+@pytest.mark.parametrize("order,xcd,iters,grid,nt,wide", [(0, 1, 0, 0, 0, 0), (0, 0, 4, 0, 1, 0),
+                                                          (1, 1, 0, 1024, 1, 0), (1, 0, 0, 96, 0, 0),
+                                                          (0, 2, 1, 64, 1, 1), (0, 0, 1, 0, 1, 1)])
+def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt, wide):
     """Every launch shape computes each row the same way: bitwise equal."""
     m, A = build("hub8", "sell", 32, 256)
     X = dev(start_block(A.D, 16, 1))
     Y0 = torch.empty_like(X)
     fd.spmmv(m, X, Y0)
     try:
-        fd.spmmv_tune(order, xcd, iters, grid, nt)
+        fd.spmmv_tune(order, xcd, iters, grid, nt, wide)
         Y1 = torch.empty_like(X)
         fd.spmmv(m, X, Y1)
         lo, hi = O.gershgorin(A)
