@@ -165,9 +165,20 @@ fd_status cheb_filter_impl(fd_matrix m, fd_dtype dt, int nb, int nbund, void *V,
         return filter_run(M, dt, nb, nbund, (char *)V, ldv, mu, degree, alpha, beta, (char *)W1, (char *)W2,
                           ldw, nb, s);
     }
+    // One bundle after another.  When V is wider than a bundle, each bundle
+    // is staged in a contiguous D x nb slab (a gather and a scatter per
+    // filter application) so that the degree steps stream V contiguously.
+    char *stage = nullptr;
+    if (ldv != nb && degree >= 8) stage = (char *)workspace((size_t)M.D * nb * es, 7);
     for (int b = 0; b < nbund; b++) {
-        FD_TRY(filter_run(M, dt, nb, 1, (char *)V + (size_t)b * nb * es, ldv, mu, degree, alpha, beta,
-                          (char *)W1, (char *)W2, ldw, 0, s));
+        char *Vb = (char *)V + (size_t)b * nb * es;
+        if (stage) {
+            FD_TRY(copy_rows(M.D, (int64_t)nb * es, Vb, ldv * (int64_t)es, stage, (int64_t)nb * es, s));
+            FD_TRY(filter_run(M, dt, nb, 1, stage, nb, mu, degree, alpha, beta, (char *)W1, (char *)W2, ldw, 0, s));
+            FD_TRY(copy_rows(M.D, (int64_t)nb * es, stage, (int64_t)nb * es, Vb, ldv * (int64_t)es, s));
+        } else {
+            FD_TRY(filter_run(M, dt, nb, 1, Vb, ldv, mu, degree, alpha, beta, (char *)W1, (char *)W2, ldw, 0, s));
+        }
     }
     return FD_OK;
 }

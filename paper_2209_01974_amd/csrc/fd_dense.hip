@@ -819,6 +819,42 @@ fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *d
     return FD_OK;
 }
 
+// ------------------------------------------------ strided block copy ----
+namespace {
+// rows of `w` units of U (4, 8 or 16 bytes): b[i * lb + j] = a[i * la + j]
+template <typename U>
+__global__ __launch_bounds__(256) void k_copy2d(int64_t D, int w, const U *__restrict__ a, int64_t la,
+                                                U *__restrict__ b, int64_t lb) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= D * w) return;
+    const int64_t i = e / w;
+    const int j = (int)(e % w);
+    __builtin_nontemporal_store(__builtin_nontemporal_load(a + i * la + j), b + i * lb + j);
+}
+}  // namespace
+
+fd_status copy_rows(int64_t D, int64_t row_bytes, const void *src, int64_t src_ld_bytes, void *dst,
+                    int64_t dst_ld_bytes, hipStream_t s) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const uintptr_t al = (uintptr_t)src | (uintptr_t)dst | (uintptr_t)row_bytes | (uintptr_t)src_ld_bytes |
+                         (uintptr_t)dst_ld_bytes;
+    const int64_t u = (al % 16 == 0) ? 16 : (al % 8 == 0) ? 8 : 4;
+    if (al % 4) return fail(FD_ERR_INVALID, "copy_rows: 4-byte alignment needed");
+    const int w = (int)(row_bytes / u);
+    const unsigned g = (unsigned)((D * w + 255) / 256);
+    if (u == 16)
+        hipLaunchKernelGGL(k_copy2d<f4>, dim3(g), dim3(256), 0, s, D, w, (const f4 *)src, src_ld_bytes / 16,
+                           (f4 *)dst, dst_ld_bytes / 16);
+    else if (u == 8)
+        hipLaunchKernelGGL(k_copy2d<double>, dim3(g), dim3(256), 0, s, D, w, (const double *)src, src_ld_bytes / 8,
+                           (double *)dst, dst_ld_bytes / 8);
+    else
+        hipLaunchKernelGGL(k_copy2d<float>, dim3(g), dim3(256), 0, s, D, w, (const float *)src, src_ld_bytes / 4,
+                           (float *)dst, dst_ld_bytes / 4);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
 // --------------------------------------------------- element-wise kernels --
 namespace {
 

@@ -149,6 +149,8 @@ fd_status symmetrize(int n, double *H, hipStream_t s);
 fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
                    hipStream_t s);
 fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s);
+fd_status copy_rows(int64_t D, int64_t row_bytes, const void *src, int64_t src_ld_bytes, void *dst,
+                    int64_t dst_ld_bytes, hipStream_t s);
 fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s);
 
 // Degree-picker network (fd_mlp.hip).
