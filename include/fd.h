@@ -51,7 +51,7 @@ typedef enum {
 } fd_status;
 
 typedef enum { FD_F64 = 0, FD_F32 = 1 } fd_dtype;
-typedef enum { FD_FMT_CSR = 0, FD_FMT_SELL = 1 } fd_format;
+typedef enum { FD_FMT_CSR = 0, FD_FMT_SELL = 1, FD_FMT_MATFREE = 2 } fd_format;
 typedef enum {
     FD_HUBBARD_RING = 0, /* 1D Hubbard model, L sites, n_up + n_dn fermions  */
     FD_ANDERSON_3D = 1,  /* 3D Anderson lattice, L^3 sites                   */
@@ -101,6 +101,15 @@ typedef struct fd_matrix_s *fd_matrix; /* opaque, owned by the library */
  * FD_BUILD_HOST_ONLY is set, FP64 values, FP32 values (round to nearest
  * even) and the index arrays are copied to the current device.  The
  * Gershgorin interval of A is computed here.  *out receives a new handle.  */
+/* FD_FMT_MATFREE (FD_HUBBARD_RING only): no stored matrix, on the host or
+ * the device.  The sparse kernels apply H = H_up x I + I x H_dn + U D from
+ * per-species hop tables (the tensor-product structure behind the paper's
+ * matrix-free Hubbard SpMV, Sec. 4.2): one pass for the down hops and the
+ * diagonal in row order, one for the up hops in tiles of C down-states
+ * (C = 0: 16; fd_autotune may choose another tile).  The Gershgorin interval
+ * is taken from the tables; fd_matrix_export_csr returns FD_ERR_INVALID;
+ * fd_matrix_info reports the hop-table entries as "stored".  sigma is
+ * ignored.  C outside [0, 2^20]: FD_ERR_INVALID.                           */
 fd_status fd_build_matrix(const fd_model_params *params, fd_format fmt, int32_t C,
                           int32_t sigma, int32_t flags, fd_matrix *out);
 
@@ -220,8 +229,8 @@ fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_ta
 /* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
  * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
  * D x nb (allocated and freed here) and keeps the fastest in the handle for
- * (dtype, nb); later calls on this matrix use it.  shape (5 ints, may be
- * NULL) receives order, xcd, iters, grid, nontemporal, wide (6 ints).
+ * (dtype, nb); later calls on this matrix use it.  shape (7 ints, may be
+ * NULL) receives order, xcd, iters, grid, nontemporal, wide, tile.
  * Synchronizes.                                                            */
 fd_status fd_autotune(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
 
@@ -243,11 +252,14 @@ int32_t fd_syev_last_sweeps(void);
  * xcd 2 (order 0 only): XCD x owns the row chunks x, x+8, x+16, ... of
  * `grid` rows each (0 = 1024).  nontemporal != 0: operands that are streamed
  * once bypass the caches.  wide != 0 (nb >= 16): each lane owns 32 bytes of
- * a row (two 16-byte loads per gathered row) instead of 16.  Default:
- * order 0, xcd 2, iters 1, grid 1024, nontemporal 1, wide 0.  A shape chosen
- * by fd_autotune for a matrix takes precedence for that matrix.            */
+ * a row (two 16-byte loads per gathered row) instead of 16.  Matrix-free
+ * Hubbard matrices use xcd (1: remap as above, else none), nontemporal and
+ * tile (down-states per tile of the up-hop pass, 0: the matrix's default).
+ * Default: order 0, xcd 2, iters 1, grid 1024, nontemporal 1, wide 0,
+ * tile 0.  A shape chosen by fd_autotune for a matrix takes precedence for
+ * that matrix.  tile outside [0, 2^20]: FD_ERR_INVALID.                    */
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal,
-                        int32_t wide);
+                        int32_t wide, int32_t tile);
 
 #define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */
 #define FD_ORTHO_CHOLQR2 1 /* two Cholesky-QR passes, SVQB2 if one fails    */

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfd.so")
 
 FD_OK, FD_ERR_INVALID, FD_ERR_OOM, FD_ERR_HIP, FD_ERR_NOT_CONVERGED, FD_ERR_BREAKDOWN, FD_ERR_UNSUPPORTED = range(7)
 FD_F64, FD_F32 = 0, 1
-FD_FMT_CSR, FD_FMT_SELL = 0, 1
+FD_FMT_CSR, FD_FMT_SELL, FD_FMT_MATFREE = 0, 1, 2
 FD_HUBBARD_RING, FD_ANDERSON_3D, FD_DIAGONAL, FD_USER_CSR = range(4)
 FD_BUILD_HOST_ONLY = 1
 FD_ORTHO_SVQB2, FD_ORTHO_CHOLQR2 = 0, 1
@@ -81,7 +81,7 @@ _SIGS = {
     "fd_orthog": [_I64, _I32, _P, _I64, _I32, C.c_uint64, C.POINTER(_I32), _P],
     "fd_rayleigh_ritz": [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P],
     "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
-    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32, _I32],
+    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32, _I32, _I32],
     "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
     "fd_autotune": [_P, C.c_int, _I32, _P, _P],
     "fd_kpm_moments": [_P, _I32, _P, _I64, _I32, _D, _D, _P, _P, _I64, _P, _P],
@@ -198,7 +198,8 @@ class Matrix:
 def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host_only: bool = False,
                  L: int = 0, n_up: int = 0, n_dn: int = 0, periodic: bool = True, t: float = 1.0,
                  U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None) -> Matrix:
-    """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"}."""
+    """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"} and fmt in
+    {"csr", "sell", "matfree"} ("matfree": Hubbard only, C_ = default up-pass tile)."""
     p = ModelParams()
     keep = []
     codes = {"hubbard": FD_HUBBARD_RING, "anderson": FD_ANDERSON_3D, "diagonal": FD_DIAGONAL, "csr": FD_USER_CSR}
@@ -216,7 +217,7 @@ def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host
         keep += [rowptr, col, val]
         p.D = rowptr.size - 1
         p.rowptr, p.col, p.val = rowptr.ctypes.data, col.ctypes.data, val.ctypes.data
-    f = {"csr": FD_FMT_CSR, "sell": FD_FMT_SELL}[fmt]
+    f = {"csr": FD_FMT_CSR, "sell": FD_FMT_SELL, "matfree": FD_FMT_MATFREE}[fmt]
     h = C.c_void_p()
     _check(lib().fd_build_matrix(C.byref(p), f, C_, sigma, FD_BUILD_HOST_ONLY if host_only else 0, C.byref(h)))
     return Matrix(h, f, C_ if f == FD_FMT_SELL else 1)
@@ -275,9 +276,9 @@ def syev(S, w, U, stream=None) -> None:
 
 
 def spmmv_tune(order: int = 0, xcd: int = 2, iters: int = 1, grid: int = 1024, nontemporal: int = 1,
-               wide: int = 0) -> None:
+               wide: int = 0, tile: int = 0) -> None:
     """Launch shape of the sparse kernels (process-wide; results unchanged)."""
-    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide))
+    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide, tile))
 
 
 def kpm_moments(m: "Matrix", R, nmom: int, alpha: float, beta: float, stream=None) -> np.ndarray:
@@ -346,7 +347,7 @@ def window_count(mu_kpm: np.ndarray, D: int, a: float, b: float) -> float:
 
 def autotune(m: "Matrix", dtype: str = "f64", nb: int = 64, stream=None) -> tuple:
     """Pick the fastest launch shape of the fused step for (m, dtype, nb)."""
-    shape = (C.c_int32 * 6)()
+    shape = (C.c_int32 * 7)()
     _check(lib().fd_autotune(m.handle, FD_F64 if dtype == "f64" else FD_F32, nb, shape, _stream(stream)))
     return tuple(shape)
 

@@ -56,7 +56,39 @@ bool overlap(const void *a, int64_t la, const void *b, int64_t lb, int64_t D, si
     return a0 < b1 && b0 < a1;
 }
 
+template <typename T>
+fd_status to_device(T **dst, const std::vector<T> &src) {
+    FD_HIP(hipMalloc((void **)dst, std::max<size_t>(1, src.size()) * sizeof(T)));
+    if (!src.empty()) FD_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FD_OK;
+}
+
+// matrix-free Hubbard: the hop tables and spin masks, FP64 and FP32 elements
+fd_status upload_tables(fd_matrix m) {
+    DevMatrix &d = m->dev;
+    const HubbardTables &T = m->hub;
+    d.matfree = true;
+    d.D = T.nu * T.nd;
+    d.nu = T.nu;
+    d.nd = T.nd;
+    d.U = T.U;
+    std::vector<float> u32(T.val_u.begin(), T.val_u.end()), d32(T.val_d.begin(), T.val_d.end());
+    FD_TRY(to_device(&d.mu, T.mu));
+    FD_TRY(to_device(&d.md, T.md));
+    FD_TRY(to_device(&d.off_u, T.off_u));
+    FD_TRY(to_device(&d.off_d, T.off_d));
+    FD_TRY(to_device(&d.idx_u, T.idx_u));
+    FD_TRY(to_device(&d.idx_d, T.idx_d));
+    FD_TRY(to_device(&d.val_u64, T.val_u));
+    FD_TRY(to_device(&d.val_d64, T.val_d));
+    FD_TRY(to_device(&d.val_u32, u32));
+    FD_TRY(to_device(&d.val_d32, d32));
+    FD_HIP(hipGetDevice(&m->device));
+    return FD_OK;
+}
+
 fd_status upload(fd_matrix m) {
+    if (m->fmt == FD_FMT_MATFREE) return upload_tables(m);
     DevMatrix &d = m->dev;
     const int64_t D = m->csr.D;
     d.D = D;
@@ -110,6 +142,9 @@ void free_dev(DevMatrix &d) {
     if (d.val64) (void)hipFree(d.val64);
     if (d.val32) (void)hipFree(d.val32);
     if (d.perm) (void)hipFree(d.perm);
+    void *tabs[] = {d.mu, d.md, d.off_u, d.off_d, d.idx_u, d.idx_d, d.val_u64, d.val_d64, d.val_u32, d.val_d32};
+    for (void *p : tabs)
+        if (p) (void)hipFree(p);
     d = DevMatrix();
 }
 
@@ -340,10 +375,36 @@ const char *fd_last_error(void) { return g_err.c_str(); }
 fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, int32_t sigma, int32_t flags,
                           fd_matrix *out) {
     if (!p || !out) return fail(FD_ERR_INVALID, "fd_build_matrix: null argument");
-    if (fmt != FD_FMT_CSR && fmt != FD_FMT_SELL) return fail(FD_ERR_INVALID, "fd_build_matrix: bad format");
+    if (fmt != FD_FMT_CSR && fmt != FD_FMT_SELL && fmt != FD_FMT_MATFREE)
+        return fail(FD_ERR_INVALID, "fd_build_matrix: bad format");
+    if (fmt == FD_FMT_MATFREE && p->model != FD_HUBBARD_RING)
+        return fail(FD_ERR_INVALID, "fd_build_matrix: the matrix-free format is for the Hubbard ring only");
+    if (fmt == FD_FMT_MATFREE && (C < 0 || C > (1 << 20)))
+        return fail(FD_ERR_INVALID, "fd_build_matrix: matrix-free tile C must be in [0, 2^20]");
     fd_matrix m = new (std::nothrow) fd_matrix_s;
     if (!m) return fail(FD_ERR_OOM, "fd_build_matrix: host allocation");
     fd_status st;
+    if (fmt == FD_FMT_MATFREE) {
+        st = hubbard_tables(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->hub);
+        m->fmt = fmt;
+        if (st == FD_OK) {
+            m->D = m->hub.nu * m->hub.nd;
+            m->nnz = hubbard_tables_nnz(m->hub);
+            m->stored = (int64_t)(m->hub.idx_u.size() + m->hub.idx_d.size());
+            hubbard_tables_gershgorin(m->hub, m->lam_lo, m->lam_hi);
+            m->dev.mf_tile = C > 0 ? C : 16;
+        }
+        if (st == FD_OK && !(flags & FD_BUILD_HOST_ONLY)) {
+            st = upload(m);
+            if (st != FD_OK) free_dev(m->dev);
+        }
+        if (st != FD_OK) {
+            delete m;
+            return st;
+        }
+        *out = m;
+        return FD_OK;
+    }
     switch (p->model) {
         case FD_HUBBARD_RING: st = build_hubbard(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->csr); break;
         case FD_ANDERSON_3D: st = build_anderson(p->L, p->t, p->W, p->seed, m->csr); break;
@@ -353,7 +414,12 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
     }
     if (st == FD_OK && fmt == FD_FMT_SELL) st = build_sell(m->csr, C, sigma, m->sell);
     m->fmt = fmt;
-    if (st == FD_OK) gershgorin(m->csr, m->lam_lo, m->lam_hi);
+    if (st == FD_OK) {
+        gershgorin(m->csr, m->lam_lo, m->lam_hi);
+        m->D = m->csr.D;
+        m->nnz = m->csr.rowptr[m->csr.D];
+        m->stored = (fmt == FD_FMT_SELL) ? m->sell.chunk_ptr.back() : m->nnz;
+    }
     if (st == FD_OK && !(flags & FD_BUILD_HOST_ONLY)) {
         st = upload(m);
         if (st != FD_OK) free_dev(m->dev);
@@ -368,9 +434,9 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
 
 fd_status fd_matrix_info(fd_matrix m, int64_t *D, int64_t *nnz, int64_t *stored, double *lo, double *hi) {
     if (!m) return fail(FD_ERR_INVALID, "fd_matrix_info: null handle");
-    if (D) *D = m->csr.D;
-    if (nnz) *nnz = m->csr.rowptr[m->csr.D];
-    if (stored) *stored = (m->fmt == FD_FMT_SELL) ? m->sell.chunk_ptr.back() : m->csr.rowptr[m->csr.D];
+    if (D) *D = m->D;
+    if (nnz) *nnz = m->nnz;
+    if (stored) *stored = m->stored;
     if (lo) *lo = m->lam_lo;
     if (hi) *hi = m->lam_hi;
     return FD_OK;
@@ -378,6 +444,7 @@ fd_status fd_matrix_info(fd_matrix m, int64_t *D, int64_t *nnz, int64_t *stored,
 
 fd_status fd_matrix_export_csr(fd_matrix m, int64_t *rowptr, uint32_t *col, double *val) {
     if (!m || !rowptr || !col || !val) return fail(FD_ERR_INVALID, "fd_matrix_export_csr: null argument");
+    if (m->fmt == FD_FMT_MATFREE) return fail(FD_ERR_INVALID, "fd_matrix_export_csr: matrix-free matrix stores no CSR");
     std::memcpy(rowptr, m->csr.rowptr.data(), m->csr.rowptr.size() * sizeof(int64_t));
     std::memcpy(col, m->csr.col.data(), m->csr.col.size() * sizeof(uint32_t));
     std::memcpy(val, m->csr.val.data(), m->csr.val.size() * sizeof(double));
@@ -475,6 +542,7 @@ fd_status fd_autotune(fd_matrix m, fd_dtype dt, int32_t nb, int32_t *shape, void
         shape[3] = t.grid;
         shape[4] = t.nontemporal;
         shape[5] = t.wide;
+        shape[6] = t.tile;
     }
     return FD_OK;
 }
@@ -608,9 +676,10 @@ fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, dou
     return stream_op(op, n, a, b, c, scalar, (hipStream_t)stream);
 }
 
-fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal, int32_t wide) {
+fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal, int32_t wide,
+                        int32_t tile) {
     if (order < 0 || order > 1 || xcd < 0 || xcd > 2 || (order == 1 && xcd == 2) || iters < 0 || grid < 0 ||
-        grid > (1 << 24))
+        grid > (1 << 24) || tile < 0 || tile > (1 << 20))
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
     SpmmvTune &t = spmmv_tune();
     t.order = order;
@@ -619,6 +688,7 @@ fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid,
     t.grid = grid;
     t.nontemporal = nontemporal != 0;
     t.wide = wide != 0;
+    t.tile = tile;
     return FD_OK;
 }
 

@@ -185,6 +185,55 @@ fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double
     return FD_OK;
 }
 
+fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, HubbardTables &T) {
+    if (L < 3 || L > 62 || nup < 0 || nup > L || ndn < 0 || ndn > L)
+        return fail(FD_ERR_INVALID, "Hubbard: need 3 <= L <= 62 and 0 <= n_up, n_dn <= L");
+    if ((uint64_t)binom().c[L][nup] * binom().c[L][ndn] >= (1ULL << 32))
+        return fail(FD_ERR_UNSUPPORTED, "Hubbard: D >= 2^32");
+    std::vector<uint32_t> ou, od;
+    std::vector<Hop> hu, hd;
+    species_hops(L, nup, periodic, t, T.mu, ou, hu);
+    species_hops(L, ndn, periodic, t, T.md, od, hd);
+    T.nu = (int64_t)T.mu.size();
+    T.nd = (int64_t)T.md.size();
+    T.U = U;
+    T.off_u.assign(ou.begin(), ou.end());
+    T.off_d.assign(od.begin(), od.end());
+    for (const Hop &h : hu) {
+        T.idx_u.push_back((int32_t)h.rank);
+        T.val_u.push_back(h.el);
+    }
+    for (const Hop &h : hd) {
+        T.idx_d.push_back((int32_t)h.rank);
+        T.val_d.push_back(h.el);
+    }
+    return FD_OK;
+}
+
+int64_t hubbard_tables_nnz(const HubbardTables &T) {
+    return T.nu * T.nd + (int64_t)T.idx_u.size() * T.nd + (int64_t)T.idx_d.size() * T.nu;
+}
+
+// Gershgorin interval of the tensor-product form: row (a, b) has centre
+// U popcount(mu[a] & md[b]) and radius sum |up hops of a| + sum |down hops of b|.
+void hubbard_tables_gershgorin(const HubbardTables &T, double &lo, double &hi) {
+    std::vector<double> ru(T.nu, 0.0), rd(T.nd, 0.0);
+    for (int64_t a = 0; a < T.nu; a++)
+        for (int32_t j = T.off_u[a]; j < T.off_u[a + 1]; j++) ru[a] += std::fabs(T.val_u[j]);
+    for (int64_t b = 0; b < T.nd; b++)
+        for (int32_t j = T.off_d[b]; j < T.off_d[b + 1]; j++) rd[b] += std::fabs(T.val_d[j]);
+    lo = HUGE_VAL;
+    hi = -HUGE_VAL;
+    for (int64_t a = 0; a < T.nu; a++)
+        for (int64_t b = 0; b < T.nd; b++) {
+            const double c = T.U * (double)__builtin_popcountll(T.mu[a] & T.md[b]);
+            const double r = ru[a] + rd[b];
+            lo = std::min(lo, c - r);
+            hi = std::max(hi, c + r);
+        }
+    if (T.nu * T.nd == 0) lo = hi = 0.0;
+}
+
 fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A) {
     if (L < 3 || (int64_t)L * L * L >= (1LL << 32))
         return fail(FD_ERR_INVALID, "Anderson: need L >= 3 and L^3 < 2^32");

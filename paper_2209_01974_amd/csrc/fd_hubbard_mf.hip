@@ -1,0 +1,257 @@
+// Matrix-free Hubbard SpMMV and fused Chebyshev step on gfx950.
+//
+// In the up-major Fock basis (row (a, b) = a nd + b) the Hubbard ring is the
+// tensor-product sum H = H_up x I + I x H_dn + U D (the structure the paper's
+// matrix-free Hubbard SpMV uses, Sec. 4.2): row (a, b) couples to (a', b) for
+// each up hop a -> a' and to (a, b') for each down hop b -> b'.  No matrix is
+// stored.  The operator is applied in two passes so that both kinds of
+// gathers are served from cache:
+//   pass 1, rows in natural order: the down hops and the diagonal.  The
+//     gathers of row (a, b) stay in the slab x[a, :] (nd rows), which L2
+//     holds.  It writes the part of the update that needs no up hop,
+//     e.g. y = a (I x H_dn + U D) x + b x - z for the Chebyshev step.
+//   pass 2, rows in tiles of tile_b down-states, tile after tile with all up
+//     states of a tile in a row: y += a (H_up x I) x, then the rest of the
+//     update.  The gathers x[a', b] of one tile touch only nu * tile_b rows.
+// The first pass writes its partial result into y itself, so the only extra
+// traffic over a stored-matrix step is one more read and write of y, against
+// the matrix and the strided up-hop gathers it saves.  Lane mapping as in
+// the stored-matrix kernel: a row of nb values is split over G lanes of VEC
+// values each; blockIdx.y selects the bundle.
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+template <typename T, int VEC> struct VT;
+template <> struct VT<double, 1> { typedef double type; };
+template <> struct VT<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct VT<float, 1> { typedef float type; };
+template <> struct VT<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct VT<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+
+template <typename T>
+struct MfArgs {
+    int64_t nu, nd, D, nlog;  // nlog: logical rows of pass 2 (ntiles nu tile_b)
+    int64_t tile_b;
+    int64_t nblk, q8;         // blocks per bundle, floor(nblk / 8)
+    const uint64_t *__restrict__ mu;
+    const uint64_t *__restrict__ md;
+    const int32_t *__restrict__ off_u;
+    const int32_t *__restrict__ idx_u;
+    const T *__restrict__ val_u;
+    const int32_t *__restrict__ off_d;
+    const int32_t *__restrict__ idx_d;
+    const T *__restrict__ val_d;
+    T U;
+    const T *x; int64_t ldx, bx;
+    T *y; int64_t ldy, by;
+    const T *z; int64_t ldz, bz;
+    T *v; int64_t ldv, bv;
+    T a, b, cv, cx, ct;
+};
+
+template <typename V>
+__device__ __forceinline__ V ld(const void *p) { return *reinterpret_cast<const V *>(p); }
+template <typename V, bool NT>
+__device__ __forceinline__ V lds(const void *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    else return *reinterpret_cast<const V *>(p);
+}
+template <typename V, bool NT>
+__device__ __forceinline__ void sts(void *p, V x) {
+    if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<V *>(p));
+    else *reinterpret_cast<V *>(p) = x;
+}
+
+// Block index -> logical block.  XCD: the hardware deals consecutive blocks
+// to the 8 XCDs in turn; remap so that XCD k works through the k-th eighth
+// of the logical blocks (a bijection on the first 8 q8 blocks, the tail
+// unchanged), which keeps a slab or a tile in one XCD's L2.
+template <bool XCD>
+__device__ __forceinline__ int64_t logical_block(int64_t bid, int64_t q8) {
+    if constexpr (XCD) {
+        if (bid < 8 * q8) return (bid & 7) * q8 + (bid >> 3);
+    }
+    return bid;
+}
+
+// pass 1: down hops + diagonal, rows in natural order.
+//   MODE 0: y = s           MODE 1: y = a s + b x
+//   MODE 2: y = a s + b x - v        MODE 3, 4: y = a s + b x - z
+// with s = (I x H_dn + U D) x.  y may alias z (same element read first).
+template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
+__global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
+    typedef typename VT<T, VEC>::type V;
+    constexpr int RPB = 256 / G;
+    const int64_t blk = logical_block<XCD>(blockIdx.x, p.q8);
+    const int64_t s = blk * RPB + threadIdx.x / G;
+    if (s >= p.D) return;
+    const int q = threadIdx.x % G;
+    const int64_t bnd = blockIdx.y;
+    const T *xq = p.x + bnd * p.bx + q * VEC;
+    const int64_t a = s / p.nd, b = s - a * p.nd;
+    V zi = (V)0;
+    if constexpr (MODE == 2) zi = lds<V, NT>(p.v + bnd * p.bv + s * p.ldv + q * VEC);
+    if constexpr (MODE == 3 || MODE == 4) zi = lds<V, NT>(p.z + bnd * p.bz + s * p.ldz + q * VEC);
+    const V xi = ld<V>(xq + s * p.ldx);
+    V acc0 = (p.U * (T)__popcll(p.mu[a] & p.md[b])) * xi, acc1 = (V)0;
+    const int64_t row0 = a * p.nd;
+    const int32_t j1 = p.off_d[b + 1];
+    int32_t j = p.off_d[b];
+    for (; j + 2 <= j1; j += 2) {
+        const int32_t c0 = p.idx_d[j], c1 = p.idx_d[j + 1];
+        const T e0 = p.val_d[j], e1 = p.val_d[j + 1];
+        acc0 += e0 * ld<V>(xq + (row0 + c0) * p.ldx);
+        acc1 += e1 * ld<V>(xq + (row0 + c1) * p.ldx);
+    }
+    if (j < j1) acc0 += p.val_d[j] * ld<V>(xq + (row0 + p.idx_d[j]) * p.ldx);
+    V r = acc0 + acc1;
+    if constexpr (MODE >= 1) r = p.a * r + p.b * xi;
+    if constexpr (MODE >= 2) r -= zi;
+    sts<V, NT>(p.y + bnd * p.by + s * p.ldy + q * VEC, r);
+}
+
+// pass 2: up hops, rows in down-state tiles; t = y + c u with
+// u = (H_up x I) x and c = 1 (MODE 0) or a (else).  Then
+//   MODE 0, 1, 4: y = t
+//   MODE 2: y = t, v = cv v + cx x + ct t
+//   MODE 3: y = t, v = v + ct t
+template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
+__global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
+    typedef typename VT<T, VEC>::type V;
+    constexpr int RPB = 256 / G;
+    const int64_t blk = logical_block<XCD>(blockIdx.x, p.q8);
+    const int64_t l = blk * RPB + threadIdx.x / G;
+    if (l >= p.nlog) return;
+    const int64_t per_tile = p.nu * p.tile_b;
+    const int64_t tile = l / per_tile;
+    const int64_t rem = l - tile * per_tile;
+    const int64_t a = rem / p.tile_b;
+    const int64_t b = tile * p.tile_b + (rem - a * p.tile_b);
+    if (b >= p.nd) return;
+    const int64_t s = a * p.nd + b;
+    const int q = threadIdx.x % G;
+    const int64_t bnd = blockIdx.y;
+    const T *xq = p.x + bnd * p.bx + q * VEC;
+    T *yr = p.y + bnd * p.by + s * p.ldy + q * VEC;
+    V vi = (V)0, xi = (V)0;
+    T *vr = nullptr;
+    if constexpr (MODE == 2 || MODE == 3) {
+        vr = p.v + bnd * p.bv + s * p.ldv + q * VEC;
+        vi = lds<V, NT>(vr);
+    }
+    if constexpr (MODE == 2) xi = ld<V>(xq + s * p.ldx);
+    const V yi = lds<V, NT>(yr);
+    V acc0 = (V)0, acc1 = (V)0;
+    const int32_t j1 = p.off_u[a + 1];
+    int32_t j = p.off_u[a];
+    for (; j + 2 <= j1; j += 2) {
+        const int32_t c0 = p.idx_u[j], c1 = p.idx_u[j + 1];
+        const T e0 = p.val_u[j], e1 = p.val_u[j + 1];
+        acc0 += e0 * ld<V>(xq + ((int64_t)c0 * p.nd + b) * p.ldx);
+        acc1 += e1 * ld<V>(xq + ((int64_t)c1 * p.nd + b) * p.ldx);
+    }
+    if (j < j1) acc0 += p.val_u[j] * ld<V>(xq + ((int64_t)p.idx_u[j] * p.nd + b) * p.ldx);
+    V t;
+    if constexpr (MODE == 0) t = yi + (acc0 + acc1);
+    else t = yi + p.a * (acc0 + acc1);
+    sts<V, NT>(yr, t);
+    if constexpr (MODE == 2) sts<V, NT>(vr, p.cv * vi + p.cx * xi + p.ct * t);
+    if constexpr (MODE == 3) sts<V, NT>(vr, vi + p.ct * t);
+}
+
+template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
+fd_status launch_mode(const MfArgs<T> &p, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+    MfArgs<T> p1 = p, p2 = p;
+    p1.nblk = g1;
+    p1.q8 = g1 / 8;
+    p2.nblk = g2;
+    p2.q8 = g2 / 8;
+    hipLaunchKernelGGL((k_mf_down<T, VEC, G, MODE, XCD, NT>), dim3((unsigned)g1, nbund), dim3(256), 0, s, p1);
+    FD_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_mf_up<T, VEC, G, MODE, XCD, NT>), dim3((unsigned)g2, nbund), dim3(256), 0, s, p2);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+template <typename T, int VEC, int G, bool XCD, bool NT>
+fd_status launch_x(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+    switch (mode) {
+        case 0: return launch_mode<T, VEC, G, 0, XCD, NT>(p, nbund, g1, g2, s);
+        case 1: return launch_mode<T, VEC, G, 1, XCD, NT>(p, nbund, g1, g2, s);
+        case 2: return launch_mode<T, VEC, G, 2, XCD, NT>(p, nbund, g1, g2, s);
+        case 3: return launch_mode<T, VEC, G, 3, XCD, NT>(p, nbund, g1, g2, s);
+        case 4: return launch_mode<T, VEC, G, 4, XCD, NT>(p, nbund, g1, g2, s);
+    }
+    return fail(FD_ERR_INVALID, "matrix-free SpMMV: bad mode");
+}
+
+template <typename T, int VEC, int G>
+fd_status launch_mf_t(const DevMatrix &M, const T *val_u, const T *val_d, const SpmmvTune &tn,
+                      const SpmmvCall &c, hipStream_t s) {
+    constexpr int RPB = 256 / G;
+    MfArgs<T> p;
+    p.nu = M.nu;
+    p.nd = M.nd;
+    p.D = M.D;
+    p.tile_b = std::max<int64_t>(1, std::min<int64_t>(tn.tile > 0 ? tn.tile : M.mf_tile, M.nd));
+    const int64_t ntiles = (M.nd + p.tile_b - 1) / p.tile_b;
+    p.nlog = ntiles * M.nu * p.tile_b;
+    p.nblk = p.q8 = 0;
+    p.mu = M.mu;
+    p.md = M.md;
+    p.off_u = M.off_u;
+    p.idx_u = M.idx_u;
+    p.val_u = val_u;
+    p.off_d = M.off_d;
+    p.idx_d = M.idx_d;
+    p.val_d = val_d;
+    p.U = (T)M.U;
+    p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;
+    p.y = (T *)c.y; p.ldy = c.ldy; p.by = c.by;
+    p.z = (const T *)c.z; p.ldz = c.ldz; p.bz = c.bz;
+    p.v = (T *)c.v; p.ldv = c.ldv; p.bv = c.bv;
+    p.a = (T)c.a; p.b = (T)c.b; p.cv = (T)c.cv; p.cx = (T)c.cx; p.ct = (T)c.ct;
+    if (M.D == 0) return FD_OK;
+    const int64_t g1 = (M.D + RPB - 1) / RPB, g2 = (p.nlog + RPB - 1) / RPB;
+    if (g1 > 0x7fffffff || g2 > 0x7fffffff || c.nbundles < 1 || c.nbundles > 65535)
+        return fail(FD_ERR_UNSUPPORTED, "matrix-free SpMMV: grid too large");
+    const bool xcd = tn.xcd == 1, nt = tn.nontemporal != 0;
+    if (xcd) {
+        if (nt) return launch_x<T, VEC, G, true, true>(p, c.mode, c.nbundles, g1, g2, s);
+        return launch_x<T, VEC, G, true, false>(p, c.mode, c.nbundles, g1, g2, s);
+    }
+    if (nt) return launch_x<T, VEC, G, false, true>(p, c.mode, c.nbundles, g1, g2, s);
+    return launch_x<T, VEC, G, false, false>(p, c.mode, c.nbundles, g1, g2, s);
+}
+
+}  // namespace
+
+fd_status launch_spmmv_mf(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, const SpmmvTune &tn,
+                          hipStream_t s) {
+    if (dt == FD_F64) {
+        switch (c.nb) {
+            case 1: return launch_mf_t<double, 1, 1>(M, M.val_u64, M.val_d64, tn, c, s);
+            case 2: return launch_mf_t<double, 2, 1>(M, M.val_u64, M.val_d64, tn, c, s);
+            case 4: return launch_mf_t<double, 2, 2>(M, M.val_u64, M.val_d64, tn, c, s);
+            case 8: return launch_mf_t<double, 2, 4>(M, M.val_u64, M.val_d64, tn, c, s);
+            case 16: return launch_mf_t<double, 2, 8>(M, M.val_u64, M.val_d64, tn, c, s);
+            case 32: return launch_mf_t<double, 2, 16>(M, M.val_u64, M.val_d64, tn, c, s);
+            case 64: return launch_mf_t<double, 2, 32>(M, M.val_u64, M.val_d64, tn, c, s);
+        }
+    } else {
+        switch (c.nb) {
+            case 1: return launch_mf_t<float, 1, 1>(M, M.val_u32, M.val_d32, tn, c, s);
+            case 2: return launch_mf_t<float, 2, 1>(M, M.val_u32, M.val_d32, tn, c, s);
+            case 4: return launch_mf_t<float, 4, 1>(M, M.val_u32, M.val_d32, tn, c, s);
+            case 8: return launch_mf_t<float, 4, 2>(M, M.val_u32, M.val_d32, tn, c, s);
+            case 16: return launch_mf_t<float, 4, 4>(M, M.val_u32, M.val_d32, tn, c, s);
+            case 32: return launch_mf_t<float, 4, 8>(M, M.val_u32, M.val_d32, tn, c, s);
+            case 64: return launch_mf_t<float, 4, 16>(M, M.val_u32, M.val_d32, tn, c, s);
+        }
+    }
+    return fail(FD_ERR_INVALID, "nb must be one of 1, 2, 4, 8, 16, 32, 64");
+}
+
+}  // namespace fd

@@ -45,6 +45,20 @@ struct HostSELL {
 };
 
 fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, HostCSR &A);
+
+// Tensor-product form of the Hubbard ring: H = H_up x I + I x H_dn + U D.
+// Per spin species, the configurations one hop away (rank, element), sorted.
+struct HubbardTables {
+    int64_t nu = 0, nd = 0;
+    double U = 0;
+    std::vector<uint64_t> mu, md;           // spin configurations (bit masks)
+    std::vector<int32_t> off_u, off_d;      // nu + 1, nd + 1
+    std::vector<int32_t> idx_u, idx_d;      // hop targets (ranks)
+    std::vector<double> val_u, val_d;       // hop elements
+};
+fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, HubbardTables &T);
+int64_t hubbard_tables_nnz(const HubbardTables &T);  // non-zeros of the full matrix
+void hubbard_tables_gershgorin(const HubbardTables &T, double &lo, double &hi);
 fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A);
 fd_status build_diagonal(int64_t n, const double *d, HostCSR &A);
 fd_status build_user(int64_t D, const int64_t *rowptr, const uint32_t *col, const double *val,
@@ -67,6 +81,7 @@ struct SpmmvTune {
     int grid = 1024;      // order 1: blocks per bundle; xcd 2: rows per chunk
     int nontemporal = 1;  // 1: streamed operands bypass the caches
     int wide = 0;         // 1: 32 bytes per lane (nb >= 16)
+    int tile = 0;         // matrix-free Hubbard: down-state tile of the up pass (0: 16)
 };
 
 // One layout serves CSR and SELL: "slot" s of the device format belongs to
@@ -86,6 +101,15 @@ struct DevMatrix {
     // launch shapes chosen by fd_autotune, per dtype and log2(nb)
     bool tuned[2][7] = {};
     SpmmvTune tune[2][7];
+    // matrix-free Hubbard (format FD_FMT_MATFREE): device copies of the tables
+    bool matfree = false;
+    int64_t nu = 0, nd = 0;
+    double U = 0;
+    uint64_t *mu = nullptr, *md = nullptr;
+    int32_t *off_u = nullptr, *off_d = nullptr, *idx_u = nullptr, *idx_d = nullptr;
+    double *val_u64 = nullptr, *val_d64 = nullptr;
+    float *val_u32 = nullptr, *val_d32 = nullptr;
+    int32_t mf_tile = 16;  // default down-state tile of the up pass
 };
 
 }  // namespace fd
@@ -94,6 +118,8 @@ struct fd_matrix_s {
     fd_format fmt = FD_FMT_CSR;
     fd::HostCSR csr;
     fd::HostSELL sell;
+    fd::HubbardTables hub;
+    int64_t D = 0, nnz = 0, stored = 0;
     double lam_lo = 0, lam_hi = 0;
     int device = -1;
     fd::DevMatrix dev;
@@ -117,6 +143,9 @@ struct SpmmvCall {
     double a = 1, b = 0, cv = 0, cx = 0, ct = 0;
 };
 fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipStream_t s);
+// matrix-free Hubbard form of the same call (fd_hubbard_mf.hip)
+fd_status launch_spmmv_mf(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, const SpmmvTune &tn,
+                          hipStream_t s);
 
 SpmmvTune &spmmv_tune();
 fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *best);

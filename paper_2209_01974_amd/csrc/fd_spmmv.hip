@@ -277,6 +277,15 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
         {0, 2, 2, 2048, 1, 0}, {0, 0, 1, 0, 1, 0},   {0, 1, 1, 0, 1, 0},    {1, 1, 1, 4096, 1, 0},
         {0, 2, 1, 1024, 1, 1}, {0, 2, 1, 4096, 1, 1}, {0, 0, 1, 0, 1, 1},
     };
+    // matrix-free Hubbard: down-state tile of the up pass, XCD remap on/off
+    const SpmmvTune mf_cands[] = {
+        {0, 0, 1, 0, 1, 0, 4},  {0, 0, 1, 0, 1, 0, 8},  {0, 0, 1, 0, 1, 0, 16}, {0, 0, 1, 0, 1, 0, 32},
+        {0, 0, 1, 0, 1, 0, 64}, {0, 1, 1, 0, 1, 0, 2},  {0, 1, 1, 0, 1, 0, 4},  {0, 1, 1, 0, 1, 0, 8},
+        {0, 1, 1, 0, 1, 0, 16}, {0, 1, 1, 0, 1, 0, 64},
+    };
+    const SpmmvTune *cb = M.matfree ? mf_cands : cands;
+    const SpmmvTune *ce = M.matfree ? mf_cands + sizeof(mf_cands) / sizeof(mf_cands[0])
+                                    : cands + sizeof(cands) / sizeof(cands[0]);
     const int lg = __builtin_ctz((unsigned)nb);
     const int di = dt == FD_F64 ? 0 : 1;
     SpmmvCall c;
@@ -292,7 +301,8 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     float best_ms = 1e30f;
     SpmmvTune best = spmmv_tune();
     fd_status st = FD_OK;
-    for (const SpmmvTune &t : cands) {
+    for (const SpmmvTune *tp = cb; tp != ce; ++tp) {
+        const SpmmvTune &t = *tp;
         if (t.wide && nb < 16) continue;
         M.tune[di][lg] = t;
         M.tuned[di][lg] = true;
@@ -325,6 +335,7 @@ fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipS
     const int lg = __builtin_ctz((unsigned)std::max(1, c.nb));
     const int di = dt == FD_F64 ? 0 : 1;
     const SpmmvTune &tn = M.tuned[di][lg & 7] ? M.tune[di][lg & 7] : spmmv_tune();
+    if (M.matfree) return launch_spmmv_mf(M, dt, c, tn, s);
     if (tn.wide) {
         if (dt == FD_F64) {
             if (c.nb == 64) return launch_t<double, 4, 16>(M, M.val64, c, s);

@@ -136,3 +136,32 @@ def test_argument_errors():
     assert b"host-only" in fd.lib().fd_last_error()
     st = fd.lib().fd_orthog(10, 0, None, 1, 0, 0, None, None)
     assert st == fd.FD_ERR_INVALID
+
+
+@pytest.mark.parametrize("L,nu,nd,U,t,per", [(6, 3, 3, 4.0, 1.0, True), (8, 4, 4, 4.0, 1.0, True),
+                                             (7, 2, 3, 2.5, 1.0, True), (8, 4, 4, 4.0, 1.0, False),
+                                             (5, 0, 2, 1.0, 1.0, True), (6, 3, 3, 2.0, 0.0, True),
+                                             (9, 4, 5, 8.0, 0.5, True)])
+def test_matfree_sizes_and_gershgorin_match_csr(L, nu, nd, U, t, per):
+    """The tensor-product (matrix-free) form describes the same matrix: the
+    same dimension and non-zero count as the stored Hubbard matrix, and the
+    same Gershgorin interval as the oracle's CSR (exact: row sums of +-t and
+    an integer multiple of U)."""
+    m = fd.build_matrix("hubbard", fmt="matfree", host_only=True, L=L, n_up=nu, n_dn=nd, t=t, U=U, periodic=per)
+    A = O.hubbard(L, nu, nd, t, U, per)
+    assert (m.D, m.nnz) == (A.D, int(A.rowptr[-1]))
+    assert (m.lam_lo, m.lam_hi) == O.gershgorin(A)
+    with pytest.raises(fd.FDError):
+        m.export_csr()
+
+
+def test_matfree_argument_errors():
+    with pytest.raises(fd.FDError) as e:
+        fd.build_matrix("anderson", fmt="matfree", host_only=True, L=4, W=1.0)
+    assert e.value.status == fd.FD_ERR_INVALID
+    with pytest.raises(fd.FDError) as e:
+        fd.build_matrix("hubbard", fmt="matfree", C_=-1, host_only=True, L=6, n_up=3, n_dn=3)
+    assert e.value.status == fd.FD_ERR_INVALID
+    with pytest.raises(fd.FDError):
+        fd.spmmv_tune(tile=-1)
+    fd.spmmv_tune()

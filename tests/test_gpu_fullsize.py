@@ -5,7 +5,8 @@ sampled rows that the oracle computes one by one from the definition.
 * 3D Anderson L=200 (D = 8,000,000, nnz = 56,000,000, W = 16.5, seed 1):
   SpMMV and a degree-3 fused filter (all three fused step forms) on nb = 64.
 * Hubbard ring L=14, 7 up + 7 down, U=8 (D = 11,778,624, nnz = 189,364,032):
-  SpMMV on nb = 32 with integer-valued blocks, bit-exact in FP64 and FP32.
+  SpMMV on nb = 32 with integer-valued blocks, bit-exact in FP64 and FP32,
+  stored (CSR) and matrix-free; a degree-3 matrix-free filter on nb = 32.
 """
 import numpy as np
 import pytest
@@ -85,3 +86,45 @@ def test_hubbard14_spmmv_nb32_integer_bit_exact(hubbard14, dt, bound):
     rows = sample_rows(A.D, 3)
     got = Yd[torch.from_numpy(rows).cuda()].double().cpu().numpy()
     assert np.array_equal(got, O.spmmv_rows(A, X, rows))
+
+
+@pytest.fixture(scope="module")
+def hubbard14_matfree():
+    m = fd.build_matrix("hubbard", fmt="matfree", L=14, n_up=7, n_dn=7, t=1.0, U=8.0)
+    assert (m.D, m.nnz) == (11_778_624, 189_364_032)
+    return m
+
+
+@pytest.mark.parametrize("dt,bound", [(torch.float64, 1 << 10), (torch.float32, 1 << 8)])
+def test_hubbard14_matfree_spmmv_nb32_integer_bit_exact(hubbard14, hubbard14_matfree, dt, bound):
+    """The matrix-free Hubbard L=14 SpMMV in its autotuned launch shape."""
+    _, A = hubbard14
+    m = hubbard14_matfree
+    fd.autotune(m, "f64" if dt == torch.float64 else "f32", 32)
+    X = int_block(A.D, 32, 24, bound)
+    Xd = torch.from_numpy(X).to(dt).cuda()
+    Yd = torch.empty_like(Xd)
+    fd.spmmv(m, Xd, Yd)
+    rows = sample_rows(A.D, 4)
+    got = Yd[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    assert np.array_equal(got, O.spmmv_rows(A, X, rows))
+
+
+def test_hubbard14_matfree_filter_degree3_sampled(hubbard14, hubbard14_matfree):
+    """Degree-3 filter (first, second and general step) on nb = 32, sampled
+    rows against the oracle's neighbourhood recursion."""
+    _, A = hubbard14
+    m = hubbard14_matfree
+    fd.autotune(m, "f64", 32)
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    mu = O.cheb_coeffs(0, alpha * -1.0 + beta, alpha * 1.0 + beta, 3)
+    V = start_block(A.D, 32, 25)
+    Vd = torch.from_numpy(V).cuda()
+    W1 = torch.empty_like(Vd)
+    W2 = torch.empty_like(Vd)
+    fd.cheb_filter(m, Vd, mu, alpha, beta, W1, W2, 32)
+    rows = np.unique(np.concatenate([sample_rows(A.D, 5)[:40], [A.D - 1]]))
+    got = Vd[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref = O.cheb_filter_rows(A, V, mu, alpha, beta, rows)
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-12
