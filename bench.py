@@ -90,7 +90,7 @@ def fd_runs(args, fd, np):
     if args.hubbard14:
         runs.append(("hubbard14", dict(L=14, n_up=7, n_dn=7, U=8.0), -1.0, 1.0, 64, 256, 32, 800))
     for name, kw, lo, hi, nt, nsr, nbr, deg in runs:
-        mh = fd.build_matrix("hubbard", t=1.0, **kw)
+        mh = fd.build_matrix("hubbard", fmt=args.hub_fmt, t=1.0, **kw)
         V0 = start_block(mh.D, nsr, 0) if mh.D * nsr <= 50_000_000 else None
         res = {}
         evs = {}
@@ -106,7 +106,8 @@ def fd_runs(args, fd, np):
             evs[label] = r.evals
             normH = st["norm_H"]
             log("FD %s %s: %s" % (name, label, res[label]))
-        res["config"] = {"D": mh.D, "nnz": mh.nnz, "window": [lo, hi], "n_target": nt, "n_search": nsr,
+        res["config"] = {"D": mh.D, "nnz": mh.nnz, "format": args.hub_fmt, "window": [lo, hi], "n_target": nt,
+                         "n_search": nsr,
                          "nb": nbr, "degree": deg, "window_rule": "adaptive"}
         res["mixed_vs_fp64_max_rel_eval_diff"] = float(np.max(np.abs(evs["mixed"] - evs["fp64"])) / normH)
         res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
@@ -131,6 +132,8 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
     ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
     ap.add_argument("--fd-only", action="store_true", help="only the FD eigenpairs/s runs (no Anderson step)")
+    ap.add_argument("--hub-fmt", choices=["csr", "sell", "matfree"], default="matfree",
+                    help="storage of the Hubbard matrices in the FD runs (matfree: tensor-product form)")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
@@ -138,8 +141,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the filter would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path; "
+              "the filter's sharding across GPUs is a design, not code.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -18,7 +18,7 @@ large-scale eigenvalue computations"):
   Wu 2002), used here in place of the paper's TSQR; the two give the same span.
 * Sec. 3.1, Eq. SpMVprocess / Eq. traffic -- block SpMV on row-major blocks.
 
-Readings where the paper is silent (every one is also listed in the design doc):
+Readings where the paper is silent:
 the window function is the indicator of the target interval with Jackson
 damping; the inclusion interval is Gershgorin's; ||H|| is max(|lam_l|, |lam_r|)
 of that interval; the N_t "best" Ritz pairs are those nearest tau inside the

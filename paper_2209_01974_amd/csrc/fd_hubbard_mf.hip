@@ -29,6 +29,8 @@ template <> struct VT<double, 2> { typedef double __attribute__((ext_vector_type
 template <> struct VT<float, 1> { typedef float type; };
 template <> struct VT<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
 template <> struct VT<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VT<double, 4> { typedef double __attribute__((ext_vector_type(4))) type; };
+template <> struct VT<float, 8> { typedef float __attribute__((ext_vector_type(8))) type; };
 
 template <typename T>
 struct MfArgs {
@@ -90,7 +92,8 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
     const int q = threadIdx.x % G;
     const int64_t bnd = blockIdx.y;
     const T *xq = p.x + bnd * p.bx + q * VEC;
-    const int64_t a = s / p.nd, b = s - a * p.nd;
+    // D < 2^32 (checked at build): 32-bit division, far cheaper than 64-bit
+    const int64_t a = (uint32_t)s / (uint32_t)p.nd, b = s - a * p.nd;
     V zi = (V)0;
     if constexpr (MODE == 2) zi = lds<V, NT>(p.v + bnd * p.bv + s * p.ldv + q * VEC);
     if constexpr (MODE == 3 || MODE == 4) zi = lds<V, NT>(p.z + bnd * p.bz + s * p.ldz + q * VEC);
@@ -125,10 +128,15 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     const int64_t l = blk * RPB + threadIdx.x / G;
     if (l >= p.nlog) return;
     const int64_t per_tile = p.nu * p.tile_b;
-    const int64_t tile = l / per_tile;
-    const int64_t rem = l - tile * per_tile;
-    const int64_t a = rem / p.tile_b;
-    const int64_t b = tile * p.tile_b + (rem - a * p.tile_b);
+    int64_t tile, a;
+    if (p.nlog < (int64_t(1) << 32)) {  // uniform branch: 32-bit divisions
+        tile = (uint32_t)l / (uint32_t)per_tile;
+        a = (uint32_t)(l - tile * per_tile) / (uint32_t)p.tile_b;
+    } else {
+        tile = l / per_tile;
+        a = (l - tile * per_tile) / p.tile_b;
+    }
+    const int64_t b = tile * p.tile_b + (l - tile * per_tile - a * p.tile_b);
     if (b >= p.nd) return;
     const int64_t s = a * p.nd + b;
     const int q = threadIdx.x % G;
@@ -230,6 +238,17 @@ fd_status launch_mf_t(const DevMatrix &M, const T *val_u, const T *val_d, const 
 
 fd_status launch_spmmv_mf(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, const SpmmvTune &tn,
                           hipStream_t s) {
+    if (tn.wide) {  // 32 bytes per lane
+        if (dt == FD_F64) {
+            if (c.nb == 64) return launch_mf_t<double, 4, 16>(M, M.val_u64, M.val_d64, tn, c, s);
+            if (c.nb == 32) return launch_mf_t<double, 4, 8>(M, M.val_u64, M.val_d64, tn, c, s);
+            if (c.nb == 16) return launch_mf_t<double, 4, 4>(M, M.val_u64, M.val_d64, tn, c, s);
+        } else {
+            if (c.nb == 64) return launch_mf_t<float, 8, 8>(M, M.val_u32, M.val_d32, tn, c, s);
+            if (c.nb == 32) return launch_mf_t<float, 8, 4>(M, M.val_u32, M.val_d32, tn, c, s);
+            if (c.nb == 16) return launch_mf_t<float, 8, 2>(M, M.val_u32, M.val_d32, tn, c, s);
+        }
+    }
     if (dt == FD_F64) {
         switch (c.nb) {
             case 1: return launch_mf_t<double, 1, 1>(M, M.val_u64, M.val_d64, tn, c, s);

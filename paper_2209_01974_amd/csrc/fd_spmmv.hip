@@ -279,9 +279,9 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     };
     // matrix-free Hubbard: down-state tile of the up pass, XCD remap on/off
     const SpmmvTune mf_cands[] = {
-        {0, 0, 1, 0, 1, 0, 4},  {0, 0, 1, 0, 1, 0, 8},  {0, 0, 1, 0, 1, 0, 16}, {0, 0, 1, 0, 1, 0, 32},
-        {0, 0, 1, 0, 1, 0, 64}, {0, 1, 1, 0, 1, 0, 2},  {0, 1, 1, 0, 1, 0, 4},  {0, 1, 1, 0, 1, 0, 8},
-        {0, 1, 1, 0, 1, 0, 16}, {0, 1, 1, 0, 1, 0, 64},
+        {0, 0, 1, 0, 1, 0, 16}, {0, 0, 1, 0, 1, 0, 64}, {0, 0, 1, 0, 1, 0, 256}, {0, 1, 1, 0, 1, 0, 4},
+        {0, 1, 1, 0, 1, 0, 16}, {0, 1, 1, 0, 1, 0, 64}, {0, 1, 1, 0, 0, 0, 16}, {0, 0, 1, 0, 0, 0, 64},
+        {0, 1, 1, 0, 1, 1, 16},
     };
     const SpmmvTune *cb = M.matfree ? mf_cands : cands;
     const SpmmvTune *ce = M.matfree ? mf_cands + sizeof(mf_cands) / sizeof(mf_cands[0])

@@ -122,8 +122,9 @@ def test_matfree_filter_fp32_error():
     assert relerr(Vd.cpu().double().numpy(), ref) <= 100 * 2.0 ** -24 * 10
 
 
-@pytest.mark.parametrize("xcd,nt,tile", [(1, 1, 0), (0, 0, 1), (1, 0, 5), (0, 1, 1000), (1, 1, 2)])
-def test_matfree_launch_shapes_bitwise_equal(xcd, nt, tile):
+@pytest.mark.parametrize("xcd,nt,tile,wide", [(1, 1, 0, 0), (0, 0, 1, 0), (1, 0, 5, 0), (0, 1, 1000, 0),
+                                               (1, 1, 2, 0), (0, 1, 64, 1), (1, 1, 3, 1)])
+def test_matfree_launch_shapes_bitwise_equal(xcd, nt, tile, wide):
     m, A = build("hub9")
     X = dev(start_block(A.D, 16, 1))
     Y0 = torch.empty_like(X)
@@ -136,7 +137,7 @@ def test_matfree_launch_shapes_bitwise_equal(xcd, nt, tile):
     W2 = torch.empty_like(Va)
     fd.cheb_filter(m, Va, mu, alpha, beta, W1, W2, 16)
     try:
-        fd.spmmv_tune(0, xcd, 1, 1024, nt, 0, tile)
+        fd.spmmv_tune(0, xcd, 1, 1024, nt, wide, tile)
         Y1 = torch.empty_like(X)
         fd.spmmv(m, X, Y1)
         Vb = dev(V0)
