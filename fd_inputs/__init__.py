@@ -26,3 +26,33 @@ def int_block(D: int, n: int, seed: int = 0, bound: int = 1 << 10) -> np.ndarray
 HUBBARD8 = dict(model="hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0, periodic=True)
 HUBBARD14 = dict(model="hubbard", L=14, n_up=7, n_dn=7, t=1.0, U=8.0, periodic=True)
 ANDERSON200 = dict(model="anderson", L=200, t=1.0, W=16.5, seed=1)
+
+
+def _splitmix64_uniforms(seed: int, n: int) -> list:
+    """The first n outputs of SplitMix64(seed) as doubles in [0, 1) (top 53
+    bits times 2^-53) -- the generator of the Anderson disorder, here only
+    to draw instance parameters."""
+    M = (1 << 64) - 1
+    s = seed & M
+    out = []
+    for _ in range(n):
+        s = (s + 0x9E3779B97F4A7C15) & M
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        z ^= z >> 31
+        out.append((z >> 11) * 2.0 ** -53)
+    return out
+
+
+def anderson_batch(seeds, L_lo: int = 20, L_span: int = 45, W_lo: float = 2.0, W_span: float = 18.0) -> list:
+    """Batched Anderson workload: instance s draws L = L_lo + floor(L_span u0)
+    and W = W_lo + W_span u1 from the first two outputs of SplitMix64(s); its
+    disorder continues on the same stream (skip = 2).  The defaults give
+    L in [20, 64], W in [2, 20)."""
+    out = []
+    for s in seeds:
+        u0, u1 = _splitmix64_uniforms(s, 2)
+        out.append(dict(model="anderson", L=L_lo + int(L_span * u0), t=1.0, W=W_lo + W_span * u1, seed=s,
+                        skip=2))
+    return out

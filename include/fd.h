@@ -68,8 +68,9 @@ typedef enum {
  *   The diagonal U * (number of doubly occupied sites) is always stored.
  *   D = C(L, n_up) C(L, n_dn) (the Hubbard dimension of Sec. 4.1).
  * FD_ANDERSON_3D: site (x,y,z) -> x + L y + L^2 z, periodic nearest-neighbour
- *   hopping -t, on-site energy W (u_i - 1/2), u_i the i-th output of
- *   SplitMix64 seeded with `seed` (top 53 bits times 2^-53), L >= 3.
+ *   hopping -t, on-site energy W (u_{i+skip} - 1/2), u_k the k-th output
+ *   (from 0) of SplitMix64 seeded with `seed` (top 53 bits times 2^-53),
+ *   L >= 3, skip >= 0 (draws already used, e.g. for L and W themselves).
  * FD_DIAGONAL: n entries from `diag` (host).
  * FD_USER_CSR: D rows, rowptr[D+1] (int64), col (uint32, ascending per row),
  *   val (double); host arrays, copied.  D < 2^32.                          */
@@ -84,6 +85,7 @@ typedef struct {
     const int64_t *rowptr;  /* FD_USER_CSR */
     const uint32_t *col;    /* FD_USER_CSR */
     const double *val;      /* FD_USER_CSR */
+    int64_t skip;           /* FD_ANDERSON_3D */
 } fd_model_params;
 
 typedef struct fd_matrix_s *fd_matrix; /* opaque, owned by the library */
@@ -323,6 +325,72 @@ typedef struct {
 fd_status fd_solve(fd_matrix m, const fd_solve_params *params, const double *V0_host,
                    double *evals_host, double *evecs_dev, double *resid_host,
                    fd_solve_stats *stats);
+
+/* ------------------------------------------------------------ batched FD --
+ * Many independent problems in one launch per degree step.  The instance
+ * matrices are stacked into one block-diagonal CSR on the current device:
+ * instance i owns rows [row_off[i], row_off[i+1]) of every batched block
+ * and keeps its own inclusion interval, scaling (alpha_i, beta_i), filter
+ * coefficients and degree (Alg. 1, Alg. 2 caption, applied per instance).
+ * Small problems then share the GPU instead of each being bound by launch
+ * latency.  An opaque handle owned by the library.                          */
+typedef struct fd_batch_s *fd_batch;
+
+/* Stack n_inst (1..65535) matrices built with a stored format (CSR or SELL;
+ * FD_FMT_MATFREE gives FD_ERR_INVALID) into a new batch on the current
+ * device.  The matrices stay the caller's and may be freed afterwards.
+ * Rows and entries in all < 2^32 (else FD_ERR_UNSUPPORTED).                */
+fd_status fd_batch_create(int32_t n_inst, const fd_matrix *mats, fd_batch *out);
+/* Total rows D_total and row_off[n_inst + 1] (host, may be NULL).           */
+fd_status fd_batch_info(fd_batch b, int64_t *D_total, int64_t *row_off);
+void fd_batch_free(fd_batch b);
+
+/* Y = A_i X on the rows of every instance (D_total x nb blocks, as
+ * fd_spmmv).  Synchronizes the stream before returning.                    */
+fd_status fd_batch_spmmv(fd_batch b, fd_dtype dtype, int32_t nb, const void *X_dev, int64_t ldx,
+                         void *Y_dev, int64_t ldy, void *stream);
+
+/* The Chebyshev filter of fd_cheb_filter on every instance at once:
+ * V_i <- p_i[alpha_i A_i + beta_i] V_i.  Host arrays: alpha, beta, degree
+ * (n_inst each) and mu (n_inst x (max_degree + 1), row i = mu_i0 ..
+ * mu_i,max_degree; entries past degree[i] are ignored).  degree[i] = 0
+ * leaves instance i untouched, otherwise 2 <= degree[i] <= max_degree
+ * <= 100000.  All n_bundles bundles of nb columns run in one launch per
+ * degree step: V, W1, W2 are D_total x (nb n_bundles) or wider, pairwise
+ * disjoint.  use_graph != 0: the max_degree launches are captured once into
+ * a HIP graph kept in the handle (captured again when the buffers, shape or
+ * max_degree change) and replayed as one graph launch on `stream`.  The
+ * parameters are copied to the device first (the call synchronizes the
+ * stream for that); the steps are asynchronous.                            */
+fd_status fd_batch_filter(fd_batch b, fd_dtype dtype, int32_t nb, int32_t n_bundles, void *V_dev,
+                          int64_t ldv, const double *mu_host, const int32_t *degree_host,
+                          int32_t max_degree, const double *alpha_host, const double *beta_host,
+                          void *W1_dev, void *W2_dev, int64_t ldw, int32_t use_graph, void *stream);
+
+typedef struct {
+    int32_t iters;         /* outer iterations of the batch                  */
+    int32_t n_converged;   /* instances whose N_t pairs converged            */
+    int64_t graph_launches;/* filter graph replays                           */
+    double t_filter, t_orthog, t_rr, t_total; /* seconds, whole batch        */
+} fd_batch_stats;
+
+/* fd_solve on every instance of the batch (FP64 only: precision must be 0,
+ * else FD_ERR_UNSUPPORTED).  params[n_inst]: nb, n_search, n_target and
+ * ortho must agree; the window, degree (2..100000, no picker), max_iter,
+ * tol, seed and adapt are per instance.  Each outer iteration
+ * orthogonalizes and runs Rayleigh-Ritz instance by instance (one batched
+ * SpMMV for W = A V), drops the instances that converged or reached
+ * max_iter, and filters all others with one graph launch.  V0_host
+ * (D_total x N_s) or NULL (instance i starts from SplitMix64(seed_i)).
+ * Outputs: evals_host[n_inst x N_t] (row i ascending), evecs_dev
+ * (D_total x N_t, ld N_t) or NULL, resid_host[n_inst x N_t] or NULL,
+ * stats[n_inst] or NULL (t_total = time from the start of the batch to the
+ * instance's last Rayleigh-Ritz; t_filter/t_orthog/t_rr are 0 there and
+ * batch-wide in bstats), bstats or NULL.  FD_ERR_NOT_CONVERGED (outputs
+ * written) if any instance reached max_iter.                               */
+fd_status fd_solve_batch(fd_batch b, const fd_solve_params *params, const double *V0_host,
+                         double *evals_host, double *evecs_dev, double *resid_host,
+                         fd_solve_stats *stats, fd_batch_stats *bstats);
 
 const char *fd_last_error(void);
 

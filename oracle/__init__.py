@@ -56,7 +56,7 @@ def lib():
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.orc_hubbard_csr.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                       C.c_double, i64p, u32p, f64p]
-        L.orc_anderson_csr.argtypes = [C.c_int, C.c_double, C.c_double, C.c_uint64,
+        L.orc_anderson_csr.argtypes = [C.c_int, C.c_double, C.c_double, C.c_uint64, C.c_int64,
                                        i64p, u32p, f64p]
         L.orc_sell_size.restype = C.c_int64
         L.orc_sell_size.argtypes = [C.c_int64, i64p, C.c_int, C.c_int, i32p, i64p, i32p]
@@ -136,13 +136,14 @@ def hubbard(L: int, n_up: int, n_dn: int, t: float = 1.0, U: float = 0.0,
     return CSR(D.value, rowptr, col, val)
 
 
-def anderson(L: int, t: float = 1.0, W: float = 0.0, seed: int = 1) -> CSR:
-    """3D Anderson lattice, L^3 sites, periodic, disorder W (u - 1/2)."""
+def anderson(L: int, t: float = 1.0, W: float = 0.0, seed: int = 1, skip: int = 0) -> CSR:
+    """3D Anderson lattice, L^3 sites, periodic, disorder W (u - 1/2), the
+    u drawn in row order after the first `skip` draws of SplitMix64(seed)."""
     D = L ** 3
     rowptr = np.empty(D + 1, np.int64)
     col = np.empty(7 * D, np.uint32)
     val = np.empty(7 * D, np.float64)
-    if lib().orc_anderson_csr(L, t, W, seed, rowptr, col, val):
+    if lib().orc_anderson_csr(L, t, W, seed, skip, rowptr, col, val):
         raise ValueError("invalid Anderson parameters")
     return CSR(D, rowptr, col, val)
 

@@ -221,14 +221,15 @@ int orc_hubbard_csr(int L, int nup, int ndn, int periodic, double t, double U,
 }
 
 /* 3D Anderson lattice, L^3 sites, site (x,y,z) -> i = x + L y + L^2 z,
- * periodic nearest-neighbour hopping -t, on-site energy W (u_i - 1/2) with
- * u_i drawn from SplitMix64(seed) in row order.                           */
-int orc_anderson_csr(int L, double t, double W, uint64_t seed,
+ * periodic nearest-neighbour hopping -t, on-site energy W (u - 1/2) with u
+ * drawn from SplitMix64(seed) in row order after the first `skip` draws.  */
+int orc_anderson_csr(int L, double t, double W, uint64_t seed, int64_t skip,
                      int64_t *rowptr, uint32_t *col, double *val)
 {
-    if (L < 3) return 1;
+    if (L < 3 || skip < 0) return 1;
     int64_t D = (int64_t)L * L * L;
     uint64_t s = seed;
+    for (int64_t k = 0; k < skip; k++) (void)orc_uniform(&s);
     int64_t k = 0;
     rowptr[0] = 0;
     for (int64_t i = 0; i < D; i++) {

@@ -41,7 +41,7 @@ class ModelParams(C.Structure):
     _fields_ = [("model", C.c_int), ("L", C.c_int32), ("n_up", C.c_int32), ("n_dn", C.c_int32),
                 ("periodic", C.c_int32), ("t", C.c_double), ("U", C.c_double), ("W", C.c_double),
                 ("seed", C.c_uint64), ("n", C.c_int64), ("diag", C.c_void_p), ("D", C.c_int64),
-                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p), ("skip", C.c_int64)]
 
 
 class SolveParams(C.Structure):
@@ -56,6 +56,15 @@ class SolveStats(C.Structure):
                 ("spmmv_count", C.c_int64), ("t_filter", C.c_double), ("t_orthog", C.c_double),
                 ("t_rr", C.c_double), ("t_total", C.c_double), ("norm_H", C.c_double),
                 ("max_resid", C.c_double), ("degree", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_converged", C.c_int32), ("graph_launches", C.c_int64),
+                ("t_filter", C.c_double), ("t_orthog", C.c_double), ("t_rr", C.c_double),
+                ("t_total", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +98,11 @@ _SIGS = {
     "fd_mlp_forward": [_P, _I32, _P, _P, _P],
     "fd_mlp_grad": [_P, _I32, _P, _P, _P, _P, _P, _P],
     "fd_mlp_adam": [_P, _P, _P, _P, _I32, C.c_float, C.c_float, _P],
+    "fd_batch_create": [_I32, _P, C.POINTER(_P)],
+    "fd_batch_info": [_P, C.POINTER(_I64), _P],
+    "fd_batch_spmmv": [_P, C.c_int, _I32, _P, _I64, _P, _I64, _P],
+    "fd_batch_filter": [_P, C.c_int, _I32, _I32, _P, _I64, _P, _P, _I32, _P, _P, _P, _P, _I64, _I32, _P],
+    "fd_solve_batch": [_P, _P, _P, _P, _P, _P, _P, C.POINTER(BatchStats)],
 }
 
 
@@ -108,6 +122,8 @@ def lib() -> C.CDLL:
             f.restype = C.c_int
         L.fd_matrix_free.argtypes = [_P]
         L.fd_matrix_free.restype = None
+        L.fd_batch_free.argtypes = [_P]
+        L.fd_batch_free.restype = None
         L.fd_last_error.restype = C.c_char_p
         L.fd_syev_last_sweeps.restype = C.c_int32
         L.fd_syev_last_sweeps.argtypes = []
@@ -197,7 +213,7 @@ class Matrix:
 
 def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host_only: bool = False,
                  L: int = 0, n_up: int = 0, n_dn: int = 0, periodic: bool = True, t: float = 1.0,
-                 U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None) -> Matrix:
+                 U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None, skip: int = 0) -> Matrix:
     """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"} and fmt in
     {"csr", "sell", "matfree"} ("matfree": Hubbard only, C_ = default up-pass tile)."""
     p = ModelParams()
@@ -205,7 +221,7 @@ def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host
     codes = {"hubbard": FD_HUBBARD_RING, "anderson": FD_ANDERSON_3D, "diagonal": FD_DIAGONAL, "csr": FD_USER_CSR}
     p.model = codes[model]
     p.L, p.n_up, p.n_dn, p.periodic = L, n_up, n_dn, int(periodic)
-    p.t, p.U, p.W, p.seed = t, U, W, seed
+    p.t, p.U, p.W, p.seed, p.skip = t, U, W, seed, skip
     if diag is not None:
         d = np.ascontiguousarray(diag, dtype=np.float64)
         keep.append(d)
@@ -416,3 +432,99 @@ def solve(m: Matrix, tau_lo: float, tau_hi: float, n_target: int, n_search: int,
                                    vecs.data_ptr() if vecs is not None else None, rs.ctypes.data,
                                    C.byref(st)), allow=(FD_OK, FD_ERR_NOT_CONVERGED))
     return SolveResult(status, ev, rs, vecs, st.as_dict())
+
+
+# ------------------------------------------------------------------- batched --
+class Batch:
+    """Owning wrapper of an fd_batch handle: the instance matrices stacked as
+    one block-diagonal CSR on the GPU (instance i owns rows off[i]:off[i+1])."""
+
+    def __init__(self, mats):
+        arr = (C.c_void_p * len(mats))(*[m.handle for m in mats])
+        h = C.c_void_p()
+        _check(lib().fd_batch_create(len(mats), arr, C.byref(h)))
+        self._h = h
+        self.n = len(mats)
+        D = _I64()
+        off = np.empty(self.n + 1, np.int64)
+        _check(lib().fd_batch_info(self._h, C.byref(D), off.ctypes.data))
+        self.D, self.off = D.value, off
+        self.lam = [(m.lam_lo, m.lam_hi) for m in mats]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().fd_batch_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def batch_spmmv(b: Batch, X, Y, stream=None) -> None:
+    """Y = A_i X on every instance's rows (fd_batch_spmmv)."""
+    px, ldx, dt = _blk(X, "X")
+    py, ldy, dty = _blk(Y, "Y")
+    if dt != dty or X.shape != Y.shape or X.shape[0] != b.D:
+        raise ValueError("X and Y must be D_total x nb blocks of one dtype")
+    _check(lib().fd_batch_spmmv(b.handle, dt, X.shape[1], px, ldx, py, ldy, _stream(stream)))
+
+
+def batch_filter(b: Batch, V, mu, degree, alpha, beta, W1, W2, nb: int, use_graph: bool = True,
+                 stream=None) -> None:
+    """fd_batch_filter: mu is a list of per-instance coefficient arrays (the
+    length of mu[i] minus one is instance i's degree, 0 entries: idle)."""
+    pv, ldv, dt = _blk(V, "V")
+    p1, ldw, _ = _blk(W1, "W1")
+    p2, ldw2, _ = _blk(W2, "W2")
+    if ldw != ldw2 or V.shape[1] % nb:
+        raise ValueError("W1 and W2 need one leading dimension; V's width a multiple of nb")
+    dmax = max(int(d) for d in degree)
+    M = np.zeros((b.n, dmax + 1))
+    for i, m in enumerate(mu):
+        m = np.asarray(m, dtype=np.float64)
+        M[i, :m.size] = m
+    deg = np.ascontiguousarray(degree, dtype=np.int32)
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    _check(lib().fd_batch_filter(b.handle, dt, nb, V.shape[1] // nb, pv, ldv, M.ctypes.data, deg.ctypes.data,
+                                 dmax, al.ctypes.data, be.ctypes.data, p1, p2, ldw, int(use_graph),
+                                 _stream(stream)))
+
+
+class BatchResult:
+    def __init__(self, status, evals, resid, evecs, stats, bstats):
+        self.status, self.evals, self.resid, self.evecs = status, evals, resid, evecs
+        self.stats, self.bstats = stats, bstats
+
+
+def solve_batch(b: Batch, params: list, V0: np.ndarray | None = None, want_vectors: bool = False) -> BatchResult:
+    """fd_solve_batch.  params: one dict per instance with the keys of
+    solve() (tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol,
+    seed, adapt; precision 0)."""
+    import torch
+    P = (SolveParams * b.n)()
+    for i, q in enumerate(params):
+        P[i] = SolveParams(q["tau_lo"], q["tau_hi"], q["n_target"], q["n_search"], q["nb"], q["degree"],
+                           q.get("max_iter", 50), q.get("tol", 1e-9), 0, q.get("ortho", FD_ORTHO_SVQB2),
+                           q.get("seed", 0), q.get("adapt", 0), None)
+    nt = params[0]["n_target"]
+    ev = np.full((b.n, nt), np.nan)
+    rs = np.full((b.n, nt), np.nan)
+    vecs = torch.empty((b.D, nt), dtype=torch.float64, device="cuda") if want_vectors else None
+    v0p = None
+    if V0 is not None:
+        V0 = np.ascontiguousarray(V0, dtype=np.float64)
+        if V0.shape != (b.D, params[0]["n_search"]):
+            raise ValueError("V0 must be D_total x n_search")
+        v0p = V0.ctypes.data
+    st = (SolveStats * b.n)()
+    bs = BatchStats()
+    torch.cuda.synchronize()
+    status = _check(lib().fd_solve_batch(b.handle, P, v0p, ev.ctypes.data,
+                                         vecs.data_ptr() if vecs is not None else None, rs.ctypes.data,
+                                         st, C.byref(bs)), allow=(FD_OK, FD_ERR_NOT_CONVERGED))
+    return BatchResult(status, ev, rs, vecs, [x.as_dict() for x in st], bs.as_dict())

@@ -280,18 +280,12 @@ fd_status orthog_impl(int64_t D, int ns, double *V, int64_t ldv, int method, uin
     return FD_OK;
 }
 
-fd_status rr_impl(fd_matrix m, int ns, int nb, double *V, double *W, int64_t ld, double *theta_host,
-                  double *resid_host, hipStream_t s) {
-    const int64_t D = m->dev.D;
+// Rayleigh-Ritz once W = A V is in place: H = V^t W, H = Y Theta Y^t,
+// V <- V Y, W <- W Y, rho_j = ||W_j - theta_j V_j||; theta and rho to the host.
+fd_status rr_dense(int64_t D, int ns, double *V, double *W, int64_t ld, double *theta_host, double *resid_host,
+                   hipStream_t s) {
     Small b;
     FD_TRY(small_buffers(ns, b));
-    SpmmvCall c;
-    c.mode = 0;
-    c.nb = nb;
-    c.nbundles = ns / nb;
-    c.x = V; c.ldx = ld; c.bx = nb;
-    c.y = W; c.ldy = ld; c.by = nb;
-    FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
     FD_TRY(gram(D, ns, ns, V, ld, W, ld, b.G, ns, false, s));
     FD_TRY(symmetrize(ns, b.G, s));
     FD_TRY(syev(ns, b.G, ns, b.theta, b.Q, ns, s));
@@ -302,6 +296,18 @@ fd_status rr_impl(fd_matrix m, int ns, int nb, double *V, double *W, int64_t ld,
     FD_HIP(hipMemcpyAsync(resid_host, b.rho, ns * sizeof(double), hipMemcpyDeviceToHost, s));
     FD_HIP(hipStreamSynchronize(s));
     return FD_OK;
+}
+
+fd_status rr_impl(fd_matrix m, int ns, int nb, double *V, double *W, int64_t ld, double *theta_host,
+                  double *resid_host, hipStream_t s) {
+    SpmmvCall c;
+    c.mode = 0;
+    c.nb = nb;
+    c.nbundles = ns / nb;
+    c.x = V; c.ldx = ld; c.bx = nb;
+    c.y = W; c.ldy = ld; c.by = nb;
+    FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
+    return rr_dense(m->dev.D, ns, V, W, ld, theta_host, resid_host, s);
 }
 
 double now() {
@@ -366,6 +372,147 @@ struct DevBuf {
 }  // namespace
 }  // namespace fd
 
+// Batched problems: a block-diagonal stack of instance matrices on one device.
+struct fd_batch_s {
+    int device = -1;
+    std::vector<int64_t> off;  // n_inst + 1 row offsets
+    std::vector<double> lam_lo, lam_hi;
+    fd::BatchDev dev;
+    int32_t mu_cap = 0;  // entries allocated in dev.mu
+    hipStream_t cap = nullptr;  // capture-only stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct Key {
+        int dt = -1, nb = 0, nbund = 0, max_degree = 0;
+        const void *V = nullptr, *W1 = nullptr, *W2 = nullptr;
+        int64_t ldv = 0, ldw = 0;
+        bool operator==(const Key &o) const {
+            return dt == o.dt && nb == o.nb && nbund == o.nbund && max_degree == o.max_degree && V == o.V &&
+                   W1 == o.W1 && W2 == o.W2 && ldv == o.ldv && ldw == o.ldw;
+        }
+    } key;
+    int64_t graph_launches = 0, graph_captures = 0;
+};
+
+namespace fd {
+namespace {
+
+void batch_release(fd_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    BatchDev &d = b->dev;
+    void *bufs[] = {d.ptr, d.col, d.val64, d.val32, d.inst, d.alpha, d.beta, d.deg, d.act, d.mu};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    d = BatchDev();
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->cap = nullptr;
+}
+
+// Per-instance filter parameters to the device (ordered on stream s).
+fd_status batch_params(fd_batch b, const double *alpha, const double *beta, const int32_t *deg,
+                       const int32_t *act, const double *mu, int32_t mstride, hipStream_t s) {
+    BatchDev &d = b->dev;
+    const int n = d.n_inst;
+    if (mu && (int64_t)n * mstride > b->mu_cap) {
+        FD_HIP(hipStreamSynchronize(s));
+        if (d.mu) (void)hipFree(d.mu);
+        d.mu = nullptr;
+        b->mu_cap = 0;
+        FD_HIP(hipMalloc(&d.mu, (size_t)n * mstride * sizeof(double)));
+        b->mu_cap = n * mstride;
+    }
+    if (alpha) FD_HIP(hipMemcpyAsync(d.alpha, alpha, n * sizeof(double), hipMemcpyHostToDevice, s));
+    if (beta) FD_HIP(hipMemcpyAsync(d.beta, beta, n * sizeof(double), hipMemcpyHostToDevice, s));
+    if (deg) FD_HIP(hipMemcpyAsync(d.deg, deg, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (act) FD_HIP(hipMemcpyAsync(d.act, act, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (mu) {
+        FD_HIP(hipMemcpyAsync(d.mu, mu, (size_t)n * mstride * sizeof(double), hipMemcpyHostToDevice, s));
+        d.mstride = mstride;
+    }
+    // the host arrays may be temporaries of the caller
+    FD_HIP(hipStreamSynchronize(s));
+    return FD_OK;
+}
+
+// The degree steps of the filter on every instance (Alg. 2 caption): step 1
+// W2 = T_1 V, step 2 W1 = T_2 V and V = mu_0 V + mu_1 W2 + mu_2 W1, steps
+// k >= 3 prev = 2 B cur - prev in place and V += mu_k prev.  Each instance
+// stops after its own degree.  All bundles in one launch per step.
+fd_status batch_filter_steps(const BatchDev &B, fd_dtype dt, int nb, int nbund, char *V, int64_t ldv,
+                             int max_degree, char *W1, char *W2, int64_t ldw, hipStream_t s) {
+    BatchCall c;
+    c.nb = nb;
+    c.nbundles = nbund;
+    c.mode = 1;
+    c.k = 1;
+    c.x = V; c.ldx = ldv; c.bx = nb;
+    c.y = W2; c.ldy = ldw; c.by = nb;
+    FD_TRY(launch_batch(B, dt, c, s));
+    c.mode = 2;
+    c.k = 2;
+    c.x = W2; c.ldx = ldw; c.bx = nb;
+    c.y = W1; c.ldy = ldw; c.by = nb;
+    c.v = V; c.ldv = ldv; c.bv = nb;
+    FD_TRY(launch_batch(B, dt, c, s));
+    char *cur = W1, *prev = W2;
+    for (int k = 3; k <= max_degree; k++) {
+        c.mode = 3;
+        c.k = k;
+        c.x = cur; c.ldx = ldw; c.bx = nb;
+        c.z = prev; c.ldz = ldw; c.bz = nb;
+        c.y = prev; c.ldy = ldw; c.by = nb;
+        FD_TRY(launch_batch(B, dt, c, s));
+        std::swap(cur, prev);
+    }
+    return FD_OK;
+}
+
+// Run the steps eagerly, or as one replay of a HIP graph captured on the
+// handle's private stream (re-captured when buffers, shape or degree change).
+fd_status batch_filter_run(fd_batch b, fd_dtype dt, int nb, int nbund, char *V, int64_t ldv, int max_degree,
+                           char *W1, char *W2, int64_t ldw, bool use_graph, hipStream_t s) {
+    if (!use_graph) return batch_filter_steps(b->dev, dt, nb, nbund, V, ldv, max_degree, W1, W2, ldw, s);
+    fd_batch_s::Key k;
+    k.dt = (int)dt;
+    k.nb = nb;
+    k.nbund = nbund;
+    k.max_degree = max_degree;
+    k.V = V;
+    k.W1 = W1;
+    k.W2 = W2;
+    k.ldv = ldv;
+    k.ldw = ldw;
+    if (!b->exec || !(k == b->key)) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        if (!b->cap) FD_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        FD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        fd_status st = batch_filter_steps(b->dev, dt, nb, nbund, V, ldv, max_degree, W1, W2, ldw, b->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (st != FD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "batched filter: graph capture");
+        b->graph = g;
+        FD_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->key = k;
+        b->graph_captures++;
+    }
+    FD_HIP(hipGraphLaunch(b->exec, s));
+    b->graph_launches++;
+    return FD_OK;
+}
+
+}  // namespace
+}  // namespace fd
+
 using namespace fd;
 
 extern "C" {
@@ -407,7 +554,7 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
     }
     switch (p->model) {
         case FD_HUBBARD_RING: st = build_hubbard(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->csr); break;
-        case FD_ANDERSON_3D: st = build_anderson(p->L, p->t, p->W, p->seed, m->csr); break;
+        case FD_ANDERSON_3D: st = build_anderson(p->L, p->t, p->W, p->seed, p->skip, m->csr); break;
         case FD_DIAGONAL: st = build_diagonal(p->n, p->diag, m->csr); break;
         case FD_USER_CSR: st = build_user(p->D, p->rowptr, p->col, p->val, m->csr); break;
         default: st = fail(FD_ERR_INVALID, "fd_build_matrix: unknown model");
@@ -876,6 +1023,306 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     st.t_total = now() - t0;
     if (stats) *stats = st;
     if (!converged) return fail(FD_ERR_NOT_CONVERGED, "fd_solve: not converged within max_iter");
+    return FD_OK;
+}
+
+// ------------------------------------------------------------- batched FD --
+fd_status fd_batch_create(int32_t n_inst, const fd_matrix *mats, fd_batch *out) {
+    if (!mats || !out || n_inst < 1 || n_inst > 65535)
+        return fail(FD_ERR_INVALID, "fd_batch_create: need 1 <= n_inst <= 65535 and arrays");
+    int64_t D = 0, nnz = 0;
+    for (int i = 0; i < n_inst; i++) {
+        const fd_matrix m = mats[i];
+        if (!m) return fail(FD_ERR_INVALID, "fd_batch_create: null matrix");
+        if (m->fmt == FD_FMT_MATFREE) return fail(FD_ERR_INVALID, "fd_batch_create: matrix-free matrices have no CSR");
+        D += m->csr.D;
+        nnz += m->csr.rowptr[m->csr.D];
+    }
+    if (D >= (int64_t)UINT32_MAX || nnz >= (int64_t)UINT32_MAX)
+        return fail(FD_ERR_UNSUPPORTED, "fd_batch_create: more than 2^32 rows or entries in all");
+    fd_batch b = new (std::nothrow) fd_batch_s;
+    if (!b) return fail(FD_ERR_OOM, "fd_batch_create: host allocation");
+    b->off.assign(n_inst + 1, 0);
+    std::vector<uint32_t> ptr(D + 1), col(nnz);
+    std::vector<double> val(nnz);
+    std::vector<uint16_t> inst(D);
+    int64_t r = 0, e = 0;
+    for (int i = 0; i < n_inst; i++) {
+        const HostCSR &A = mats[i]->csr;
+        b->lam_lo.push_back(mats[i]->lam_lo);
+        b->lam_hi.push_back(mats[i]->lam_hi);
+        for (int64_t row = 0; row < A.D; row++) {
+            ptr[r + row] = (uint32_t)(e + A.rowptr[row]);
+            inst[r + row] = (uint16_t)i;
+        }
+        const int64_t n = A.rowptr[A.D];
+        for (int64_t j = 0; j < n; j++) {
+            col[e + j] = (uint32_t)(r + A.col[j]);
+            val[e + j] = A.val[j];
+        }
+        r += A.D;
+        e += n;
+        b->off[i + 1] = r;
+    }
+    ptr[D] = (uint32_t)e;
+    std::vector<float> v32(val.begin(), val.end());
+    BatchDev &d = b->dev;
+    d.n_inst = n_inst;
+    d.D = D;
+    fd_status st = FD_OK;
+    auto put = [&](void **dst, const void *src, size_t bytes) {
+        if (st != FD_OK) return;
+        if (hipMalloc(dst, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            *dst = nullptr;
+            st = fail(FD_ERR_OOM, "fd_batch_create: device allocation");
+            return;
+        }
+        if (src && bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(FD_ERR_HIP, "fd_batch_create: copy to device");
+    };
+    put((void **)&d.ptr, ptr.data(), ptr.size() * sizeof(uint32_t));
+    put((void **)&d.col, col.data(), col.size() * sizeof(uint32_t));
+    put((void **)&d.val64, val.data(), val.size() * sizeof(double));
+    put((void **)&d.val32, v32.data(), v32.size() * sizeof(float));
+    put((void **)&d.inst, inst.data(), inst.size() * sizeof(uint16_t));
+    std::vector<int32_t> ones(n_inst, 1), zeros(n_inst, 0);
+    std::vector<double> dz(n_inst, 0.0);
+    put((void **)&d.alpha, dz.data(), n_inst * sizeof(double));
+    put((void **)&d.beta, dz.data(), n_inst * sizeof(double));
+    put((void **)&d.deg, zeros.data(), n_inst * sizeof(int32_t));
+    put((void **)&d.act, ones.data(), n_inst * sizeof(int32_t));
+    if (st == FD_OK && hipGetDevice(&b->device) != hipSuccess) st = fail(FD_ERR_HIP, "fd_batch_create: device");
+    if (st != FD_OK) {
+        batch_release(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FD_OK;
+}
+
+fd_status fd_batch_info(fd_batch b, int64_t *D_total, int64_t *row_off) {
+    if (!b) return fail(FD_ERR_INVALID, "fd_batch_info: null handle");
+    if (D_total) *D_total = b->dev.D;
+    if (row_off) std::copy(b->off.begin(), b->off.end(), row_off);
+    return FD_OK;
+}
+
+void fd_batch_free(fd_batch b) {
+    if (!b) return;
+    batch_release(b);
+    delete b;
+}
+
+fd_status fd_batch_spmmv(fd_batch b, fd_dtype dt, int32_t nb, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                         void *stream) {
+    if (!b) return fail(FD_ERR_INVALID, "fd_batch_spmmv: null handle");
+    if (dt != FD_F64 && dt != FD_F32) return fail(FD_ERR_INVALID, "fd_batch_spmmv: bad dtype");
+    if (!nb_ok(nb)) return fail(FD_ERR_INVALID, "fd_batch_spmmv: nb must be one of 1, 2, 4, 8, 16, 32, 64");
+    FD_TRY(check_block(X, ldx, nb, dt, nb, "fd_batch_spmmv X"));
+    FD_TRY(check_block(Y, ldy, nb, dt, nb, "fd_batch_spmmv Y"));
+    if (overlap(X, ldx, Y, ldy, b->dev.D, esize(dt))) return fail(FD_ERR_INVALID, "fd_batch_spmmv: X and Y overlap");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> ones(b->dev.n_inst, 1);
+    FD_TRY(batch_params(b, nullptr, nullptr, nullptr, ones.data(), nullptr, 0, s));
+    BatchCall c;
+    c.mode = 0;
+    c.nb = nb;
+    c.x = X; c.ldx = ldx; c.bx = nb;
+    c.y = Y; c.ldy = ldy; c.by = nb;
+    return launch_batch(b->dev, dt, c, s);
+}
+
+fd_status fd_batch_filter(fd_batch b, fd_dtype dt, int32_t nb, int32_t n_bundles, void *V, int64_t ldv,
+                          const double *mu, const int32_t *degree, int32_t max_degree, const double *alpha,
+                          const double *beta, void *W1, void *W2, int64_t ldw, int32_t use_graph, void *stream) {
+    if (!b || !mu || !degree || !alpha || !beta) return fail(FD_ERR_INVALID, "fd_batch_filter: null argument");
+    if (dt != FD_F64 && dt != FD_F32) return fail(FD_ERR_INVALID, "fd_batch_filter: bad dtype");
+    if (!nb_ok(nb) || n_bundles < 1 || n_bundles > 65535 || max_degree < 2 || max_degree > 100000)
+        return fail(FD_ERR_INVALID, "fd_batch_filter: bad nb, n_bundles or max_degree");
+    const int n = b->dev.n_inst;
+    for (int i = 0; i < n; i++)
+        if (degree[i] != 0 && (degree[i] < 2 || degree[i] > max_degree))
+            return fail(FD_ERR_INVALID, "fd_batch_filter: degree[i] must be 0 or in [2, max_degree]");
+    const int64_t w = (int64_t)nb * n_bundles;
+    FD_TRY(check_block(V, ldv, w, dt, nb, "fd_batch_filter V"));
+    FD_TRY(check_block(W1, ldw, w, dt, nb, "fd_batch_filter W1"));
+    FD_TRY(check_block(W2, ldw, w, dt, nb, "fd_batch_filter W2"));
+    const int64_t D = b->dev.D;
+    const size_t es = esize(dt);
+    if (overlap(V, ldv, W1, ldw, D, es) || overlap(V, ldv, W2, ldw, D, es) || overlap(W1, ldw, W2, ldw, D, es))
+        return fail(FD_ERR_INVALID, "fd_batch_filter: V, W1 and W2 must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    FD_TRY(batch_params(b, alpha, beta, degree, nullptr, mu, max_degree + 1, s));
+    return batch_filter_run(b, dt, nb, n_bundles, (char *)V, ldv, max_degree, (char *)W1, (char *)W2, ldw,
+                            use_graph != 0, s);
+}
+
+fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0, double *evals, double *evecs,
+                         double *resid, fd_solve_stats *stats, fd_batch_stats *bstats) {
+    if (!b || !P || !evals) return fail(FD_ERR_INVALID, "fd_solve_batch: null argument");
+    const int n = b->dev.n_inst;
+    const int nb = P[0].nb, ns = P[0].n_search, nt = P[0].n_target, ortho = P[0].ortho;
+    if (!nb_ok(nb) || ns < nb || ns % nb || ns > 512 || nt < 1 || nt > ns)
+        return fail(FD_ERR_INVALID, "fd_solve_batch: need nb in {1..64}, N_s a multiple of nb, N_t <= N_s <= 512");
+    for (int i = 0; i < n; i++) {
+        const fd_solve_params &p = P[i];
+        if (p.nb != nb || p.n_search != ns || p.n_target != nt || p.ortho != ortho)
+            return fail(FD_ERR_INVALID, "fd_solve_batch: nb, N_s, N_t and ortho must agree across instances");
+        if (p.precision != 0) return fail(FD_ERR_UNSUPPORTED, "fd_solve_batch: FP64 only (precision 0)");
+        if (p.degree < 2 || p.degree > 100000) return fail(FD_ERR_INVALID, "fd_solve_batch: degree must be in [2, 1e5]");
+        if (p.max_iter < 0 || !(p.tol > 0) || (p.adapt != 0 && p.adapt != 1))
+            return fail(FD_ERR_INVALID, "fd_solve_batch: bad max_iter, tol or adapt");
+        if (!(p.tau_lo <= p.tau_hi) || p.tau_lo < b->lam_lo[i] || p.tau_hi > b->lam_hi[i] ||
+            !(b->lam_hi[i] > b->lam_lo[i]))
+            return fail(FD_ERR_INVALID, "fd_solve_batch: window must satisfy lam_lo <= tau_lo <= tau_hi <= lam_hi");
+        if (ns > b->off[i + 1] - b->off[i]) return fail(FD_ERR_INVALID, "fd_solve_batch: N_s > D of an instance");
+    }
+    const double t0 = now();
+    const int64_t D = b->dev.D;
+    hipStream_t s = nullptr;
+    int max_degree = 0;
+    for (int i = 0; i < n; i++) max_degree = std::max(max_degree, P[i].degree);
+    const int mstride = max_degree + 1;
+    std::vector<double> alpha(n), beta(n), normH(n), mu((size_t)n * mstride, 0.0);
+    std::vector<int32_t> deg(n), act(n, 1);
+    // coefficients of instance i for the target window [wlo, whi]
+    auto set_coeffs = [&](int i, double wlo, double whi) -> fd_status {
+        double *m = mu.data() + (size_t)i * mstride;
+        const double a = std::max(-1.0, std::min(1.0, alpha[i] * wlo + beta[i]));
+        if (whi > wlo) return cheb_coeffs(0, a, std::max(a, std::min(1.0, alpha[i] * whi + beta[i])), P[i].degree, m);
+        return cheb_coeffs(1, a, 0.0, P[i].degree, m);
+    };
+    for (int i = 0; i < n; i++) {
+        const double lo = b->lam_lo[i], hi = b->lam_hi[i];
+        alpha[i] = 2.0 / (hi - lo);
+        beta[i] = -(hi + lo) / (hi - lo);
+        normH[i] = std::max(std::fabs(lo), std::fabs(hi));
+        deg[i] = P[i].degree;
+        FD_TRY(set_coeffs(i, P[i].tau_lo, P[i].tau_hi));
+    }
+    DevBuf V, W, W1, W2;
+    FD_TRY(V.alloc((size_t)D * ns * 8, "V"));
+    FD_TRY(W.alloc((size_t)D * ns * 8, "W"));
+    FD_TRY(W1.alloc((size_t)D * ns * 8, "W1"));
+    FD_TRY(W2.alloc((size_t)D * ns * 8, "W2"));
+    double *Vd = (double *)V.p, *Wd = (double *)W.p;
+    if (V0) {
+        FD_HIP(hipMemcpy(Vd, V0, (size_t)D * ns * 8, hipMemcpyHostToDevice));
+    } else {
+        for (int i = 0; i < n; i++)
+            FD_TRY(fill_normal(b->off[i + 1] - b->off[i], ns, Vd + b->off[i] * ns, ns, P[i].seed, s));
+    }
+    FD_TRY(batch_params(b, alpha.data(), beta.data(), deg.data(), act.data(), mu.data(), mstride, s));
+    std::vector<fd_solve_stats> st(n);
+    std::vector<std::vector<double>> th(n, std::vector<double>(ns)), rho(n, std::vector<double>(ns));
+    std::vector<std::vector<int>> sel(n);
+    std::vector<char> conv(n, 0), done(n, 0);
+    for (int i = 0; i < n; i++) {
+        std::memset(&st[i], 0, sizeof(fd_solve_stats));
+        st[i].norm_H = normH[i];
+        st[i].degree = P[i].degree;
+    }
+    fd_batch_stats bs;
+    std::memset(&bs, 0, sizeof(bs));
+    const int64_t launches0 = b->graph_launches;
+    int n_active = n;
+    for (int it = 0; n_active > 0; it++) {
+        double ta = now();
+        for (int i = 0; i < n; i++) {
+            if (done[i]) continue;
+            const int64_t Di = b->off[i + 1] - b->off[i];
+            int rank = 0;
+            FD_TRY(orthog_impl(Di, ns, Vd + b->off[i] * ns, ns, ortho, P[i].seed + 0x1000 + it, &rank, s));
+        }
+        FD_HIP(hipStreamSynchronize(s));
+        double tb = now();
+        bs.t_orthog += tb - ta;
+        // W = A V for every active instance in one launch, then the dense
+        // Rayleigh-Ritz steps instance by instance
+        BatchCall c;
+        c.mode = 0;
+        c.nb = nb;
+        c.nbundles = ns / nb;
+        c.x = Vd; c.ldx = ns; c.bx = nb;
+        c.y = Wd; c.ldy = ns; c.by = nb;
+        FD_TRY(launch_batch(b->dev, FD_F64, c, s));
+        n_active = 0;
+        for (int i = 0; i < n; i++) {
+            if (done[i]) continue;
+            const int64_t Di = b->off[i + 1] - b->off[i];
+            FD_TRY(rr_dense(Di, ns, Vd + b->off[i] * ns, Wd + b->off[i] * ns, ns, th[i].data(), rho[i].data(), s));
+            st[i].spmmv_count += ns / nb;
+            for (int j = 0; j < ns; j++)
+                if (!std::isfinite(th[i][j]) || !std::isfinite(rho[i][j]))
+                    return fail(FD_ERR_BREAKDOWN, "fd_solve_batch: non-finite Ritz data");
+            const fd_solve_params &p = P[i];
+            sel[i] = select_targets(th[i], p.tau_lo, p.tau_hi, nt);
+            double mx = (int)sel[i].size() == nt ? 0.0 : INFINITY;
+            for (int j : sel[i]) mx = std::max(mx, rho[i][j]);
+            const double tol = p.tol * normH[i];
+            st[i].n_conv = 0;
+            for (int j = 0; j < ns; j++)
+                if ((p.tau_hi <= p.tau_lo || (th[i][j] >= p.tau_lo && th[i][j] <= p.tau_hi)) && rho[i][j] <= tol)
+                    st[i].n_conv++;
+            conv[i] = (int)sel[i].size() == nt && mx <= tol;
+            if (conv[i] || st[i].iters >= p.max_iter) {
+                done[i] = 1;
+                act[i] = 0;
+                deg[i] = 0;
+                st[i].t_total = now() - t0;
+                continue;
+            }
+            n_active++;
+            if (p.adapt == 1 && p.tau_hi > p.tau_lo && (int)sel[i].size() == nt) {
+                const double tau = 0.5 * (p.tau_lo + p.tau_hi);
+                const double r = std::fabs(th[i][sel[i].back()] - tau);
+                FD_TRY(set_coeffs(i, std::max(p.tau_lo, tau - r), std::min(p.tau_hi, tau + r)));
+            }
+        }
+        bs.t_rr += now() - tb;
+        if (n_active == 0) break;
+        double tf = now();
+        FD_TRY(batch_params(b, nullptr, nullptr, deg.data(), act.data(), mu.data(), mstride, s));
+        FD_TRY(batch_filter_run(b, FD_F64, nb, ns / nb, (char *)Vd, ns, max_degree, (char *)W1.p, (char *)W2.p,
+                                ns, true, s));
+        FD_HIP(hipStreamSynchronize(s));
+        bs.t_filter += now() - tf;
+        for (int i = 0; i < n; i++)
+            if (!done[i]) {
+                st[i].spmmv_count += (int64_t)P[i].degree * (ns / nb);
+                st[i].iters++;
+            }
+        bs.iters = it + 1;
+    }
+    // results: selected pairs of each instance sorted by eigenvalue
+    bool all = true;
+    for (int i = 0; i < n; i++) {
+        std::vector<int> order(sel[i]);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return th[i][x] < th[i][y]; });
+        const int nret = (int)order.size();
+        st[i].max_resid = 0.0;
+        for (int k = 0; k < nt; k++) {
+            evals[(size_t)i * nt + k] = k < nret ? th[i][order[k]] : NAN;
+            if (resid) resid[(size_t)i * nt + k] = k < nret ? rho[i][order[k]] : NAN;
+            if (k < nret) st[i].max_resid = std::max(st[i].max_resid, rho[i][order[k]]);
+        }
+        if (evecs && nret > 0) {
+            int *idx = (int *)workspace(nret * sizeof(int), 4);
+            if (!idx) return fail(FD_ERR_OOM, "fd_solve_batch: index workspace");
+            FD_HIP(hipMemcpy(idx, order.data(), nret * sizeof(int), hipMemcpyHostToDevice));
+            FD_TRY(gather_cols(b->off[i + 1] - b->off[i], nret, Vd + b->off[i] * ns, ns, idx,
+                               evecs + b->off[i] * nt, nt, s));
+            FD_HIP(hipStreamSynchronize(s));
+        }
+        if (conv[i]) bs.n_converged++;
+        all = all && conv[i];
+    }
+    bs.t_total = now() - t0;
+    bs.graph_launches = b->graph_launches - launches0;
+    if (stats) std::copy(st.begin(), st.end(), stats);
+    if (bstats) *bstats = bs;
+    if (!all) return fail(FD_ERR_NOT_CONVERGED, "fd_solve_batch: some instances did not converge within max_iter");
     return FD_OK;
 }
 

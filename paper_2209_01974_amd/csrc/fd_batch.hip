@@ -1,0 +1,179 @@
+// Batched sparse kernels on gfx950: many independent FD problems stacked as
+// one block-diagonal CSR matrix.  Instance i owns rows [off_i, off_{i+1}),
+// its columns are shifted by off_i, and it brings its own scaling
+// (alpha_i, beta_i, Alg. 2 caption), filter coefficients mu_i and degree n_i.
+// One launch per degree step serves every instance and every bundle, so
+// small problems share the GPU instead of each paying for its own launches.
+// Rows of an instance whose degree is below the step return at once.
+//
+// Lane mapping as in the single-matrix kernel: a row of nb values is split
+// over G lanes of VEC values (16 bytes); blockIdx.y selects the bundle.
+// Row groups are dealt to the 8 XCDs in interleaved chunks of CHUNK rows, so
+// that the near neighbours of a row (+-1, +-L for a 3D stencil) stay in one
+// XCD's L2.
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+template <typename T, int VEC> struct BV;
+template <> struct BV<double, 1> { typedef double type; };
+template <> struct BV<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct BV<float, 1> { typedef float type; };
+template <> struct BV<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct BV<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+
+constexpr int CHUNK = 1024;  // rows per XCD chunk
+
+template <typename T>
+struct BArgs {
+    int64_t D;
+    int32_t k, mstride;
+    const uint32_t *__restrict__ ptr;
+    const uint32_t *__restrict__ col;
+    const T *__restrict__ val;
+    const uint16_t *__restrict__ inst;
+    const double *__restrict__ alpha;
+    const double *__restrict__ beta;
+    const int32_t *__restrict__ deg;
+    const int32_t *__restrict__ act;
+    const double *__restrict__ mu;
+    const T *x; int64_t ldx, bx;
+    T *y; int64_t ldy, by;
+    const T *z; int64_t ldz, bz;
+    T *v; int64_t ldv, bv;
+};
+
+template <typename V>
+__device__ __forceinline__ V ldg(const void *p) { return *reinterpret_cast<const V *>(p); }
+template <typename V>
+__device__ __forceinline__ V ldn(const void *p) { return __builtin_nontemporal_load(reinterpret_cast<const V *>(p)); }
+template <typename V>
+__device__ __forceinline__ void stn(void *p, V x) { __builtin_nontemporal_store(x, reinterpret_cast<V *>(p)); }
+
+// MODE 0: y = A x (rows of active instances)
+// MODE 1: y = alpha_i A x + beta_i x
+// MODE 2: t = 2 alpha_i A x + 2 beta_i x - v; y = t; v = mu_i0 v + mu_i1 x + mu_i2 t
+// MODE 3: t = 2 alpha_i A x + 2 beta_i x - z; y = t (in place over z); v += mu_ik t
+template <typename T, int VEC, int G, int MODE>
+__global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
+    typedef typename BV<T, VEC>::type V;
+    constexpr int RPB = 256 / G;
+    constexpr int64_t CB = CHUNK / RPB;  // blocks per chunk (a power of two)
+    // block -> row group: XCD x = b % 8 works through chunks x, x+8, ...
+    const int64_t b = blockIdx.x;
+    const int64_t j = b >> 3, c = j / CB;
+    const int64_t rg = ((c << 3) + (b & 7)) * CB + (j - c * CB);
+    const int64_t row = rg * RPB + threadIdx.x / G;
+    if (row >= p.D) return;
+    const int i = p.inst[row];
+    if constexpr (MODE == 0) {
+        if (!p.act[i]) return;
+    } else {
+        if (p.k > p.deg[i]) return;
+    }
+    const int q = threadIdx.x % G;
+    const int64_t bnd = blockIdx.y;
+    const T *xq = p.x + bnd * p.bx + q * VEC;
+    V zi = (V)0, vi = (V)0;
+    T *vr = nullptr;
+    if constexpr (MODE >= 2) {
+        vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
+        vi = ldn<V>(vr);
+    }
+    if constexpr (MODE == 3) zi = ldn<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+    const uint32_t j0 = p.ptr[row], j1 = p.ptr[row + 1];
+    V acc0 = (V)0, acc1 = (V)0;
+    uint32_t jj = j0;
+    for (; jj + 2 <= j1; jj += 2) {
+        const uint32_t c0 = p.col[jj], c1 = p.col[jj + 1];
+        const T e0 = p.val[jj], e1 = p.val[jj + 1];
+        acc0 += e0 * ldg<V>(xq + (int64_t)c0 * p.ldx);
+        acc1 += e1 * ldg<V>(xq + (int64_t)c1 * p.ldx);
+    }
+    if (jj < j1) acc0 += p.val[jj] * ldg<V>(xq + (int64_t)p.col[jj] * p.ldx);
+    const V acc = acc0 + acc1;
+    T *yr = p.y + bnd * p.by + row * p.ldy + q * VEC;
+    if constexpr (MODE == 0) {
+        stn<V>(yr, acc);
+    } else {
+        const V xi = ldg<V>(xq + row * p.ldx);
+        const double sc = MODE == 1 ? 1.0 : 2.0;
+        const T a = (T)(sc * p.alpha[i]), bb = (T)(sc * p.beta[i]);
+        V t = a * acc + bb * xi;
+        if constexpr (MODE == 1) {
+            stn<V>(yr, t);
+        } else if constexpr (MODE == 2) {
+            const double *m = p.mu + (int64_t)i * p.mstride;
+            t -= vi;
+            stn<V>(yr, t);
+            stn<V>(vr, (T)m[0] * vi + (T)m[1] * xi + (T)m[2] * t);
+        } else {
+            t -= zi;
+            stn<V>(yr, t);
+            stn<V>(vr, vi + (T)p.mu[(int64_t)i * p.mstride + p.k] * t);
+        }
+    }
+}
+
+template <typename T, int VEC, int G>
+fd_status launch_bt(const BatchDev &B, const T *val, const BatchCall &c, hipStream_t s) {
+    constexpr int RPB = 256 / G;
+    BArgs<T> p;
+    p.D = B.D;
+    p.k = c.k;
+    p.mstride = B.mstride;
+    p.ptr = B.ptr; p.col = B.col; p.val = val; p.inst = B.inst;
+    p.alpha = B.alpha; p.beta = B.beta; p.deg = B.deg; p.act = B.act; p.mu = B.mu;
+    p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;
+    p.y = (T *)c.y; p.ldy = c.ldy; p.by = c.by;
+    p.z = (const T *)c.z; p.ldz = c.ldz; p.bz = c.bz;
+    p.v = (T *)c.v; p.ldv = c.ldv; p.bv = c.bv;
+    if (B.D == 0) return FD_OK;
+    // grid: whole super-chunks (8 chunks of cb blocks), so the block -> row
+    // group map is a bijection; row groups past D return at once
+    const int64_t ngroups = (B.D + RPB - 1) / RPB;
+    const int64_t super = 8 * (CHUNK / RPB);
+    const int64_t nblk = (ngroups + super - 1) / super * super;
+    if (nblk > 0x7fffffff || c.nbundles < 1 || c.nbundles > 65535)
+        return fail(FD_ERR_UNSUPPORTED, "batched SpMMV: grid too large");
+    const dim3 grid((unsigned)nblk, c.nbundles);
+    switch (c.mode) {
+        case 0: hipLaunchKernelGGL((k_batch<T, VEC, G, 0>), grid, dim3(256), 0, s, p); break;
+        case 1: hipLaunchKernelGGL((k_batch<T, VEC, G, 1>), grid, dim3(256), 0, s, p); break;
+        case 2: hipLaunchKernelGGL((k_batch<T, VEC, G, 2>), grid, dim3(256), 0, s, p); break;
+        case 3: hipLaunchKernelGGL((k_batch<T, VEC, G, 3>), grid, dim3(256), 0, s, p); break;
+        default: return fail(FD_ERR_INVALID, "batched SpMMV: bad mode");
+    }
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+}  // namespace
+
+fd_status launch_batch(const BatchDev &B, fd_dtype dt, const BatchCall &c, hipStream_t s) {
+    if (dt == FD_F64) {
+        switch (c.nb) {
+            case 1: return launch_bt<double, 1, 1>(B, B.val64, c, s);
+            case 2: return launch_bt<double, 2, 1>(B, B.val64, c, s);
+            case 4: return launch_bt<double, 2, 2>(B, B.val64, c, s);
+            case 8: return launch_bt<double, 2, 4>(B, B.val64, c, s);
+            case 16: return launch_bt<double, 2, 8>(B, B.val64, c, s);
+            case 32: return launch_bt<double, 2, 16>(B, B.val64, c, s);
+            case 64: return launch_bt<double, 2, 32>(B, B.val64, c, s);
+        }
+    } else {
+        switch (c.nb) {
+            case 1: return launch_bt<float, 1, 1>(B, B.val32, c, s);
+            case 2: return launch_bt<float, 2, 1>(B, B.val32, c, s);
+            case 4: return launch_bt<float, 4, 1>(B, B.val32, c, s);
+            case 8: return launch_bt<float, 4, 2>(B, B.val32, c, s);
+            case 16: return launch_bt<float, 4, 4>(B, B.val32, c, s);
+            case 32: return launch_bt<float, 4, 8>(B, B.val32, c, s);
+            case 64: return launch_bt<float, 4, 16>(B, B.val32, c, s);
+        }
+    }
+    return fail(FD_ERR_INVALID, "nb must be one of 1, 2, 4, 8, 16, 32, 64");
+}
+
+}  // namespace fd

@@ -234,9 +234,9 @@ void hubbard_tables_gershgorin(const HubbardTables &T, double &lo, double &hi) {
     if (T.nu * T.nd == 0) lo = hi = 0.0;
 }
 
-fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A) {
-    if (L < 3 || (int64_t)L * L * L >= (1LL << 32))
-        return fail(FD_ERR_INVALID, "Anderson: need L >= 3 and L^3 < 2^32");
+fd_status build_anderson(int L, double t, double W, uint64_t seed, int64_t skip, HostCSR &A) {
+    if (L < 3 || (int64_t)L * L * L >= (1LL << 32) || skip < 0)
+        return fail(FD_ERR_INVALID, "Anderson: need L >= 3, L^3 < 2^32 and skip >= 0");
     const int64_t L1 = L, L2 = (int64_t)L * L, D = L2 * L;
     A.D = D;
     try {
@@ -250,7 +250,7 @@ fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A) {
         for (int64_t i = i0; i < i1; i++) {
             // SplitMix64 is counter based: the state after i+1 draws is
             // seed + (i+1) * gamma, so row i's disorder needs no sequential pass.
-            uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+            uint64_t z = seed + (uint64_t)(i + 1 + skip) * 0x9E3779B97F4A7C15ULL;
             z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
             z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
             z ^= z >> 31;

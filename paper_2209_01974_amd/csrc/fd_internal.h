@@ -59,7 +59,7 @@ struct HubbardTables {
 fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, HubbardTables &T);
 int64_t hubbard_tables_nnz(const HubbardTables &T);  // non-zeros of the full matrix
 void hubbard_tables_gershgorin(const HubbardTables &T, double &lo, double &hi);
-fd_status build_anderson(int L, double t, double W, uint64_t seed, HostCSR &A);
+fd_status build_anderson(int L, double t, double W, uint64_t seed, int64_t skip, HostCSR &A);
 fd_status build_diagonal(int64_t n, const double *d, HostCSR &A);
 fd_status build_user(int64_t D, const int64_t *rowptr, const uint32_t *col, const double *val,
                      HostCSR &A);
@@ -149,6 +149,38 @@ fd_status launch_spmmv_mf(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, c
 
 SpmmvTune &spmmv_tune();
 fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *best);
+
+// Batched problems (fd_batch.hip): n_inst independent matrices stacked as one
+// block-diagonal CSR; instance i owns rows [off[i], off[i+1]).  Per-instance
+// scaling, filter coefficients and degree live in device arrays, so one
+// launch per degree step serves every instance and bundle.
+struct BatchDev {
+    int32_t n_inst = 0;
+    int64_t D = 0;
+    uint32_t *ptr = nullptr, *col = nullptr;  // D + 1, nnz (columns already shifted)
+    double *val64 = nullptr;
+    float *val32 = nullptr;
+    uint16_t *inst = nullptr;  // row -> instance
+    double *alpha = nullptr, *beta = nullptr;  // n_inst
+    int32_t *deg = nullptr;  // n_inst: rows of instance i take part in steps k <= deg[i]
+    int32_t *act = nullptr;  // n_inst: rows take part in the plain SpMMV when act[i] != 0
+    double *mu = nullptr;    // n_inst x mstride filter coefficients
+    int32_t mstride = 0;
+};
+struct BatchCall {
+    int mode = 0;  // 0: y = A x; 1: first step; 2: second step; 3: step k >= 3
+    int k = 0;
+    int nb = 1, nbundles = 1;
+    const void *x = nullptr;
+    int64_t ldx = 0, bx = 0;
+    void *y = nullptr;
+    int64_t ldy = 0, by = 0;
+    const void *z = nullptr;
+    int64_t ldz = 0, bz = 0;
+    void *v = nullptr;
+    int64_t ldv = 0, bv = 0;
+};
+fd_status launch_batch(const BatchDev &B, fd_dtype dt, const BatchCall &c, hipStream_t s);
 
 // Dense kernels (fd_dense.hip).
 fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const double *Y,

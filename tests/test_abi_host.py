@@ -165,3 +165,28 @@ def test_matfree_argument_errors():
     with pytest.raises(fd.FDError):
         fd.spmmv_tune(tile=-1)
     fd.spmmv_tune()
+
+
+def test_anderson_stream_offset_bit_exact():
+    """skip = k: the disorder continues after k draws of the stream.  The
+    oracle's diagonal is W (u_{i+k} - 1/2) of its own SplitMix64 stream, and
+    the library's counter-based draw gives the same bits."""
+    L, W, seed, k = 5, 7.5, 123, 2
+    A = O.anderson(L, 1.0, W, seed, skip=k)
+    u = O.uniforms(seed, L ** 3 + k)
+    diag = np.array([A.val[A.rowptr[i]:A.rowptr[i + 1]][A.col[A.rowptr[i]:A.rowptr[i + 1]] == i][0]
+                     for i in range(A.D)])
+    assert np.array_equal(diag, W * (u[k:] - 0.5))
+    m = fd.build_matrix("anderson", host_only=True, L=L, t=1.0, W=W, seed=seed, skip=k)
+    _same_csr(m, A)
+
+
+def test_anderson_batch_instance_draws():
+    """Instance parameters come from the first two draws of SplitMix64(s),
+    the same generator as the oracle's (two implementations)."""
+    from fd_inputs import _splitmix64_uniforms, anderson_batch
+    for s in (0, 100, 195, 2 ** 63 + 5):
+        assert np.array_equal(np.array(_splitmix64_uniforms(s, 4)), O.uniforms(s, 4))
+    inst = anderson_batch(range(100, 196))
+    assert len(inst) == 96
+    assert all(20 <= q["L"] <= 64 and 2.0 <= q["W"] < 20.0 and q["skip"] == 2 for q in inst)
