@@ -115,6 +115,124 @@ def fd_runs(args, fd, np):
     return fdres
 
 
+def batch_runs(args, fd, np, torch):
+    """Batched workload: 96 3D Anderson instances drawn from SplitMix64 seeds
+    100-195 (L in [20, 64], W in [2, 20)), 16 pairs nearest E = 0 each,
+    N_s = 64.  (1) One degree-200 filter application (damped delta at E = 0)
+    on every instance: batched (one graph replay) against one instance after
+    another, algorithmic GB/s.  (2) FD to 1e-9 ||H|| on instances drawn the
+    same way at L in [8, 16] (the full-size instances need filter degrees of
+    10^4 and more near E = 0): batched against one fd_solve per instance,
+    eigenpairs/s and p50/p99 time per instance."""
+    from fd_inputs import anderson_batch
+    out = {}
+    ns, degree = 64, 200
+    inst = anderson_batch(range(100, 196))
+    t0 = time.time()
+    mats = [fd.build_matrix(**q) for q in inst]
+    b = fd.Batch(mats)
+    log("batch: 96 instances, D_total=%d, built in %.1fs" % (b.D, time.time() - t0))
+    alpha = [2.0 / (m.lam_hi - m.lam_lo) for m in mats]
+    beta = [-(m.lam_hi + m.lam_lo) / (m.lam_hi - m.lam_lo) for m in mats]
+    mu = [fd.cheb_coeffs(1, bt, 0.0, degree) for bt in beta]
+    degs = [degree] * len(mats)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    V = torch.randn((b.D, ns), generator=g, dtype=torch.float64, device="cuda")
+    W1 = torch.empty_like(V)
+    W2 = torch.empty_like(V)
+
+    def alg_bytes(nb):
+        return sum(degree * (ns // nb) * (m.nnz * 12 + 4 * (m.D + 1) + 5 * m.D * nb * 8) for m in mats)
+
+    # nb picked by timing one application per candidate (graph captured on
+    # the first call of each shape)
+    times = {}
+    for nb in (8, 16, 32, 64):
+        fd.batch_filter(b, V, mu, degs, alpha, beta, W1, W2, nb)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fd.batch_filter(b, V, mu, degs, alpha, beta, W1, W2, nb)
+        torch.cuda.synchronize()
+        times[nb] = time.perf_counter() - t
+        V.div_(V.norm())
+    nb = min(times, key=times.get)
+    reps = 3
+    t = time.perf_counter()
+    for _ in range(reps):
+        fd.batch_filter(b, V, mu, degs, alpha, beta, W1, W2, nb)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) / reps
+    # one instance after another, same nb, fd_cheb_filter per instance
+    t = time.perf_counter()
+    for i, m in enumerate(mats):
+        r = slice(int(b.off[i]), int(b.off[i + 1]))
+        fd.cheb_filter(m, V[r], mu[i], alpha[i], beta[i], W1[r], W2[r], nb)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    out["filter_full"] = {"instances": len(mats), "D_total": b.D, "n_search": ns, "degree": degree, "nb": nb,
+                          "nb_times_s": {str(k): round(v, 4) for k, v in times.items()},
+                          "batched_s": round(tb, 4), "sequential_s": round(ts, 4),
+                          "batched_GBs": round(alg_bytes(nb) / tb / 1e9, 1),
+                          "sequential_GBs": round(alg_bytes(nb) / ts / 1e9, 1),
+                          "speedup": round(ts / tb, 2)}
+    log("batch filter: %s" % out["filter_full"])
+    del V, W1, W2, b, mats
+    torch.cuda.empty_cache()
+
+    # (2) FD on small instances drawn the same way, with both orthogonalizations
+    inst = anderson_batch(range(100, 196), L_lo=8, L_span=9)
+    mats = [fd.build_matrix(**q) for q in inst]
+    nt, ns, nb = 16, 64, 16
+    degs = [fd.pick_degree(m, 0.0, 0.0, nt, ns)[0] for m in mats]
+    log("FD batch: degrees from the KPM rule in [%d, %d]" % (min(degs), max(degs)))
+    b = fd.Batch(mats)
+    out["fd_small"] = {"instances": len(mats), "D_total": b.D, "L": [min(q["L"] for q in inst),
+                                                                       max(q["L"] for q in inst)],
+                       "n_target": nt, "n_search": ns, "nb": nb, "degree_range": [min(degs), max(degs)]}
+    for oname, ortho in (("svqb2", fd.FD_ORTHO_SVQB2), ("cholqr2", fd.FD_ORTHO_CHOLQR2)):
+        params = [dict(tau_lo=0.0, tau_hi=0.0, n_target=nt, n_search=ns, nb=nb, degree=d,
+                       max_iter=args.batch_iters, tol=1e-9, seed=1000 + i, ortho=ortho) for i, d in enumerate(degs)]
+        r = fd.solve_batch(b, params)
+        conv = [s["iters"] <= args.batch_iters and s["max_resid"] <= 1e-9 * s["norm_H"] for s in r.stats]
+        tconv = sorted(s["t_total"] for s, c in zip(r.stats, conv) if c)
+        res = {"batched": {"converged": int(sum(conv)), "t_total_s": round(r.bstats["t_total"], 3),
+                           "eigenpairs_per_s": round(nt * sum(conv) / r.bstats["t_total"], 2),
+                           "p50_completion_s": round(float(np.percentile(tconv, 50)), 3) if tconv else None,
+                           "p99_completion_s": round(float(np.percentile(tconv, 99)), 3) if tconv else None,
+                           "iters": r.bstats["iters"], "t_filter_s": round(r.bstats["t_filter"], 3),
+                           "t_orthog_s": round(r.bstats["t_orthog"], 3), "t_rr_s": round(r.bstats["t_rr"], 3),
+                           "graph_launches": r.bstats["graph_launches"]}}
+        log("batched FD (%s): %s" % (oname, res["batched"]))
+        ev_b = r.evals
+        tl, done_at, nconv, maxdiff = [], [], 0, 0.0
+        t = time.perf_counter()
+        for i, m in enumerate(mats):
+            q = params[i]
+            s1 = fd.solve(m, 0.0, 0.0, nt, ns, nb, q["degree"], max_iter=q["max_iter"], tol=1e-9, seed=q["seed"],
+                          ortho=ortho, want_vectors=False)
+            if i % 32 == 31:
+                log("sequential FD (%s): %d of %d instances done" % (oname, i + 1, len(mats)))
+            if s1.status == fd.FD_OK:
+                nconv += 1
+                tl.append(s1.stats["t_total"])
+                done_at.append(time.perf_counter() - t)
+                if conv[i]:
+                    maxdiff = max(maxdiff, float(np.max(np.abs(s1.evals - ev_b[i])) / s1.stats["norm_H"]))
+        tseq = time.perf_counter() - t
+        res["sequential"] = {"converged": nconv, "t_total_s": round(tseq, 3),
+                             "eigenpairs_per_s": round(nt * nconv / tseq, 2),
+                             "p50_completion_s": round(float(np.percentile(done_at, 50)), 3) if done_at else None,
+                             "p99_completion_s": round(float(np.percentile(done_at, 99)), 3) if done_at else None,
+                             "p50_solve_s": round(float(np.percentile(tl, 50)), 3) if tl else None,
+                             "p99_solve_s": round(float(np.percentile(tl, 99)), 3) if tl else None}
+        res["speedup_batched_over_sequential"] = round(tseq / r.bstats["t_total"], 2)
+        res["max_rel_eval_diff_batched_vs_single"] = maxdiff
+        log("sequential FD (%s): %s" % (oname, res["sequential"]))
+        out["fd_small"][oname] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +250,9 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
     ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
     ap.add_argument("--fd-only", action="store_true", help="only the FD eigenpairs/s runs (no Anderson step)")
+    ap.add_argument("--batch", action="store_true",
+                    help="only the batched workload (96 Anderson instances; filter and FD, batched vs one by one)")
+    ap.add_argument("--batch-iters", type=int, default=80, help="max outer iterations per batched FD instance")
     ap.add_argument("--hub-fmt", choices=["csr", "sell", "matfree"], default="matfree",
                     help="storage of the Hubbard matrices in the FD runs (matfree: tensor-product form)")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
@@ -156,6 +277,9 @@ def main():
 
     if args.fd_only:
         print(json.dumps({"fd": fd_runs(args, fd, np)}), flush=True)
+        return
+    if args.batch:
+        print(json.dumps({"batch": batch_runs(args, fd, np, torch)}), flush=True)
         return
 
     # ---------------------------------------------------------- workload ----
