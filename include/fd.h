@@ -263,6 +263,22 @@ int32_t fd_syev_last_sweeps(void);
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal,
                         int32_t wide, int32_t tile);
 
+/* Lehmann intervals (Lehmann 1963; Sec. 2 determines the target and search
+ * intervals of FD from them).  V_dev: D x n block (ld >= n, linearly
+ * independent columns, e.g. the orthonormal search vectors), W_dev = A V
+ * (same layout).  For the shift rho the pencil S x = mu B x with
+ * S = V^t (A - rho) V and B = ((A - rho) V)^t ((A - rho) V) gives:
+ *   lower_host[i] = rho + 1/mu (the i-th most negative mu): [lower[i], rho)
+ *     holds at least i+1 eigenvalues of A;          *n_lower such bounds;
+ *   upper_host[i] = rho + 1/mu (the i-th largest positive mu): (rho,
+ *     upper[i]] holds at least i+1 eigenvalues;     *n_upper such bounds.
+ * lower_host and upper_host need n entries each.  All on the GPU (three MFMA
+ * Gram products, Cholesky of B, eigenvalues); synchronizes.  B singular
+ * (rho an eigenvalue with its eigenvector in span V): FD_ERR_BREAKDOWN.    */
+fd_status fd_lehmann(int64_t D, int32_t n, const double *V_dev, const double *W_dev, int64_t ld,
+                     double rho, double *lower_host, int32_t *n_lower, double *upper_host,
+                     int32_t *n_upper, void *stream);
+
 #define FD_ORTHO_SVQB2 0  /* two SVQB passes (Stathopoulos & Wu 2002)       */
 #define FD_ORTHO_CHOLQR2 1 /* two Cholesky-QR passes, SVQB2 if one fails    */
 
@@ -298,7 +314,10 @@ typedef struct {
     int32_t adapt;         /* 0: filter for the whole window; 1: each
                               iteration shrink the filter's window around tau
                               to the N_t-th nearest Ritz value in the window
-                              (Sec. 2: target interval tracked during FD)   */
+                              (Sec. 2: target interval tracked during FD);
+                              2: shrink it to the Lehmann radius at tau, the
+                              smallest tau +- r that provably holds N_t
+                              eigenvalues (fd_lehmann; Sec. 2)              */
     const float *picker_dev; /* degree 0: degree-picker parameters (device,
                               FD_MLP_NPARAMS) or NULL for the KPM rule     */
 } fd_solve_params;

@@ -365,8 +365,39 @@ class FDResult:
     history: list = field(default_factory=list)
 
 
+def lehmann(A: CSR, V: np.ndarray, rho: float):
+    """Lehmann's inclusion intervals (Lehmann 1963) for the shift rho from the
+    subspace spanned by the columns of V; the paper determines its target and
+    search intervals from them (Sec. 2).
+
+    With M0 = V^t V, M1 = V^t A V, M2 = (AV)^t (AV), the eigenvalues mu of
+    the definite pencil (M1 - rho M0) x = mu (M2 - 2 rho M1 + rho^2 M0) x
+    give: for the i-th most negative mu, [rho + 1/mu, rho) holds at least i
+    eigenvalues of A; for the i-th largest positive mu, (rho, rho + 1/mu]
+    holds at least i.  Returns (lower, upper, mu) with lower and upper in
+    that order (nearest rho first)."""
+    import scipy.linalg
+    AV = spmmv(A, V)
+    M0 = V.T @ V
+    M1 = V.T @ AV
+    M1 = 0.5 * (M1 + M1.T)
+    M2 = AV.T @ AV
+    mu = scipy.linalg.eigh(M1 - rho * M0, M2 - 2.0 * rho * M1 + rho * rho * M0, eigvals_only=True)
+    lower = rho + 1.0 / mu[mu < 0]
+    upper = rho + 1.0 / mu[mu > 0][::-1]
+    return lower, upper, mu
+
+
+def lehmann_radius(lower: np.ndarray, upper: np.ndarray, rho: float, k: int) -> float:
+    """Smallest r such that the Lehmann intervals certify k eigenvalues in
+    [rho - r, rho + r] (left and right counts add: the intervals are
+    disjoint); inf if fewer than k are certified."""
+    d = np.sort(np.concatenate([rho - lower, upper - rho]))
+    return float(d[k - 1]) if d.size >= k else float("inf")
+
+
 def fd_solve(A: CSR, V0: np.ndarray, tau_lo: float, tau_hi: float, n_target: int,
-             degree: int, tol: float = 1e-9, max_iter: int = 50, adapt: bool = False) -> FDResult:
+             degree: int, tol: float = 1e-9, max_iter: int = 50, adapt: int = 0) -> FDResult:
     """Plain FD (Alg. 1 reading) with a fixed degree and fixed target window.
 
     [lam_l, lam_r] = Gershgorin interval; alpha, beta from it; ||H|| =
@@ -376,7 +407,8 @@ def fd_solve(A: CSR, V0: np.ndarray, tau_lo: float, tau_hi: float, n_target: int
     damped delta at tau when tau_lo == tau_hi).  With adapt, the filter's
     window is shrunk each iteration to tau +- the distance of the n_target-th
     nearest Ritz value in the window (the target interval is tracked during
-    the iteration, Sec. 2).
+    the iteration, Sec. 2); with adapt == 2 to tau +- the Lehmann radius,
+    which provably holds n_target eigenvalues.
     """
     lam_l, lam_r = gershgorin(A)
     alpha, beta = scaling(lam_l, lam_r)
@@ -399,9 +431,15 @@ def fd_solve(A: CSR, V0: np.ndarray, tau_lo: float, tau_hi: float, n_target: int
         if ok or it >= max_iter:
             order = sel[np.argsort(theta[sel], kind="stable")]
             return FDResult(theta[order], V[:, order], rho[order], ok, it, spmv, norm_H, hist)
-        if adapt and tau_hi > tau_lo and sel.size == n_target:
-            tau = 0.5 * (tau_lo + tau_hi)
+        tau = 0.5 * (tau_lo + tau_hi)
+        r = None
+        if adapt == 1 and tau_hi > tau_lo and sel.size == n_target:
             r = abs(theta[sel[-1]] - tau)
+        if adapt == 2 and tau_hi > tau_lo:
+            lo_l, up_l, _ = lehmann(A, V, tau)
+            r = lehmann_radius(lo_l, up_l, tau, n_target)
+            r = r if np.isfinite(r) else None
+        if r is not None:
             lo_w, hi_w = max(tau_lo, tau - r), min(tau_hi, tau + r)
             a = min(1.0, max(-1.0, alpha * lo_w + beta))
             b = max(a, min(1.0, alpha * hi_w + beta))

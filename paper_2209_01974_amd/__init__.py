@@ -98,6 +98,7 @@ _SIGS = {
     "fd_mlp_forward": [_P, _I32, _P, _P, _P],
     "fd_mlp_grad": [_P, _I32, _P, _P, _P, _P, _P, _P],
     "fd_mlp_adam": [_P, _P, _P, _P, _I32, C.c_float, C.c_float, _P],
+    "fd_lehmann": [_I64, _I32, _P, _P, _I64, _D, _P, C.POINTER(_I32), _P, C.POINTER(_I32), _P],
     "fd_batch_create": [_I32, _P, C.POINTER(_P)],
     "fd_batch_info": [_P, C.POINTER(_I64), _P],
     "fd_batch_spmmv": [_P, C.c_int, _I32, _P, _I64, _P, _I64, _P],
@@ -373,6 +374,24 @@ def stream(op: int, a, c, b=None, scalar: float = 0.0, stream=None) -> None:
     _check(lib().fd_stream(op, a.numel(), C.c_void_p(a.data_ptr()),
                            C.c_void_p(b.data_ptr()) if b is not None else None,
                            C.c_void_p(c.data_ptr()), scalar, _stream(stream)))
+
+
+def lehmann(V, W, rho: float, stream=None):
+    """Lehmann bounds (fd_lehmann) for the shift rho from V and W = A V (GPU
+    float64 D x n blocks with one leading dimension): (lower, upper) numpy
+    arrays; [lower[i], rho) and (rho, upper[i]] each hold at least i+1
+    eigenvalues."""
+    pv, ld, dt = _blk(V, "V")
+    pw, ldw, dtw = _blk(W, "W")
+    if dt != FD_F64 or dtw != FD_F64 or ld != ldw or V.shape != W.shape:
+        raise ValueError("V and W must be float64 blocks of one shape and leading dimension")
+    n = V.shape[1]
+    lo = np.empty(n)
+    up = np.empty(n)
+    nl, nu = _I32(), _I32()
+    _check(lib().fd_lehmann(V.shape[0], n, pv, pw, ld, rho, lo.ctypes.data, C.byref(nl), up.ctypes.data,
+                            C.byref(nu), _stream(stream)))
+    return lo[:nl.value].copy(), up[:nu.value].copy()
 
 
 def syev_last_sweeps() -> int:

@@ -298,6 +298,50 @@ fd_status rr_dense(int64_t D, int ns, double *V, double *W, int64_t ld, double *
     return FD_OK;
 }
 
+// Lehmann's method (Lehmann 1963; the paper takes its target and search
+// intervals from Lehmann intervals, Sec. 2): the eigenvalues mu of the
+// pencil S x = mu B x with S = V^t (A - rho) V and
+// B = ((A - rho) V)^t ((A - rho) V), W = A V given.  B = R^t R (Cholesky),
+// then mu = eig(R^-t S R^-1), ascending, to the host.
+fd_status lehmann_impl(int64_t D, int n, const double *V, const double *W, int64_t ld, double rho,
+                       double *mu_host, hipStream_t s) {
+    const size_t nn = (size_t)n * n;
+    char *ws = (char *)workspace((7 * nn + n) * sizeof(double) + 64, 8);
+    if (!ws) return fail(FD_ERR_OOM, "Lehmann: workspace");
+    double *G2 = (double *)ws, *G1 = G2 + nn, *G0 = G1 + nn, *B = G0 + nn, *S = B + nn, *Q = S + nn, *C = Q + nn;
+    double *mu = C + nn;
+    int *ok = (int *)(mu + n);
+    FD_TRY(gram(D, n, n, W, ld, W, ld, G2, n, true, s));
+    FD_TRY(gram(D, n, n, V, ld, W, ld, G1, n, false, s));
+    FD_TRY(gram(D, n, n, V, ld, V, ld, G0, n, true, s));
+    FD_TRY(lehmann_pencil(n, G2, G1, G0, rho, B, S, s));
+    FD_TRY(cholqr_transform(n, B, Q, ok, s));
+    int okh = 0;
+    FD_HIP(hipMemcpyAsync(&okh, ok, sizeof(int), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    if (!okh)
+        return fail(FD_ERR_BREAKDOWN, "Lehmann: (A - rho) V is rank deficient (rho an eigenvalue with its vector in V?)");
+    FD_TRY(rotate(n, n, n, S, n, Q, n, s));                 // S <- S R^-1
+    FD_TRY(gram(n, n, n, Q, n, S, n, C, n, false, s));      // C = R^-t S R^-1
+    FD_TRY(symmetrize(n, C, s));
+    FD_TRY(syev(n, C, n, mu, G2, n, s));
+    FD_HIP(hipMemcpyAsync(mu_host, mu, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    return FD_OK;
+}
+
+// Lehmann radius: the smallest r such that [rho - r, rho + r] provably
+// holds at least k eigenvalues (interval counts of both sides add up, since
+// [rho + 1/mu_i, rho) and (rho, rho + 1/mu_j] are disjoint).  INFINITY if
+// the subspace certifies fewer than k.
+double lehmann_radius(const std::vector<double> &mu, int k) {
+    std::vector<double> d;
+    for (double x : mu)
+        if (x != 0.0) d.push_back(std::fabs(1.0 / x));
+    std::sort(d.begin(), d.end());
+    return (int)d.size() >= k ? d[k - 1] : INFINITY;
+}
+
 fd_status rr_impl(fd_matrix m, int ns, int nb, double *V, double *W, int64_t ld, double *theta_host,
                   double *resid_host, hipStream_t s) {
     SpmmvCall c;
@@ -849,6 +893,27 @@ fd_status fd_orthog(int64_t D, int32_t ns, double *V, int64_t ldv, int32_t metho
     return FD_OK;
 }
 
+fd_status fd_lehmann(int64_t D, int32_t n, const double *V, const double *W, int64_t ld, double rho,
+                     double *lower, int32_t *n_lower, double *upper, int32_t *n_upper, void *stream) {
+    if (!V || !W || !lower || !upper || !n_lower || !n_upper || D < 1 || n < 1 || n > 512 || ld < n || n > D ||
+        !std::isfinite(rho))
+        return fail(FD_ERR_INVALID, "fd_lehmann: bad arguments");
+    if (overlap(V, ld, W, ld, D, 8)) return fail(FD_ERR_INVALID, "fd_lehmann: V and W overlap");
+    std::vector<double> mu(n);
+    FD_TRY(lehmann_impl(D, n, V, W, ld, rho, mu.data(), (hipStream_t)stream));
+    // mu ascending: the negative ones give [rho + 1/mu_i, rho) with at least i
+    // eigenvalues (i-th most negative first); the positive ones, from the
+    // largest, give (rho, rho + 1/mu_i]
+    int nl = 0, nu = 0;
+    for (int i = 0; i < n; i++)
+        if (mu[i] < 0.0) lower[nl++] = rho + 1.0 / mu[i];
+    for (int i = n - 1; i >= 0; i--)
+        if (mu[i] > 0.0) upper[nu++] = rho + 1.0 / mu[i];
+    *n_lower = nl;
+    *n_upper = nu;
+    return FD_OK;
+}
+
 fd_status fd_rayleigh_ritz(fd_matrix m, int32_t ns, int32_t nb, double *V, double *W, int64_t ld, double *theta,
                            double *resid, void *stream) {
     FD_TRY(need_device(m));
@@ -879,7 +944,7 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     const double t0 = now();
     const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
     const double normH = std::max(std::fabs(lo), std::fabs(hi));
-    if (P->adapt != 0 && P->adapt != 1) return fail(FD_ERR_INVALID, "fd_solve: adapt must be 0 or 1");
+    if (P->adapt < 0 || P->adapt > 2) return fail(FD_ERR_INVALID, "fd_solve: adapt must be 0, 1 or 2");
     int degree = P->degree;
     double r0 = -1.0;
     if (degree == 0)
@@ -940,6 +1005,8 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     const double tol = P->tol * normH;
     bool converged = false;
     int it = 0;
+    double lehmann_r = INFINITY;
+    std::vector<double> lmu(ns);
     for (;;) {
         double ta = now();
         int rank = 0;
@@ -962,13 +1029,21 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         for (int j = 0; j < ns; j++)
             if ((P->tau_hi <= P->tau_lo || (th[j] >= P->tau_lo && th[j] <= P->tau_hi)) && rho[j] <= tol) st.n_conv++;
         converged = (int)sel.size() == nt && mx <= tol;
+        const double tau = 0.5 * (P->tau_lo + P->tau_hi);
+        if (P->adapt == 2 && P->tau_hi > P->tau_lo && !converged && it < P->max_iter) {
+            // certified radius around tau that holds N_t eigenvalues
+            const double tl = now();
+            fd_status ls = lehmann_impl(D, ns, Vd, Wd, ns, tau, lmu.data(), s);
+            lehmann_r = ls == FD_OK ? lehmann_radius(lmu, nt) : INFINITY;
+            st.t_rr += now() - tl;
+        }
         if (trace) {
             std::fprintf(stderr,
                          "{\"fd_iter\": %d, \"max_resid_rel\": %.3e, \"n_in_window\": %d, \"n_conv\": %d, "
                          "\"next_fp32\": %d, \"spmmv\": %lld, \"t_filter\": %.3f, \"t_orthog\": %.3f, "
-                         "\"t_rr\": %.3f, \"t\": %.3f}\n",
+                         "\"t_rr\": %.3f, \"lehmann_r\": %.3e, \"t\": %.3f}\n",
                          it, mx / normH, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count,
-                         st.t_filter, st.t_orthog, st.t_rr, now() - t0);
+                         st.t_filter, st.t_orthog, st.t_rr, lehmann_r, now() - t0);
             std::fflush(stderr);
         }
         if (converged || it >= P->max_iter) break;
@@ -981,9 +1056,13 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
         prev_max = mx;
         if (P->adapt == 1 && P->tau_hi > P->tau_lo && (int)sel.size() == nt) {
             // target window: tau +- distance of the N_t-th nearest Ritz value
-            const double tau = 0.5 * (P->tau_lo + P->tau_hi);
             const double r = std::fabs(th[sel.back()] - tau);
             FD_TRY(set_coeffs(std::max(P->tau_lo, tau - r), std::min(P->tau_hi, tau + r)));
+        }
+        if (P->adapt == 2 && P->tau_hi > P->tau_lo && std::isfinite(lehmann_r)) {
+            // target window: the Lehmann radius, which provably holds N_t
+            // eigenvalues (the paper's requirement on the target interval)
+            FD_TRY(set_coeffs(std::max(P->tau_lo, tau - lehmann_r), std::min(P->tau_hi, tau + lehmann_r)));
         }
         double tf = now();
         if (fp32) {

@@ -34,7 +34,7 @@ struct WsSlot {
     int dev = -1;
 };
 std::mutex g_ws_mu;
-WsSlot g_ws[8];
+WsSlot g_ws[10];
 }  // namespace
 
 void *workspace(size_t bytes, int slot) {
@@ -1000,6 +1000,28 @@ fd_status gather_cols(int64_t D, int n, const double *src, int64_t lds, const in
 
 fd_status symmetrize(int n, double *H, hipStream_t s) {
     hipLaunchKernelGGL(k_symmetrize, dim3(nblocks((int64_t)n * n)), dim3(256), 0, s, n, H);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+namespace {
+// Lehmann pencil from G2 = W^t W, G1 = V^t W, G0 = V^t V (W = A V):
+// B = ((A - rho) V)^t ((A - rho) V) = G2 - rho (G1 + G1^t) + rho^2 G0 and
+// S = V^t (A - rho) V = (G1 + G1^t) / 2 - rho G0.
+__global__ void k_lehmann_prep(int n, const double *G2, const double *G1, const double *G0, double rho, double *B,
+                               double *S) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int i = e / n, j = e % n;
+    const double g1 = G1[i * n + j] + G1[j * n + i];
+    B[e] = G2[e] - rho * g1 + rho * rho * G0[e];
+    S[e] = 0.5 * g1 - rho * G0[e];
+}
+}  // namespace
+
+fd_status lehmann_pencil(int n, const double *G2, const double *G1, const double *G0, double rho, double *B,
+                         double *S, hipStream_t s) {
+    hipLaunchKernelGGL(k_lehmann_prep, dim3(nblocks((int64_t)n * n)), dim3(256), 0, s, n, G2, G1, G0, rho, B, S);
     FD_HIP(hipGetLastError());
     return FD_OK;
 }

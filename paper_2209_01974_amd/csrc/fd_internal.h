@@ -206,6 +206,9 @@ fd_status convert_f32_f64(int64_t D, int n, const float *src, int64_t lds, doubl
 fd_status gather_cols(int64_t D, int n, const double *src, int64_t lds, const int *idx,
                       double *dst, int64_t ldd, hipStream_t s);
 fd_status symmetrize(int n, double *H, hipStream_t s);
+// Lehmann pencil (B, S) from the three Gram matrices of V and W = A V
+fd_status lehmann_pencil(int n, const double *G2, const double *G1, const double *G0, double rho, double *B,
+                         double *S, hipStream_t s);
 // out[off + j] = sum_i A[i][j] B[i][j] for j < n (two-stage, fixed order)
 fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
                    hipStream_t s);

@@ -229,3 +229,70 @@ def test_mlp_oracle_gradient_by_finite_differences():
         num = (mlp.loss_and_grad(p + e, X, Y, w)[0] - mlp.loss_and_grad(p - e, X, Y, w)[0]) / (2 * h)
         assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
     assert p.size == 41858
+
+
+# ------------------------------------------------------------ Lehmann bounds --
+def test_lehmann_exact_on_eigenvectors():
+    """With V spanning exact eigenvectors, every bound is one of their
+    eigenvalues: the pencil is diagonal with mu = 1/(lambda - rho)."""
+    A = O.hubbard(6, 3, 3, 1.0, 4.0)
+    lam, X = np.linalg.eigh(A.dense())
+    idx = np.array([10, 40, 120, 121, 200, 300])
+    rho = 0.5 * (lam[121] + lam[122])  # in the gap above the degenerate pair 120, 121
+    assert lam[122] - lam[121] > 1e-3
+    lower, upper, _ = O.lehmann(A, X[:, idx], rho)
+    below = np.sort(lam[idx][lam[idx] < rho])[::-1]
+    above = np.sort(lam[idx][lam[idx] > rho])
+    np.testing.assert_allclose(lower, below, atol=1e-10 * 24)
+    np.testing.assert_allclose(upper, above, atol=1e-10 * 24)
+
+
+def test_lehmann_single_vector_is_the_temple_kato_bound():
+    """One vector v (|v| = 1), Rayleigh quotient theta < rho, residual r:
+    the bound is theta - r^2 / (rho - theta) (worked out by hand from the
+    pencil: mu = (theta - rho) / ((theta - rho)^2 + r^2))."""
+    A = O.anderson(6, 1.0, 8.0, 4)
+    v = start_block(A.D, 1, 5)
+    v /= np.linalg.norm(v)
+    Av = O.spmmv(A, v)
+    theta = float(v[:, 0] @ Av[:, 0])
+    r2 = float(np.sum((Av - theta * v) ** 2))
+    rho = theta + 0.7
+    lower, upper, _ = O.lehmann(A, v, rho)
+    assert upper.size == 0 and lower.size == 1
+    assert abs(lower[0] - (theta - r2 / (rho - theta))) <= 1e-12 * (1 + abs(lower[0]))
+
+
+@pytest.mark.parametrize("name,k,rho", [("and6", 24, 0.0), ("and6", 40, 1.3), ("hub6", 30, 2.01), ("hub6", 12, -4.4)])
+def test_lehmann_bounds_hold_against_dense_spectrum(name, k, rho):
+    """The theorem: [lower[i], rho) and (rho, upper[i]] each hold at least
+    i+1 eigenvalues; the radius certifies k_t eigenvalues in rho +- r.  V is
+    a random block after a few filter steps, so bounds are far from exact."""
+    A = O.anderson(6, 1.0, 8.0, 4) if name == "and6" else O.hubbard(6, 3, 3, 1.0, 4.0)
+    lam = np.linalg.eigvalsh(A.dense())
+    assert np.min(np.abs(lam - rho)) > 1e-6
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    V = O.cheb_filter(A, start_block(A.D, k, 8), O.cheb_coeffs(1, alpha * rho + beta, 0.0, 12), alpha, beta)
+    V, _ = O.svqb2(V)
+    lower, upper, mu = O.lehmann(A, V, rho)
+    assert lower.size + upper.size == k
+    for i, b in enumerate(lower):
+        assert np.sum((lam >= b) & (lam < rho)) >= i + 1
+    for i, b in enumerate(upper):
+        assert np.sum((lam > rho) & (lam <= b)) >= i + 1
+    for kt in (1, 4, 8):
+        r = O.lehmann_radius(lower, upper, rho, kt)
+        assert np.sum(np.abs(lam - rho) <= r) >= kt
+        # and it is no smaller than the exact kt-th distance
+        assert r >= np.sort(np.abs(lam - rho))[kt - 1] - 1e-12
+
+
+def test_fd_lehmann_window_hubbard8_vs_dense():
+    """FD with the Lehmann-controlled window converges to the dense answer."""
+    A = O.hubbard(8, 4, 4, 1.0, 4.0)
+    r = O.fd_solve(A, start_block(A.D, 128, 0), -0.5, 0.5, 16, 100, 1e-9, max_iter=80, adapt=2)
+    assert r.converged
+    ev = np.linalg.eigvalsh(A.dense())
+    inside = ev[(ev >= -0.5) & (ev <= 0.5)]
+    want = np.sort(inside[np.argsort(np.abs(inside), kind="stable")[:16]])
+    assert np.abs(r.evals - want).max() <= 1e-10 * r.norm_H
