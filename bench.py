@@ -96,7 +96,7 @@ def fd_runs(args, fd, np):
         evs = {}
         for prec, label in ((0, "fp64"), (1, "mixed")):
             r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=200, tol=1e-9, precision=prec, V0=V0,
-                         seed=0, want_vectors=False, adapt=1)
+                         seed=0, want_vectors=False, adapt=args.adapt)
             st = r.stats
             res[label] = {"converged": r.status == fd.FD_OK, "eigenpairs_per_s": round(nt / st["t_total"], 4),
                           "t_total_s": round(st["t_total"], 3), "iters": st["iters"],
@@ -108,7 +108,8 @@ def fd_runs(args, fd, np):
             log("FD %s %s: %s" % (name, label, res[label]))
         res["config"] = {"D": mh.D, "nnz": mh.nnz, "format": args.hub_fmt, "window": [lo, hi], "n_target": nt,
                          "n_search": nsr,
-                         "nb": nbr, "degree": deg, "window_rule": "adaptive"}
+                         "nb": nbr, "degree": deg,
+                         "window_rule": {0: "fixed", 1: "ritz", 2: "lehmann"}[args.adapt]}
         res["mixed_vs_fp64_max_rel_eval_diff"] = float(np.max(np.abs(evs["mixed"] - evs["fp64"])) / normH)
         res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
         fdres[name] = res
@@ -253,6 +254,9 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="only the batched workload (96 Anderson instances; filter and FD, batched vs one by one)")
     ap.add_argument("--batch-iters", type=int, default=80, help="max outer iterations per batched FD instance")
+    ap.add_argument("--adapt", type=int, choices=[0, 1, 2], default=1,
+                    help="filter window of the FD runs: 0 fixed, 1 tracked by the N_t-th Ritz value, "
+                         "2 tracked by the Lehmann radius")
     ap.add_argument("--hub-fmt", choices=["csr", "sell", "matfree"], default="matfree",
                     help="storage of the Hubbard matrices in the FD runs (matfree: tensor-product form)")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")

@@ -1038,12 +1038,16 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
             st.t_rr += now() - tl;
         }
         if (trace) {
+            // valid JSON: non-finite values as null
+            char mxs[32], lrs[32];
+            std::snprintf(mxs, sizeof mxs, std::isfinite(mx) ? "%.3e" : "null", mx / normH);
+            std::snprintf(lrs, sizeof lrs, std::isfinite(lehmann_r) ? "%.3e" : "null", lehmann_r);
             std::fprintf(stderr,
-                         "{\"fd_iter\": %d, \"max_resid_rel\": %.3e, \"n_in_window\": %d, \"n_conv\": %d, "
+                         "{\"fd_iter\": %d, \"max_resid_rel\": %s, \"n_in_window\": %d, \"n_conv\": %d, "
                          "\"next_fp32\": %d, \"spmmv\": %lld, \"t_filter\": %.3f, \"t_orthog\": %.3f, "
-                         "\"t_rr\": %.3f, \"lehmann_r\": %.3e, \"t\": %.3f}\n",
-                         it, mx / normH, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count,
-                         st.t_filter, st.t_orthog, st.t_rr, lehmann_r, now() - t0);
+                         "\"t_rr\": %.3f, \"lehmann_r\": %s, \"t\": %.3f}\n",
+                         it, mxs, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count, st.t_filter,
+                         st.t_orthog, st.t_rr, lrs, now() - t0);
             std::fflush(stderr);
         }
         if (converged || it >= P->max_iter) break;
