@@ -10,8 +10,9 @@ N_s = 512 search vectors in 8 bundles of nb = 64, target "nearest E = 0":
   -> Rayleigh-Ritz (one more SpMMV per bundle, Gram, Jacobi, rotations,
      residual norms) -> selection of the pairs nearest E = 0 (host).
 Inputs (matrix and the N(0,1) start block) are resident in HBM before the
-timed region.  `value` is the whole step's algorithmic bytes (Eq. traffic
-with kappa = 5 for the fused steps, plus the dense passes) divided by the
+timed region.  `value` is the whole step's algorithmic bytes (Eq. traffic,
+with kappa = 5 for the steps that update V and kappa = 3 for the others --
+V takes two terms every other step -- plus the dense passes) divided by the
 step's wall time.
 
 Extra fields: a SpMMV / filter bandwidth sweep over nb and precision, the FD
@@ -51,11 +52,23 @@ def fused_bytes(nnz, D, nb, sv, kappa=5):
     return nnz * (sv + 4) + 4 * (D + 1) + kappa * D * nb * sv
 
 
+def filter_step_counts(degree):
+    """Steps 3..n of the filter: (steps with the V update, kappa = 5; steps
+    with the recurrence only, kappa = 3).  V is updated with two terms at
+    every even step, and at an odd last step."""
+    n_even = degree // 2 - 1
+    n_last = 1 if degree % 2 == 1 and degree >= 3 else 0
+    return n_even + n_last, (degree - 2) - n_even - n_last
+
+
 def filter_bytes(nnz, D, nb, sv, degree):
     """One filter application on one bundle: step 1 (SpMMV + write), step 2
-    (kappa = 4: gather, read V, write W1 and V), steps 3..n (kappa = 5)."""
+    (kappa = 4: gather, read V, write W1 and V), then the steps with the V
+    update (kappa = 5: W1 read once, W2 and V read and written) and the
+    recurrence-only steps (kappa = 3)."""
+    n5, n3 = filter_step_counts(degree)
     return (fused_bytes(nnz, D, nb, sv, 2) + fused_bytes(nnz, D, nb, sv, 4)
-            + (degree - 2) * fused_bytes(nnz, D, nb, sv, 5))
+            + n5 * fused_bytes(nnz, D, nb, sv, 5) + n3 * fused_bytes(nnz, D, nb, sv, 3))
 
 
 def dense_bytes(D, ns):
@@ -69,7 +82,7 @@ def dense_bytes(D, ns):
 def traffic_from_profile(kernel_src: str):
     """HBM bytes per launch of the fused step from the committed rocprofv3
     PMC summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "fused_step_anderson200_nb64_f64_pmc.json")
+    path = os.path.join(ROOT, "profiles", "chebyshev_steps_anderson200_nb64_f64_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -307,7 +320,9 @@ def main():
         fd.cheb_filter(m, V1, fd.cheb_coeffs(1, beta, 0.0, 12), alpha, beta, Z1, Z2, nb, stream=stream)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_sample": True, "copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
-                          "fused_launches": 10, "fused_algorithmic_bytes": fused_bytes(nnz, D, nb, 8),
+                          "launches_mode5": 5, "launches_mode4": 5,
+                          "algorithmic_bytes_mode5": fused_bytes(nnz, D, nb, 8, 5),
+                          "algorithmic_bytes_mode4": fused_bytes(nnz, D, nb, 8, 3),
                           "D": D, "nnz": nnz, "nb": nb}), flush=True)
         return
     shape = fd.autotune(m, "f64", nb, stream=stream)
@@ -353,20 +368,24 @@ def main():
     step_bytes = fb + nbund * spmmv_bytes(nnz, D, nb, 8) + dense_bytes(D, ns)
     value = step_bytes / t_step / 1e9
 
-    # roofline of the dominant kernel: the fused Chebyshev step (HIP events
+    # roofline of the dominant kernel: the Chebyshev step kernel (HIP events
     # around each filter call on the launch stream; every launch in it is the
-    # SpMMV/Chebyshev kernel, 2 of each `degree` launches are the lighter
-    # first two steps)
+    # SpMMV/Chebyshev kernel: per bundle the two first steps, then the steps
+    # alternate between the recurrence only (MODE 4) and the recurrence with
+    # the two-term V update (MODE 5)); bytes and time are per average launch
     t_filter = sum(filt_times) / len(filt_times)
     launches = degree * nbund
     avg_launch = t_filter / launches
     achieved = fb / t_filter / 1e9
-    per_launch = fused_bytes(nnz, D, nb, 8)
+    per_launch = fb / launches
     traffic = traffic_from_profile(os.path.join(ROOT, "paper_2209_01974_amd", "csrc", "fd_spmmv.hip"))
+    n5, n3 = filter_step_counts(degree)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_spmmv<double,2,32,MODE=3> (fused Chebyshev step, FP64, nb=64)",
-                "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": round(avg_launch * 1e6, 2)}
+                "kernel": "k_spmmv<double,2,32,MODE 4|5> (Chebyshev steps, FP64, nb=64; per launch averaged "
+                          "over a filter application: %d steps with the V update, %d without, 2 first steps)"
+                          % (n5, n3),
+                "algorithmic_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_launch * 1e6, 2)}
     del W
     torch.cuda.empty_cache()
 

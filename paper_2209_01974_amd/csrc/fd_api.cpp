@@ -177,14 +177,25 @@ fd_status filter_run(const DevMatrix &M, fd_dtype dt, int nb, int nbund, char *V
     c.a = 2.0 * alpha; c.b = 2.0 * beta;
     c.cv = mu[0]; c.cx = mu[1]; c.ct = mu[2];
     FD_TRY(launch_spmmv(M, dt, c, s));
-    // steps k >= 3: prev = 2 B cur - prev (in place); V += mu_k prev
+    // steps k >= 3: prev = 2 B cur - prev (in place).  V is updated every
+    // other step with two terms, V += mu_{k-1} cur + mu_k prev at even k
+    // (cur's own row is read by the step anyway), which saves one read and
+    // one write of V per pair of steps; an odd last step adds mu_n alone.
     char *cur = W1, *prev = W2;
     for (int k = 3; k <= degree; k++) {
-        c.mode = 3;
         c.x = cur; c.ldx = ldw; c.bx = bw;
         c.z = prev; c.ldz = ldw; c.bz = bw;
         c.y = prev; c.ldy = ldw; c.by = bw;
-        c.ct = mu[k];
+        if (k % 2 == 0) {
+            c.mode = 5;
+            c.cx = mu[k - 1];
+            c.ct = mu[k];
+        } else if (k == degree) {
+            c.mode = 3;
+            c.ct = mu[k];
+        } else {
+            c.mode = 4;
+        }
         FD_TRY(launch_spmmv(M, dt, c, s));
         std::swap(cur, prev);
     }
@@ -503,7 +514,7 @@ fd_status batch_filter_steps(const BatchDev &B, fd_dtype dt, int nb, int nbund, 
     FD_TRY(launch_batch(B, dt, c, s));
     char *cur = W1, *prev = W2;
     for (int k = 3; k <= max_degree; k++) {
-        c.mode = 3;
+        c.mode = 5;  // V every other step, two terms (per-instance last step)
         c.k = k;
         c.x = cur; c.ldx = ldw; c.bx = nb;
         c.z = prev; c.ldz = ldw; c.bz = nb;

@@ -55,6 +55,9 @@ __device__ __forceinline__ void stn(void *p, V x) { __builtin_nontemporal_store(
 // MODE 1: y = alpha_i A x + beta_i x
 // MODE 2: t = 2 alpha_i A x + 2 beta_i x - v; y = t; v = mu_i0 v + mu_i1 x + mu_i2 t
 // MODE 3: t = 2 alpha_i A x + 2 beta_i x - z; y = t (in place over z); v += mu_ik t
+// MODE 5: as MODE 3, but V is updated every other step with two terms: at
+//   even k, v += mu_i,k-1 x + mu_ik t (x = the previous step's vector); at
+//   odd k only when k is the instance's last step (v += mu_ik t)
 template <typename T, int VEC, int G, int MODE>
 __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     typedef typename BV<T, VEC>::type V;
@@ -77,11 +80,13 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     const T *xq = p.x + bnd * p.bx + q * VEC;
     V zi = (V)0, vi = (V)0;
     T *vr = nullptr;
-    if constexpr (MODE >= 2) {
+    bool upd = MODE == 2 || MODE == 3;
+    if constexpr (MODE == 5) upd = !(p.k & 1) || p.k == p.deg[i];
+    if (upd) {
         vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
         vi = ldn<V>(vr);
     }
-    if constexpr (MODE == 3) zi = ldn<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+    if constexpr (MODE >= 3) zi = ldn<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
     const uint32_t j0 = p.ptr[row], j1 = p.ptr[row + 1];
     V acc0 = (V)0, acc1 = (V)0;
     uint32_t jj = j0;
@@ -108,10 +113,19 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
             t -= vi;
             stn<V>(yr, t);
             stn<V>(vr, (T)m[0] * vi + (T)m[1] * xi + (T)m[2] * t);
-        } else {
+        } else if constexpr (MODE == 3) {
             t -= zi;
             stn<V>(yr, t);
             stn<V>(vr, vi + (T)p.mu[(int64_t)i * p.mstride + p.k] * t);
+        } else {
+            const double *m = p.mu + (int64_t)i * p.mstride;
+            t -= zi;
+            stn<V>(yr, t);
+            if (p.k & 1) {
+                if (upd) stn<V>(vr, vi + (T)m[p.k] * t);
+            } else {
+                stn<V>(vr, vi + (T)m[p.k - 1] * xi + (T)m[p.k] * t);
+            }
         }
     }
 }
@@ -143,6 +157,7 @@ fd_status launch_bt(const BatchDev &B, const T *val, const BatchCall &c, hipStre
         case 1: hipLaunchKernelGGL((k_batch<T, VEC, G, 1>), grid, dim3(256), 0, s, p); break;
         case 2: hipLaunchKernelGGL((k_batch<T, VEC, G, 2>), grid, dim3(256), 0, s, p); break;
         case 3: hipLaunchKernelGGL((k_batch<T, VEC, G, 3>), grid, dim3(256), 0, s, p); break;
+        case 5: hipLaunchKernelGGL((k_batch<T, VEC, G, 5>), grid, dim3(256), 0, s, p); break;
         default: return fail(FD_ERR_INVALID, "batched SpMMV: bad mode");
     }
     FD_HIP(hipGetLastError());

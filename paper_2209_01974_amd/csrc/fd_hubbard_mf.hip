@@ -80,7 +80,7 @@ __device__ __forceinline__ int64_t logical_block(int64_t bid, int64_t q8) {
 
 // pass 1: down hops + diagonal, rows in natural order.
 //   MODE 0: y = s           MODE 1: y = a s + b x
-//   MODE 2: y = a s + b x - v        MODE 3, 4: y = a s + b x - z
+//   MODE 2: y = a s + b x - v        MODE 3, 4, 5: y = a s + b x - z
 // with s = (I x H_dn + U D) x.  y may alias z (same element read first).
 template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
 __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
     const int64_t a = (uint32_t)s / (uint32_t)p.nd, b = s - a * p.nd;
     V zi = (V)0;
     if constexpr (MODE == 2) zi = lds<V, NT>(p.v + bnd * p.bv + s * p.ldv + q * VEC);
-    if constexpr (MODE == 3 || MODE == 4) zi = lds<V, NT>(p.z + bnd * p.bz + s * p.ldz + q * VEC);
+    if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + s * p.ldz + q * VEC);
     const V xi = ld<V>(xq + s * p.ldx);
     V acc0 = (p.U * (T)__popcll(p.mu[a] & p.md[b])) * xi, acc1 = (V)0;
     const int64_t row0 = a * p.nd;
@@ -120,6 +120,7 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
 //   MODE 0, 1, 4: y = t
 //   MODE 2: y = t, v = cv v + cx x + ct t
 //   MODE 3: y = t, v = v + ct t
+//   MODE 5: y = t, v = v + cx x + ct t
 template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
 __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     typedef typename VT<T, VEC>::type V;
@@ -145,11 +146,11 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     T *yr = p.y + bnd * p.by + s * p.ldy + q * VEC;
     V vi = (V)0, xi = (V)0;
     T *vr = nullptr;
-    if constexpr (MODE == 2 || MODE == 3) {
+    if constexpr (MODE == 2 || MODE == 3 || MODE == 5) {
         vr = p.v + bnd * p.bv + s * p.ldv + q * VEC;
         vi = lds<V, NT>(vr);
     }
-    if constexpr (MODE == 2) xi = ld<V>(xq + s * p.ldx);
+    if constexpr (MODE == 2 || MODE == 5) xi = ld<V>(xq + s * p.ldx);
     const V yi = lds<V, NT>(yr);
     V acc0 = (V)0, acc1 = (V)0;
     const int32_t j1 = p.off_u[a + 1];
@@ -167,6 +168,7 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     sts<V, NT>(yr, t);
     if constexpr (MODE == 2) sts<V, NT>(vr, p.cv * vi + p.cx * xi + p.ct * t);
     if constexpr (MODE == 3) sts<V, NT>(vr, vi + p.ct * t);
+    if constexpr (MODE == 5) sts<V, NT>(vr, vi + p.cx * xi + p.ct * t);
 }
 
 template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
@@ -191,6 +193,7 @@ fd_status launch_x(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t 
         case 2: return launch_mode<T, VEC, G, 2, XCD, NT>(p, nbund, g1, g2, s);
         case 3: return launch_mode<T, VEC, G, 3, XCD, NT>(p, nbund, g1, g2, s);
         case 4: return launch_mode<T, VEC, G, 4, XCD, NT>(p, nbund, g1, g2, s);
+        case 5: return launch_mode<T, VEC, G, 5, XCD, NT>(p, nbund, g1, g2, s);
     }
     return fail(FD_ERR_INVALID, "matrix-free SpMMV: bad mode");
 }

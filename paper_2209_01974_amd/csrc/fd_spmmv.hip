@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
         T *vr = nullptr;
         if constexpr (MODE >= 2) {
             vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
-            if constexpr (MODE == 3 || MODE == 4) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
-            if constexpr (MODE == 2 || MODE == 3) vi = lds<V, NT>(vr);
+            if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+            if constexpr (MODE == 2 || MODE == 3 || MODE == 5) vi = lds<V, NT>(vr);
         }
         const T *xq = x + q * VEC;
         V acc0 = (V)0, acc1 = (V)0;
@@ -171,7 +171,13 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
                 t -= zi;
                 sts<V, NT>(yr, t);
                 sts<V, NT>(vr, vi + p.ct * t);
-            } else {  // MODE 4: recurrence only (moments of the kernel polynomial method)
+            } else if constexpr (MODE == 5) {
+                // two accumulation terms at once: the previous step's vector
+                // (x, whose own row is loaded anyway) and this step's
+                t -= zi;
+                sts<V, NT>(yr, t);
+                sts<V, NT>(vr, vi + p.cx * xi + p.ct * t);
+            } else {  // MODE 4: recurrence only (odd filter steps, KPM moments)
                 t -= zi;
                 sts<V, NT>(yr, t);
             }
@@ -245,6 +251,8 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
         case 7: FD_L2(3, true); break;
         case 8: FD_L2(4, false); break;
         case 9: FD_L2(4, true); break;
+        case 10: FD_L2(5, false); break;
+        case 11: FD_L2(5, true); break;
         default: return fail(FD_ERR_INVALID, "SpMMV: bad mode");
     }
 #undef FD_L2
