@@ -256,7 +256,8 @@ def main():
     ap.add_argument("--nb", type=int, default=64)
     ap.add_argument("--ns", type=int, default=512)
     ap.add_argument("--degree", type=int, default=500)
-    ap.add_argument("--fmt", choices=["csr", "sell"], default="csr")
+    ap.add_argument("--fmt", choices=["csr", "sell", "pencil"], default="csr",
+                    help="storage / walk of the Anderson matrix (pencil: (x, y) tiles of C x sigma over all z)")
     ap.add_argument("--C", type=int, default=32)
     ap.add_argument("--sigma", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

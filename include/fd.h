@@ -51,7 +51,7 @@ typedef enum {
 } fd_status;
 
 typedef enum { FD_F64 = 0, FD_F32 = 1 } fd_dtype;
-typedef enum { FD_FMT_CSR = 0, FD_FMT_SELL = 1, FD_FMT_MATFREE = 2 } fd_format;
+typedef enum { FD_FMT_CSR = 0, FD_FMT_SELL = 1, FD_FMT_MATFREE = 2, FD_FMT_PENCIL = 3 } fd_format;
 typedef enum {
     FD_HUBBARD_RING = 0, /* 1D Hubbard model, L sites, n_up + n_dn fermions  */
     FD_ANDERSON_3D = 1,  /* 3D Anderson lattice, L^3 sites                   */
@@ -112,6 +112,13 @@ typedef struct fd_matrix_s *fd_matrix; /* opaque, owned by the library */
  * is taken from the tables; fd_matrix_export_csr returns FD_ERR_INVALID;
  * fd_matrix_info reports the hop-table entries as "stored".  sigma is
  * ignored.  C outside [0, 2^20]: FD_ERR_INVALID.                           */
+/* FD_FMT_PENCIL (FD_ANDERSON_3D only): the CSR rows, walked by the sparse
+ * kernels in pencil order: (x, y) tiles of C by sigma sites (0: 16), each
+ * running over all z, tiles in x-then-y order.  A row's z neighbours
+ * (L^2 rows away in the natural order) are then a few rows away in the
+ * walk.  Stored as SELL-1 with perm[new] = old in that order (see
+ * fd_matrix_export_sell); vectors stay in the natural order, and every row
+ * is computed exactly as with FD_FMT_CSR.                                  */
 fd_status fd_build_matrix(const fd_model_params *params, fd_format fmt, int32_t C,
                           int32_t sigma, int32_t flags, fd_matrix *out);
 

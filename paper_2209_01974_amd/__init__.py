@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfd.so")
 
 FD_OK, FD_ERR_INVALID, FD_ERR_OOM, FD_ERR_HIP, FD_ERR_NOT_CONVERGED, FD_ERR_BREAKDOWN, FD_ERR_UNSUPPORTED = range(7)
 FD_F64, FD_F32 = 0, 1
-FD_FMT_CSR, FD_FMT_SELL, FD_FMT_MATFREE = 0, 1, 2
+FD_FMT_CSR, FD_FMT_SELL, FD_FMT_MATFREE, FD_FMT_PENCIL = 0, 1, 2, 3
 FD_HUBBARD_RING, FD_ANDERSON_3D, FD_DIAGONAL, FD_USER_CSR = range(4)
 FD_BUILD_HOST_ONLY = 1
 FD_ORTHO_SVQB2, FD_ORTHO_CHOLQR2 = 0, 1
@@ -216,7 +216,8 @@ def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host
                  L: int = 0, n_up: int = 0, n_dn: int = 0, periodic: bool = True, t: float = 1.0,
                  U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None, skip: int = 0) -> Matrix:
     """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"} and fmt in
-    {"csr", "sell", "matfree"} ("matfree": Hubbard only, C_ = default up-pass tile)."""
+    {"csr", "sell", "matfree", "pencil"} ("matfree": Hubbard only, C_ = default up-pass tile;
+    "pencil": Anderson only, C_ x sigma = (x, y) tile of the walk)."""
     p = ModelParams()
     keep = []
     codes = {"hubbard": FD_HUBBARD_RING, "anderson": FD_ANDERSON_3D, "diagonal": FD_DIAGONAL, "csr": FD_USER_CSR}
@@ -234,7 +235,7 @@ def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host
         keep += [rowptr, col, val]
         p.D = rowptr.size - 1
         p.rowptr, p.col, p.val = rowptr.ctypes.data, col.ctypes.data, val.ctypes.data
-    f = {"csr": FD_FMT_CSR, "sell": FD_FMT_SELL, "matfree": FD_FMT_MATFREE}[fmt]
+    f = {"csr": FD_FMT_CSR, "sell": FD_FMT_SELL, "matfree": FD_FMT_MATFREE, "pencil": FD_FMT_PENCIL}[fmt]
     h = C.c_void_p()
     _check(lib().fd_build_matrix(C.byref(p), f, C_, sigma, FD_BUILD_HOST_ONLY if host_only else 0, C.byref(h)))
     return Matrix(h, f, C_ if f == FD_FMT_SELL else 1)

@@ -577,8 +577,10 @@ const char *fd_last_error(void) { return g_err.c_str(); }
 fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, int32_t sigma, int32_t flags,
                           fd_matrix *out) {
     if (!p || !out) return fail(FD_ERR_INVALID, "fd_build_matrix: null argument");
-    if (fmt != FD_FMT_CSR && fmt != FD_FMT_SELL && fmt != FD_FMT_MATFREE)
+    if (fmt != FD_FMT_CSR && fmt != FD_FMT_SELL && fmt != FD_FMT_MATFREE && fmt != FD_FMT_PENCIL)
         return fail(FD_ERR_INVALID, "fd_build_matrix: bad format");
+    if (fmt == FD_FMT_PENCIL && p->model != FD_ANDERSON_3D)
+        return fail(FD_ERR_INVALID, "fd_build_matrix: the pencil order is for the 3D Anderson lattice only");
     if (fmt == FD_FMT_MATFREE && p->model != FD_HUBBARD_RING)
         return fail(FD_ERR_INVALID, "fd_build_matrix: the matrix-free format is for the Hubbard ring only");
     if (fmt == FD_FMT_MATFREE && (C < 0 || C > (1 << 20)))
@@ -615,12 +617,14 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
         default: st = fail(FD_ERR_INVALID, "fd_build_matrix: unknown model");
     }
     if (st == FD_OK && fmt == FD_FMT_SELL) st = build_sell(m->csr, C, sigma, m->sell);
+    if (st == FD_OK && fmt == FD_FMT_PENCIL)
+        st = build_pencil(m->csr, p->L, C > 0 ? C : 16, sigma > 0 ? sigma : 16, m->sell);
     m->fmt = fmt;
     if (st == FD_OK) {
         gershgorin(m->csr, m->lam_lo, m->lam_hi);
         m->D = m->csr.D;
         m->nnz = m->csr.rowptr[m->csr.D];
-        m->stored = (fmt == FD_FMT_SELL) ? m->sell.chunk_ptr.back() : m->nnz;
+        m->stored = (fmt == FD_FMT_SELL || fmt == FD_FMT_PENCIL) ? m->sell.chunk_ptr.back() : m->nnz;
     }
     if (st == FD_OK && !(flags & FD_BUILD_HOST_ONLY)) {
         st = upload(m);
@@ -657,7 +661,8 @@ fd_status fd_matrix_export_sell(fd_matrix m, int32_t *perm, int64_t *cptr, int32
                                 double *val) {
     if (!m || !perm || !cptr || !clen || !col || !val)
         return fail(FD_ERR_INVALID, "fd_matrix_export_sell: null argument");
-    if (m->fmt != FD_FMT_SELL) return fail(FD_ERR_INVALID, "fd_matrix_export_sell: matrix is not SELL");
+    if (m->fmt != FD_FMT_SELL && m->fmt != FD_FMT_PENCIL)
+        return fail(FD_ERR_INVALID, "fd_matrix_export_sell: matrix is not SELL or pencil-ordered");
     const HostSELL &S = m->sell;
     std::memcpy(perm, S.perm.data(), S.perm.size() * sizeof(int32_t));
     std::memcpy(cptr, S.chunk_ptr.data(), S.chunk_ptr.size() * sizeof(int64_t));

@@ -320,6 +320,15 @@ fd_status build_sell(const HostCSR &A, int C, int sigma, HostSELL &S) {
         auto b = S.perm.begin() + w, e = S.perm.begin() + std::min<int64_t>(D, w + sigma);
         std::stable_sort(b, e, [&](int32_t p, int32_t q) { return len(p) > len(q); });
     }
+    return fill_sell(A, S);
+}
+
+// Chunks of S.C rows in the order S.perm (perm[new] = old), column-major
+// inside a chunk, padded to the chunk's longest row.
+fd_status fill_sell(const HostCSR &A, HostSELL &S) {
+    const int64_t D = A.D;
+    const int C = S.C;
+    auto len = [&](int32_t r) { return A.rowptr[r + 1] - A.rowptr[r]; };
     int64_t nch = (D + C - 1) / C;
     S.chunk_len.assign(nch, 0);
     S.chunk_ptr.assign(nch + 1, 0);
@@ -355,6 +364,32 @@ fd_status build_sell(const HostCSR &A, int C, int sigma, HostSELL &S) {
         }
     });
     return FD_OK;
+}
+
+// Traversal order of the 3D lattice in pencils: (x, y) tiles of tx by ty
+// sites, each running over all z, tiles in x-then-y order.  Rows stay the
+// CSR rows (C = 1); only the order in which the kernels walk them changes.
+fd_status build_pencil(const HostCSR &A, int L, int tx, int ty, HostSELL &S) {
+    const int64_t D = A.D;
+    if (L < 3 || (int64_t)L * L * L != D || tx < 1 || ty < 1)
+        return fail(FD_ERR_INVALID, "pencil order: need the L^3 lattice and tiles of at least one site");
+    tx = std::min(tx, L);  // a tile wider than the lattice covers it whole
+    ty = std::min(ty, L);
+    S.C = 1;
+    S.sigma = 1;
+    try {
+        S.perm.resize(D);
+    } catch (...) {
+        return fail(FD_ERR_OOM, "pencil order: host allocation");
+    }
+    const int64_t L1 = L, L2 = L1 * L1;
+    int64_t r = 0;
+    for (int y0 = 0; y0 < L; y0 += ty)
+        for (int x0 = 0; x0 < L; x0 += tx)
+            for (int64_t z = 0; z < L; z++)
+                for (int y = y0; y < std::min(L, y0 + ty); y++)
+                    for (int x = x0; x < std::min(L, x0 + tx); x++) S.perm[r++] = (int32_t)(x + L1 * y + L2 * z);
+    return fill_sell(A, S);
 }
 
 void gershgorin(const HostCSR &A, double &lo, double &hi) {

@@ -64,6 +64,8 @@ fd_status build_diagonal(int64_t n, const double *d, HostCSR &A);
 fd_status build_user(int64_t D, const int64_t *rowptr, const uint32_t *col, const double *val,
                      HostCSR &A);
 fd_status build_sell(const HostCSR &A, int C, int sigma, HostSELL &S);
+fd_status fill_sell(const HostCSR &A, HostSELL &S);  // chunks from S.C and S.perm
+fd_status build_pencil(const HostCSR &A, int L, int tx, int ty, HostSELL &S);
 void gershgorin(const HostCSR &A, double &lo, double &hi);
 fd_status cheb_coeffs(int kind, double a, double b, int n, double *mu);
 

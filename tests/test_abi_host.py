@@ -190,3 +190,23 @@ def test_anderson_batch_instance_draws():
     inst = anderson_batch(range(100, 196))
     assert len(inst) == 96
     assert all(20 <= q["L"] <= 64 and 2.0 <= q["W"] < 20.0 and q["skip"] == 2 for q in inst)
+
+
+def test_pencil_order_is_the_csr_in_a_lattice_walk():
+    """Pencil-ordered Anderson: perm walks (x, y) tiles over all z; every
+    stored row is the CSR row it names, unpadded (SELL-1)."""
+    A = O.anderson(5, 1.0, 4.0, 2)
+    m = fd.build_matrix("anderson", fmt="pencil", C_=2, sigma=3, host_only=True, L=5, t=1.0, W=4.0, seed=2)
+    perm, cptr, clen, col, val = m.export_sell()
+    assert np.array_equal(np.sort(perm), np.arange(A.D))
+    L = 5
+    want = [x + L * y + L * L * z for y0 in range(0, L, 3) for x0 in range(0, L, 2) for z in range(L)
+            for y in range(y0, min(L, y0 + 3)) for x in range(x0, min(L, x0 + 2))]
+    assert np.array_equal(perm, want)
+    for r, o in enumerate(perm):
+        a, b = A.rowptr[o], A.rowptr[o + 1]
+        assert clen[r] == b - a
+        assert np.array_equal(col[cptr[r]:cptr[r + 1]], A.col[a:b])
+        assert np.array_equal(val[cptr[r]:cptr[r + 1]], A.val[a:b])
+    with pytest.raises(fd.FDError):
+        fd.build_matrix("hubbard", fmt="pencil", host_only=True, L=6, n_up=3, n_dn=3)

@@ -367,3 +367,33 @@ def test_pick_degree_rule_hubbard8():
     res = fd.solve(m, -0.5, 0.5, 16, 128, 16, 0, max_iter=80, tol=1e-9, V0=start_block(A.D, 128, 0), adapt=1)
     assert res.status == fd.FD_OK
     assert 0.7 * deg <= res.stats["degree"] <= 1.4 * deg  # its own KPM draw
+
+
+@pytest.mark.parametrize("L,tx,ty", [(13, 16, 16), (13, 4, 3), (20, 8, 8), (7, 1, 7)])
+def test_pencil_order_bitwise_equal_to_csr(L, tx, ty):
+    """The pencil walk changes only the order of the rows, not a row's
+    arithmetic: SpMMV and filter (every step form) equal CSR bit for bit,
+    and the filter matches the oracle."""
+    kw = dict(L=L, t=1.0, W=16.5, seed=1)
+    mc = fd.build_matrix("anderson", **kw)
+    mp = fd.build_matrix("anderson", fmt="pencil", C_=tx, sigma=ty, **kw)
+    A = O.anderson(L, 1.0, 16.5, 1)
+    for dt in (torch.float64, torch.float32):
+        X = dev(start_block(A.D, 16, 1), dt)
+        Yc, Yp = torch.empty_like(X), torch.empty_like(X)
+        fd.spmmv(mc, X, Yc)
+        fd.spmmv(mp, X, Yp)
+        alpha, beta = O.scaling(*O.gershgorin(A))
+        for degree in (9, 10):
+            mu = O.cheb_coeffs(1, beta, 0.0, degree)
+            V0 = dev(start_block(A.D, 32, 2), dt)
+            Vc, Vp = V0.clone(), V0.clone()
+            W1, W2 = torch.empty_like(V0), torch.empty_like(V0)
+            fd.cheb_filter(mc, Vc, mu, alpha, beta, W1, W2, 16)
+            fd.cheb_filter(mp, Vp, mu, alpha, beta, W1, W2, 16)
+            torch.cuda.synchronize()
+            assert torch.equal(Vc, Vp)
+            if dt == torch.float64:
+                ref = O.cheb_filter(A, V0.cpu().numpy(), mu, alpha, beta)
+                assert relerr(Vp.cpu().numpy(), ref) <= 1e-12
+        assert torch.equal(Yc, Yp)
