@@ -404,9 +404,12 @@ typedef struct {
  * else FD_ERR_UNSUPPORTED).  params[n_inst]: nb, n_search, n_target and
  * ortho must agree; the window, degree (2..100000, no picker), max_iter,
  * tol, seed and adapt are per instance.  Each outer iteration
- * orthogonalizes and runs Rayleigh-Ritz instance by instance (one batched
- * SpMMV for W = A V), drops the instances that converged or reached
- * max_iter, and filters all others with one graph launch.  V0_host
+ * orthogonalizes and runs Rayleigh-Ritz (one batched SpMMV for W = A V;
+ * with N_s <= 64 every dense step of all instances is one launch, else they
+ * go instance by instance; an instance whose Cholesky fails or whose block
+ * is rank deficient is orthogonalized alone), drops the instances that
+ * converged or reached max_iter, and filters all others with one graph
+ * launch.  V0_host
  * (D_total x N_s) or NULL (instance i starts from SplitMix64(seed_i)).
  * Outputs: evals_host[n_inst x N_t] (row i ascending), evecs_dev
  * (D_total x N_t, ld N_t) or NULL, resid_host[n_inst x N_t] or NULL,

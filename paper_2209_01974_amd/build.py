@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libfd.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("FD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fd_build.cpp", "fd_api.cpp", "fd_spmmv.hip", "fd_hubbard_mf.hip", "fd_batch.hip", "fd_dense.hip", "fd_mlp.hip"]
+SOURCES = ["fd_build.cpp", "fd_api.cpp", "fd_spmmv.hip", "fd_hubbard_mf.hip", "fd_batch.hip", "fd_batch_dense.hip", "fd_dense.hip", "fd_mlp.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(HERE, "..", "include")]
 HIPFLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -457,7 +457,9 @@ void batch_release(fd_batch b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     BatchDev &d = b->dev;
-    void *bufs[] = {d.ptr, d.col, d.val64, d.val32, d.inst, d.alpha, d.beta, d.deg, d.act, d.mu};
+    void *bufs[] = {d.ptr,   d.col,      d.val64,   d.val32,   d.inst,    d.alpha,   d.beta, d.deg,
+                    d.act,   d.mu,       d.off,     d.seg_inst, d.inst_s0, d.rc_inst, d.seg_r0, d.seg_r1,
+                    d.rc_r0};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     d = BatchDev();
@@ -1190,6 +1192,34 @@ fd_status fd_batch_create(int32_t n_inst, const fd_matrix *mats, fd_batch *out) 
     put((void **)&d.beta, dz.data(), n_inst * sizeof(double));
     put((void **)&d.deg, zeros.data(), n_inst * sizeof(int32_t));
     put((void **)&d.act, ones.data(), n_inst * sizeof(int32_t));
+    // row structure of the batched dense steps: reduction slices of up to
+    // 1024 rows (at most 128 per instance) and 32-row rotation chunks
+    std::vector<int32_t> seg_inst, inst_s0(n_inst + 1, 0), rc_inst;
+    std::vector<int64_t> seg_r0, seg_r1, rc_r0;
+    for (int i = 0; i < n_inst; i++) {
+        const int64_t a = b->off[i], Di = b->off[i + 1] - a;
+        const int64_t nsl = std::max<int64_t>(1, std::min<int64_t>(128, (Di + 1023) / 1024));
+        for (int64_t k = 0; k < nsl; k++) {
+            seg_inst.push_back(i);
+            seg_r0.push_back(a + k * Di / nsl);
+            seg_r1.push_back(a + (k + 1) * Di / nsl);
+        }
+        inst_s0[i + 1] = (int32_t)seg_inst.size();
+        for (int64_t r = a; r < a + Di; r += 32) {
+            rc_inst.push_back(i);
+            rc_r0.push_back(r);
+        }
+    }
+    if (rc_inst.size() > 0x7fffffff) st = fail(FD_ERR_UNSUPPORTED, "fd_batch_create: too many rows");
+    d.nseg = (int32_t)seg_inst.size();
+    d.nrc = (int32_t)rc_inst.size();
+    put((void **)&d.off, b->off.data(), b->off.size() * sizeof(int64_t));
+    put((void **)&d.seg_inst, seg_inst.data(), seg_inst.size() * sizeof(int32_t));
+    put((void **)&d.inst_s0, inst_s0.data(), inst_s0.size() * sizeof(int32_t));
+    put((void **)&d.seg_r0, seg_r0.data(), seg_r0.size() * sizeof(int64_t));
+    put((void **)&d.seg_r1, seg_r1.data(), seg_r1.size() * sizeof(int64_t));
+    put((void **)&d.rc_inst, rc_inst.data(), rc_inst.size() * sizeof(int32_t));
+    put((void **)&d.rc_r0, rc_r0.data(), rc_r0.size() * sizeof(int64_t));
     if (st == FD_OK && hipGetDevice(&b->device) != hipSuccess) st = fail(FD_ERR_HIP, "fd_batch_create: device");
     if (st != FD_OK) {
         batch_release(b);
@@ -1326,19 +1356,94 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
     std::memset(&bs, 0, sizeof(bs));
     const int64_t launches0 = b->graph_launches;
     int n_active = n;
+    // Dense steps of all instances at once when N_s <= 64 (one launch per
+    // step for every instance); larger search spaces go instance by instance.
+    const bool dense_b = ns <= 64;
+    const size_t nn = (size_t)ns * ns;
+    DevBuf Gb, Qb, Ub, Thb, Rhob, Pb, Okb, Mkb;
+    std::vector<double> th_all, rho_all;
+    std::vector<int32_t> ok_h(n), mk_h(n);
+    if (dense_b) {
+        FD_TRY(Gb.alloc(n * nn * 8, "batched Gram"));
+        FD_TRY(Qb.alloc(n * nn * 8, "batched transforms"));
+        FD_TRY(Ub.alloc(n * nn * 8, "batched eigenvectors"));
+        FD_TRY(Thb.alloc((size_t)n * ns * 8, "batched Ritz values"));
+        FD_TRY(Rhob.alloc((size_t)n * ns * 8, "batched residuals"));
+        FD_TRY(Pb.alloc((size_t)b->dev.nseg * nn * 8, "batched partial sums"));
+        FD_TRY(Okb.alloc((size_t)n * 4, "batched flags"));
+        FD_TRY(Mkb.alloc((size_t)n * 4, "batched mask"));
+        th_all.resize((size_t)n * ns);
+        rho_all.resize((size_t)n * ns);
+    }
+    double *Gd = (double *)Gb.p, *Qd = (double *)Qb.p, *Ud = (double *)Ub.p, *Thd = (double *)Thb.p,
+           *Rhod = (double *)Rhob.p, *Pd = (double *)Pb.p;
+    int32_t *Okd = (int32_t *)Okb.p, *Mkd = (int32_t *)Mkb.p;
     for (int it = 0; n_active > 0; it++) {
         double ta = now();
-        for (int i = 0; i < n; i++) {
-            if (done[i]) continue;
-            const int64_t Di = b->off[i + 1] - b->off[i];
-            int rank = 0;
-            FD_TRY(orthog_impl(Di, ns, Vd + b->off[i] * ns, ns, ortho, P[i].seed + 0x1000 + it, &rank, s));
+        if (dense_b && ortho == FD_ORTHO_CHOLQR2) {
+            // two Cholesky-QR passes for all active instances; an instance
+            // whose Cholesky fails continues alone with SVQB2
+            std::vector<char> failed(n, 0);
+            for (int pass = 0; pass < 2; pass++) {
+                for (int i = 0; i < n; i++) mk_h[i] = !done[i] && !failed[i];
+                FD_HIP(hipMemcpy(Mkd, mk_h.data(), n * 4, hipMemcpyHostToDevice));
+                FD_TRY(seg_gram(b->dev, ns, Vd, Vd, ns, Mkd, Pd, Gd, s));
+                FD_TRY(batched_cholinv(n, ns, Gd, Qd, Okd, Mkd, s));
+                FD_HIP(hipMemcpyAsync(ok_h.data(), Okd, n * 4, hipMemcpyDeviceToHost, s));
+                FD_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i < n; i++)
+                    if (mk_h[i] && !ok_h[i]) {
+                        failed[i] = 1;
+                        mk_h[i] = 0;
+                    }
+                FD_HIP(hipMemcpy(Mkd, mk_h.data(), n * 4, hipMemcpyHostToDevice));
+                FD_TRY(seg_rotate(b->dev, ns, Vd, ns, Qd, Mkd, s));
+            }
+            for (int i = 0; i < n; i++)
+                if (failed[i]) {
+                    int rank = 0;
+                    FD_TRY(orthog_impl(b->off[i + 1] - b->off[i], ns, Vd + b->off[i] * ns, ns, FD_ORTHO_SVQB2,
+                                       P[i].seed + 0x1000 + it, &rank, s));
+                }
+        } else if (dense_b) {
+            // two SVQB passes for all active instances; an instance whose
+            // block turns out rank deficient continues alone (SVQB2 with
+            // the refill of the clipped directions)
+            std::vector<char> failed(n, 0);
+            for (int pass = 0; pass < 2; pass++) {
+                for (int i = 0; i < n; i++) mk_h[i] = !done[i] && !failed[i];
+                FD_HIP(hipMemcpy(Mkd, mk_h.data(), n * 4, hipMemcpyHostToDevice));
+                FD_TRY(seg_gram(b->dev, ns, Vd, Vd, ns, Mkd, Pd, Gd, s));
+                FD_TRY(batched_svqb(n, ns, Gd, Rhod, Thd, Ud, Qd, Okd, Mkd, s));
+                FD_HIP(hipMemcpyAsync(ok_h.data(), Okd, n * 4, hipMemcpyDeviceToHost, s));
+                FD_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i < n; i++)
+                    if (mk_h[i] && ok_h[i] < ns) {
+                        failed[i] = 1;
+                        mk_h[i] = 0;
+                    }
+                FD_HIP(hipMemcpy(Mkd, mk_h.data(), n * 4, hipMemcpyHostToDevice));
+                FD_TRY(seg_rotate(b->dev, ns, Vd, ns, Qd, Mkd, s));
+            }
+            for (int i = 0; i < n; i++)
+                if (failed[i]) {
+                    int rank = 0;
+                    FD_TRY(orthog_impl(b->off[i + 1] - b->off[i], ns, Vd + b->off[i] * ns, ns, FD_ORTHO_SVQB2,
+                                       P[i].seed + 0x1000 + it, &rank, s));
+                }
+        } else {
+            for (int i = 0; i < n; i++) {
+                if (done[i]) continue;
+                const int64_t Di = b->off[i + 1] - b->off[i];
+                int rank = 0;
+                FD_TRY(orthog_impl(Di, ns, Vd + b->off[i] * ns, ns, ortho, P[i].seed + 0x1000 + it, &rank, s));
+            }
         }
         FD_HIP(hipStreamSynchronize(s));
         double tb = now();
         bs.t_orthog += tb - ta;
         // W = A V for every active instance in one launch, then the dense
-        // Rayleigh-Ritz steps instance by instance
+        // Rayleigh-Ritz steps (all instances at once, or one by one)
         BatchCall c;
         c.mode = 0;
         c.nb = nb;
@@ -1346,11 +1451,29 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
         c.x = Vd; c.ldx = ns; c.bx = nb;
         c.y = Wd; c.ldy = ns; c.by = nb;
         FD_TRY(launch_batch(b->dev, FD_F64, c, s));
+        if (dense_b) {
+            const int32_t *act = b->dev.act;  // the active instances
+            FD_TRY(seg_gram(b->dev, ns, Vd, Wd, ns, act, Pd, Gd, s));
+            FD_TRY(batched_sym(n, ns, Gd, s));
+            FD_TRY(batched_syev(n, ns, Gd, Thd, Ud, act, s));
+            FD_TRY(seg_rotate(b->dev, ns, Vd, ns, Ud, act, s));
+            FD_TRY(seg_rotate(b->dev, ns, Wd, ns, Ud, act, s));
+            FD_TRY(seg_resid(b->dev, ns, Vd, Wd, ns, Thd, act, Pd, Rhod, s));
+            FD_HIP(hipMemcpyAsync(th_all.data(), Thd, (size_t)n * ns * 8, hipMemcpyDeviceToHost, s));
+            FD_HIP(hipMemcpyAsync(rho_all.data(), Rhod, (size_t)n * ns * 8, hipMemcpyDeviceToHost, s));
+            FD_HIP(hipStreamSynchronize(s));
+        }
         n_active = 0;
         for (int i = 0; i < n; i++) {
             if (done[i]) continue;
             const int64_t Di = b->off[i + 1] - b->off[i];
-            FD_TRY(rr_dense(Di, ns, Vd + b->off[i] * ns, Wd + b->off[i] * ns, ns, th[i].data(), rho[i].data(), s));
+            if (dense_b) {
+                std::copy(th_all.begin() + (size_t)i * ns, th_all.begin() + (size_t)(i + 1) * ns, th[i].begin());
+                std::copy(rho_all.begin() + (size_t)i * ns, rho_all.begin() + (size_t)(i + 1) * ns, rho[i].begin());
+            } else {
+                FD_TRY(rr_dense(Di, ns, Vd + b->off[i] * ns, Wd + b->off[i] * ns, ns, th[i].data(), rho[i].data(),
+                                s));
+            }
             st[i].spmmv_count += ns / nb;
             for (int j = 0; j < ns; j++)
                 if (!std::isfinite(th[i][j]) || !std::isfinite(rho[i][j]))

@@ -168,7 +168,29 @@ struct BatchDev {
     int32_t *act = nullptr;  // n_inst: rows take part in the plain SpMMV when act[i] != 0
     double *mu = nullptr;    // n_inst x mstride filter coefficients
     int32_t mstride = 0;
+    // row structure for the batched dense steps: instance row offsets, the
+    // slices of the Gram / residual reductions (slice s of instance i: rows
+    // [seg_r0[s], seg_r1[s]), slices of i: [inst_s0[i], inst_s0[i+1])) and
+    // the 32-row chunks of the rotations
+    int64_t *off = nullptr;
+    int32_t nseg = 0, nrc = 0;
+    int32_t *seg_inst = nullptr, *inst_s0 = nullptr, *rc_inst = nullptr;
+    int64_t *seg_r0 = nullptr, *seg_r1 = nullptr, *rc_r0 = nullptr;
 };
+// Batched dense steps (fd_batch_dense.hip), n <= 64 columns per instance.
+fd_status seg_gram(const BatchDev &B, int n, const double *X, const double *Y, int64_t ld, const int32_t *mask,
+                   double *P, double *G, hipStream_t s);
+fd_status seg_rotate(const BatchDev &B, int n, double *X, int64_t ld, const double *Q, const int32_t *mask,
+                     hipStream_t s);
+fd_status seg_resid(const BatchDev &B, int n, const double *V, const double *W, int64_t ld, const double *theta,
+                    const int32_t *mask, double *P, double *rho, hipStream_t s);
+fd_status batched_sym(int n_inst, int n, double *G, hipStream_t s);
+fd_status batched_cholinv(int n_inst, int n, double *G, double *Q, int32_t *ok, const int32_t *mask, hipStream_t s);
+fd_status batched_syev(int n_inst, int n, const double *S, double *w, double *U, const int32_t *mask, hipStream_t s);
+// SVQB transform Q of each instance from its Gram matrix G (overwritten);
+// rank[i]: directions above the clipping floor.  d: n_inst x n, lam: n_inst x n.
+fd_status batched_svqb(int n_inst, int n, double *G, double *d, double *lam, double *U, double *Q, int32_t *rank,
+                       const int32_t *mask, hipStream_t s);
 struct BatchCall {
     int mode = 0;  // 0: y = A x; 1: first step; 2: second step; 3: step k >= 3
     int k = 0;

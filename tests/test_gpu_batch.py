@@ -187,11 +187,14 @@ def test_batch_errors():
         fd.batch_filter(b, V, [np.ones(2)], [1], [0.1], [0.0], W1, torch.zeros_like(V), 8)
 
 
-def test_solve_batch_vs_dense_and_single():
+@pytest.mark.parametrize("ortho,ns", [(fd.FD_ORTHO_SVQB2, 64), (fd.FD_ORTHO_CHOLQR2, 64), (fd.FD_ORTHO_SVQB2, 128)])
+def test_solve_batch_vs_dense_and_single(ortho, ns):
     """Five uneven instances, 8 pairs nearest tau each (damped delta at
-    tau, or a window), N_s = 64, nb = 16: every instance's eigenvalues match
-    its dense spectrum and the single-instance fd_solve on the same start
-    block; residuals recomputed from the returned vectors."""
+    tau, or a window), nb = 16: every instance's eigenvalues match its dense
+    spectrum and the single-instance fd_solve on the same start block;
+    residuals recomputed from the returned vectors.  N_s = 64 runs the
+    dense steps of all instances at once (batched Gram, Cholesky, Jacobi
+    eigensolve, rotations, residuals); N_s = 128 runs them one by one."""
     kws = [dict(model="anderson", L=8, t=1.0, W=5.0, seed=2), dict(model="anderson", L=10, t=1.0, W=16.5, seed=1),
            dict(model="hubbard", L=6, n_up=3, n_dn=3, t=1.0, U=4.0),
            dict(model="anderson", L=9, t=1.0, W=12.0, seed=7, skip=2),
@@ -203,9 +206,9 @@ def test_solve_batch_vs_dense_and_single():
     adapt = [0, 0, 0, 0, 1]  # [-1, 1] holds 167 eigenvalues of the last: track the window
     mats = [fd.build_matrix(**kw) for kw in kws]
     b = fd.Batch(mats)
-    V0 = start_block(b.D, 64, 11)
-    params = [dict(tau_lo=w[0], tau_hi=w[1], n_target=8, n_search=64, nb=16, degree=d, max_iter=100, tol=1e-9,
-                   adapt=a) for w, d, a in zip(windows, degrees, adapt)]
+    V0 = start_block(b.D, ns, 11)
+    params = [dict(tau_lo=w[0], tau_hi=w[1], n_target=8, n_search=ns, nb=16, degree=d, max_iter=100, tol=1e-9,
+                   adapt=a, ortho=ortho) for w, d, a in zip(windows, degrees, adapt)]
     r = fd.solve_batch(b, params, V0=V0, want_vectors=True)
     assert r.status == fd.FD_OK, (r.bstats, r.stats)
     assert r.bstats["n_converged"] == 5 and r.bstats["graph_launches"] >= 1
@@ -221,8 +224,35 @@ def test_solve_batch_vs_dense_and_single():
         rows = slice(b.off[i], b.off[i + 1])
         Xi = X[rows]
         assert np.linalg.norm(O.spmmv(A, Xi) - Xi * r.evals[i], axis=0).max() <= 1e-9 * normH
-        single = fd.solve(mats[i], lo, hi, 8, 64, 16, degrees[i], max_iter=100, tol=1e-9, V0=V0[rows],
-                          want_vectors=False, adapt=adapt[i])
+        single = fd.solve(mats[i], lo, hi, 8, ns, 16, degrees[i], max_iter=100, tol=1e-9, V0=V0[rows],
+                          want_vectors=False, adapt=adapt[i], ortho=ortho)
         assert single.status == fd.FD_OK
         assert np.abs(single.evals - r.evals[i]).max() <= 1e-10 * normH
         assert abs(single.stats["iters"] - r.stats[i]["iters"]) <= 1
+
+
+@pytest.mark.parametrize("ortho", [fd.FD_ORTHO_SVQB2, fd.FD_ORTHO_CHOLQR2])
+def test_solve_batch_rank_deficient_start_block(ortho):
+    """One instance starts from a block with repeated columns: the batched
+    orthogonalization sees the deficient rank (SVQB) or a failed Cholesky
+    pivot, hands that instance to the one-by-one SVQB2 with refill, and the
+    batch still converges to the dense answer."""
+    kws = [dict(model="anderson", L=8, t=1.0, W=5.0, seed=2), dict(model="hubbard", L=6, n_up=3, n_dn=3, t=1.0, U=4.0),
+           dict(model="anderson", L=9, t=1.0, W=12.0, seed=7, skip=2)]
+    As = [O.anderson(8, 1.0, 5.0, 2), O.hubbard(6, 3, 3, 1.0, 4.0), O.anderson(9, 1.0, 12.0, 7, skip=2)]
+    windows = [(0.0, 0.0), (-0.5, 0.45), (0.0, 0.0)]
+    b = fd.Batch([fd.build_matrix(**kw) for kw in kws])
+    V0 = start_block(b.D, 64, 5)
+    r1 = slice(b.off[1], b.off[2])
+    V0[r1, 32:] = V0[r1, :32]
+    params = [dict(tau_lo=w[0], tau_hi=w[1], n_target=8, n_search=64, nb=16, degree=d, max_iter=100, tol=1e-9,
+                   ortho=ortho) for w, d in zip(windows, (300, 100, 300))]
+    r = fd.solve_batch(b, params, V0=V0)
+    assert r.status == fd.FD_OK, (r.bstats, r.stats)
+    for i, A in enumerate(As):
+        ev = np.linalg.eigvalsh(A.dense())
+        lo, hi = windows[i]
+        tau = 0.5 * (lo + hi)
+        pool = ev if hi <= lo else ev[(ev >= lo) & (ev <= hi)]
+        want = np.sort(pool[np.argsort(np.abs(pool - tau), kind="stable")[:8]])
+        assert np.abs(r.evals[i] - want).max() <= 1e-10 * r.stats[i]["norm_H"], i
