@@ -102,6 +102,17 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
     const int64_t row0 = a * p.nd;
     const int32_t j1 = p.off_d[b + 1];
     int32_t j = p.off_d[b];
+    // four hops per round, all loads of a round independent
+    for (; j + 4 <= j1; j += 4) {
+        const int32_t c0 = p.idx_d[j], c1 = p.idx_d[j + 1], c2 = p.idx_d[j + 2], c3 = p.idx_d[j + 3];
+        const T e0 = p.val_d[j], e1 = p.val_d[j + 1], e2 = p.val_d[j + 2], e3 = p.val_d[j + 3];
+        const V x0 = ld<V>(xq + (row0 + c0) * p.ldx), x1 = ld<V>(xq + (row0 + c1) * p.ldx);
+        const V x2 = ld<V>(xq + (row0 + c2) * p.ldx), x3 = ld<V>(xq + (row0 + c3) * p.ldx);
+        acc0 += e0 * x0;
+        acc1 += e1 * x1;
+        acc0 += e2 * x2;
+        acc1 += e3 * x3;
+    }
     for (; j + 2 <= j1; j += 2) {
         const int32_t c0 = p.idx_d[j], c1 = p.idx_d[j + 1];
         const T e0 = p.val_d[j], e1 = p.val_d[j + 1];
@@ -155,6 +166,16 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     V acc0 = (V)0, acc1 = (V)0;
     const int32_t j1 = p.off_u[a + 1];
     int32_t j = p.off_u[a];
+    for (; j + 4 <= j1; j += 4) {
+        const int32_t c0 = p.idx_u[j], c1 = p.idx_u[j + 1], c2 = p.idx_u[j + 2], c3 = p.idx_u[j + 3];
+        const T e0 = p.val_u[j], e1 = p.val_u[j + 1], e2 = p.val_u[j + 2], e3 = p.val_u[j + 3];
+        const V x0 = ld<V>(xq + ((int64_t)c0 * p.nd + b) * p.ldx), x1 = ld<V>(xq + ((int64_t)c1 * p.nd + b) * p.ldx);
+        const V x2 = ld<V>(xq + ((int64_t)c2 * p.nd + b) * p.ldx), x3 = ld<V>(xq + ((int64_t)c3 * p.nd + b) * p.ldx);
+        acc0 += e0 * x0;
+        acc1 += e1 * x1;
+        acc0 += e2 * x2;
+        acc1 += e3 * x3;
+    }
     for (; j + 2 <= j1; j += 2) {
         const int32_t c0 = p.idx_u[j], c1 = p.idx_u[j + 1];
         const T e0 = p.val_u[j], e1 = p.val_u[j + 1];
