@@ -3,10 +3,11 @@ the launch configuration the benchmark times (autotuned shape), checked on
 sampled rows that the oracle computes one by one from the definition.
 
 * 3D Anderson L=200 (D = 8,000,000, nnz = 56,000,000, W = 16.5, seed 1):
-  SpMMV and a degree-3 fused filter (all three fused step forms) on nb = 64.
+  SpMMV and degree-3 and degree-6 filters (every step form) on nb = 64.
 * Hubbard ring L=14, 7 up + 7 down, U=8 (D = 11,778,624, nnz = 189,364,032):
   SpMMV on nb = 32 with integer-valued blocks, bit-exact in FP64 and FP32,
-  stored (CSR) and matrix-free; a degree-3 matrix-free filter on nb = 32.
+  stored (CSR) and matrix-free; degree-3 and degree-4 matrix-free filters on
+  nb = 32.
 """
 import numpy as np
 import pytest
@@ -50,17 +51,21 @@ def test_anderson200_spmmv_nb64_sampled(anderson200):
     assert err.max() <= 1e-12
 
 
-def test_anderson200_filter_degree3_sampled(anderson200):
+@pytest.mark.parametrize("degree,nrows", [(3, 800), (6, 200)])
+def test_anderson200_filter_sampled(anderson200, degree, nrows):
+    """Degree 3: the first two steps and an odd last step (V updated alone);
+    degree 6: also the recurrence-only and the two-term V steps that make up
+    the benchmark's filter."""
     m, A = anderson200
     fd.autotune(m, "f64", 64)
     alpha, beta = O.scaling(*O.gershgorin(A))
-    mu = O.cheb_coeffs(1, beta, 0.0, 3)
+    mu = O.cheb_coeffs(1, beta, 0.0, degree)
     V = start_block(A.D, 64, 22)
     Vd = torch.from_numpy(V).cuda()
     W1 = torch.empty_like(Vd)
     W2 = torch.empty_like(Vd)
     fd.cheb_filter(m, Vd, mu, alpha, beta, W1, W2, 64)
-    rows = sample_rows(A.D, 2)[:800]
+    rows = sample_rows(A.D, 2)[:nrows]
     got = Vd[torch.from_numpy(rows).cuda()].cpu().numpy()
     ref = O.cheb_filter_rows(A, V, mu, alpha, beta, rows)
     err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
@@ -110,14 +115,16 @@ def test_hubbard14_matfree_spmmv_nb32_integer_bit_exact(hubbard14, hubbard14_mat
     assert np.array_equal(got, O.spmmv_rows(A, X, rows))
 
 
-def test_hubbard14_matfree_filter_degree3_sampled(hubbard14, hubbard14_matfree):
-    """Degree-3 filter (first, second and general step) on nb = 32, sampled
-    rows against the oracle's neighbourhood recursion."""
+@pytest.mark.parametrize("degree", [3, 4])
+def test_hubbard14_matfree_filter_sampled(hubbard14, hubbard14_matfree, degree):
+    """Degree-3 and degree-4 filters (first, second, recurrence-only,
+    two-term and single-term V steps) on nb = 32, sampled rows against the
+    oracle's neighbourhood recursion."""
     _, A = hubbard14
     m = hubbard14_matfree
     fd.autotune(m, "f64", 32)
     alpha, beta = O.scaling(*O.gershgorin(A))
-    mu = O.cheb_coeffs(0, alpha * -1.0 + beta, alpha * 1.0 + beta, 3)
+    mu = O.cheb_coeffs(0, alpha * -1.0 + beta, alpha * 1.0 + beta, degree)
     V = start_block(A.D, 32, 25)
     Vd = torch.from_numpy(V).cuda()
     W1 = torch.empty_like(Vd)
