@@ -27,7 +27,9 @@
  *    are owned by the caller; the library never frees caller memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Kernel-level calls are asynchronous on it; calls that return host data
- *    (fd_rayleigh_ritz, fd_orthog's rank, fd_solve) synchronize that stream.
+ *    (fd_rayleigh_ritz, fd_orthog's rank, fd_kpm_moments, fd_pick_degree,
+ *    fd_lehmann, fd_solve, fd_solve_batch) and the calls that copy host
+ *    parameters first (fd_batch_filter, fd_batch_spmmv) synchronize it.
  *  - The library keeps one device workspace per process for the small dense
  *    steps; calls from several host threads at once are not supported.
  */
@@ -128,12 +130,14 @@ fd_status fd_build_matrix(const fd_model_params *params, fd_format fmt, int32_t 
 fd_status fd_matrix_info(fd_matrix m, int64_t *D, int64_t *nnz, int64_t *stored,
                          double *lam_lo, double *lam_hi);
 
-/* Copy the canonical CSR into caller host arrays of D+1, nnz, nnz entries.  */
+/* Copy the canonical CSR into caller host arrays of D+1, nnz, nnz entries
+ * (FD_FMT_MATFREE stores none: FD_ERR_INVALID).                            */
 fd_status fd_matrix_export_csr(fd_matrix m, int64_t *rowptr, uint32_t *col, double *val);
 
-/* Copy the SELL-C-sigma arrays (fmt == FD_FMT_SELL only) into caller host
- * arrays: perm[D], chunk_ptr[nchunks+1], chunk_len[nchunks], col[stored],
- * val[stored], nchunks = ceil(D / C).                                       */
+/* Copy the SELL-C-sigma arrays (FD_FMT_SELL, or FD_FMT_PENCIL with C = 1)
+ * into caller host arrays: perm[D], chunk_ptr[nchunks+1], chunk_len[nchunks],
+ * col[stored], val[stored], nchunks = ceil(D / C).  Other formats:
+ * FD_ERR_INVALID.                                                           */
 fd_status fd_matrix_export_sell(fd_matrix m, int32_t *perm, int64_t *chunk_ptr,
                                 int32_t *chunk_len, uint32_t *col, double *val);
 
@@ -197,7 +201,7 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R_dev, int64_t l
                          double alpha, double beta, double *W1_dev, double *W2_dev, int64_t ldw,
                          double *mu_host, void *stream);
 
-/* Degree picker network (north of the plain rule): an MLP with FD_MLP_IN
+/* Degree picker network (a refinement of the plain rule): an MLP with FD_MLP_IN
  * inputs (64 Jackson-damped KPM moments of the scaled matrix, then the scaled
  * target window [a, b]), three ReLU layers of FD_MLP_HIDDEN and FD_MLP_OUT
  * outputs (log2 of the degree relative to the KPM rule; log2 of the first

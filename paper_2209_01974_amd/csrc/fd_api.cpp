@@ -438,12 +438,13 @@ struct fd_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     struct Key {
-        int dt = -1, nb = 0, nbund = 0, max_degree = 0;
-        const void *V = nullptr, *W1 = nullptr, *W2 = nullptr;
+        int dt = -1, nb = 0, nbund = 0, max_degree = 0, mstride = 0;
+        const void *V = nullptr, *W1 = nullptr, *W2 = nullptr, *mu = nullptr;
         int64_t ldv = 0, ldw = 0;
         bool operator==(const Key &o) const {
-            return dt == o.dt && nb == o.nb && nbund == o.nbund && max_degree == o.max_degree && V == o.V &&
-                   W1 == o.W1 && W2 == o.W2 && ldv == o.ldv && ldw == o.ldw;
+            return dt == o.dt && nb == o.nb && nbund == o.nbund && max_degree == o.max_degree &&
+                   mstride == o.mstride && V == o.V && W1 == o.W1 && W2 == o.W2 && mu == o.mu && ldv == o.ldv &&
+                   ldw == o.ldw;
         }
     } key;
     int64_t graph_launches = 0, graph_captures = 0;
@@ -542,6 +543,8 @@ fd_status batch_filter_run(fd_batch b, fd_dtype dt, int nb, int nbund, char *V, 
     k.W2 = W2;
     k.ldv = ldv;
     k.ldw = ldw;
+    k.mu = b->dev.mu;  // the kernels take these by value
+    k.mstride = b->dev.mstride;
     if (!b->exec || !(k == b->key)) {
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
