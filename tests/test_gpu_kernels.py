@@ -397,3 +397,74 @@ def test_pencil_order_bitwise_equal_to_csr(L, tx, ty):
                 ref = O.cheb_filter(A, V0.cpu().numpy(), mu, alpha, beta)
                 assert relerr(Vp.cpu().numpy(), ref) <= 1e-12
         assert torch.equal(Yc, Yp)
+
+
+def _arrow(D, seed):
+    """Arrow matrix: row 0 couples to every row (D entries), every other row
+    holds only its diagonal and column 0 -- the most uneven row lengths."""
+    rng = np.random.default_rng(seed)
+    rowptr = np.zeros(D + 1, np.int64)
+    cols, vals = [], []
+    for i in range(D):
+        c = np.arange(D) if i == 0 else np.array([0, i])
+        v = rng.integers(-3, 4, size=c.size).astype(np.float64)
+        cols.append(c)
+        vals.append(v)
+        rowptr[i + 1] = rowptr[i] + c.size
+    col = np.concatenate(cols).astype(np.uint32)
+    val = np.concatenate(vals)
+    # symmetric: A[i][0] = A[0][i]
+    for i in range(1, D):
+        val[rowptr[i]] = val[i]
+    return O.CSR(D, rowptr, col, val)
+
+
+@pytest.mark.parametrize("fmt,C_,sigma", [("csr", 1, 1), ("sell", 32, 256), ("sell", 8, 1)])
+@pytest.mark.parametrize("nb", [1, 8, 64])
+def test_ragged_rows_arrow_matrix(fmt, C_, sigma, nb):
+    """Row lengths 1003 and 2 in one matrix (one ragged SELL chunk against
+    full ones): SpMMV bit-exact on integers, filter within 1e-12."""
+    A = _arrow(1003, 4)
+    m = fd.build_matrix("csr", fmt=fmt, C_=C_, sigma=sigma, csr=(A.rowptr, A.col, A.val))
+    X = int_block(A.D, nb, 6, 1 << 10)
+    Y = torch.empty((A.D, nb), dtype=torch.float64, device="cuda")
+    fd.spmmv(m, dev(X), Y)
+    torch.cuda.synchronize()
+    assert np.array_equal(Y.cpu().numpy(), O.spmmv(A, X))
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    mu = O.cheb_coeffs(0, -0.3, 0.4, 11)
+    V = start_block(A.D, nb, 7)
+    Vd = dev(V)
+    W1, W2 = torch.empty_like(Vd), torch.empty_like(Vd)
+    fd.cheb_filter(m, Vd, mu, alpha, beta, W1, W2, nb)
+    torch.cuda.synchronize()
+    assert relerr(Vd.cpu().numpy(), O.cheb_filter(A, V, mu, alpha, beta)) <= 1e-12
+
+
+@pytest.mark.parametrize("nb", [1, 2, 64])
+def test_one_row_matrix(nb):
+    """D = 1: the smallest matrix every kernel must take."""
+    m = fd.build_matrix("diagonal", diag=np.array([0.75]))
+    X = dev(np.full((1, nb), 2.0))
+    Y = torch.empty_like(X)
+    fd.spmmv(m, X, Y)
+    V = dev(np.full((1, nb), 1.0))
+    W1, W2 = torch.empty_like(V), torch.empty_like(V)
+    mu = O.cheb_coeffs(1, 0.2, 0.0, 6)
+    alpha, beta = 0.8, -0.1  # the Gershgorin interval of a 1 x 1 matrix is a point
+    fd.cheb_filter(m, V, mu, alpha, beta, W1, W2, nb)
+    torch.cuda.synchronize()
+    assert torch.all(Y == 1.5)
+    want = O.cheb_filter(O.diagonal(np.array([0.75])), np.ones((1, nb)), mu, alpha, beta)
+    assert relerr(V.cpu().numpy(), want) <= 1e-14
+
+
+def test_solve_full_search_space():
+    """N_s = D: the search space is the whole space, so one Rayleigh-Ritz
+    gives exact pairs (no filter step is needed)."""
+    d = np.linspace(-1.0, 1.0, 16)
+    m = fd.build_matrix("diagonal", diag=d)
+    r = fd.solve(m, -0.3, 0.3, 4, 16, 8, 10, max_iter=5, tol=1e-9, V0=start_block(16, 16, 1))
+    assert r.status == fd.FD_OK and r.stats["iters"] == 0
+    want = np.sort(d[np.argsort(np.abs(d), kind="stable")[:4]])
+    assert np.abs(r.evals - want).max() <= 1e-13
