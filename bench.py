@@ -247,6 +247,45 @@ def batch_runs(args, fd, np, torch):
     return out
 
 
+def hubbard16_runs(args, fd, np, torch):
+    """Matrix-free SpMMV and Chebyshev steps on the Hubbard ring L=16, 8 up +
+    8 down (D = 165,636,900, the dimension of the paper's Hubbard16), U = 25,
+    8 FP64 vectors: the setting of the paper's matrix-free per-SpMV timing on
+    one CPU node (Sec. 4.2)."""
+    t0 = time.time()
+    m = fd.build_matrix("hubbard", fmt="matfree", L=16, n_up=8, n_dn=8, t=1.0, U=25.0)
+    log("Hubbard L=16 matrix-free: D=%d nnz=%d (not stored), tables in %.1fs" % (m.D, m.nnz, time.time() - t0))
+    out = {"D": m.D, "nnz": m.nnz, "format": "matfree", "U": 25.0}
+    for dt, name, nb in ((torch.float64, "f64", 8), (torch.float64, "f64", 32), (torch.float32, "f32", 8)):
+        shape = fd.autotune(m, name, nb)
+        X = torch.randn((m.D, nb), dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        fd.spmmv(m, X, Y)
+        torch.cuda.synchronize()
+        reps = 10
+        t = time.perf_counter()
+        for _ in range(reps):
+            fd.spmmv(m, X, Y)
+        torch.cuda.synchronize()
+        t_spmmv = (time.perf_counter() - t) / reps
+        alpha, beta = 2.0 / (m.lam_hi - m.lam_lo), -(m.lam_hi + m.lam_lo) / (m.lam_hi - m.lam_lo)
+        W1, W2 = torch.empty_like(X), torch.empty_like(X)
+        deg = 20
+        mu = fd.cheb_coeffs(1, beta, 0.0, deg)
+        t = time.perf_counter()
+        fd.cheb_filter(m, X, mu, alpha, beta, W1, W2, nb)
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t) / deg
+        key = "%s_nb%d" % (name, nb)
+        out[key] = {"spmmv_ms": round(t_spmmv * 1e3, 2), "filter_step_ms": round(t_step * 1e3, 2),
+                    "launch_shape": list(shape)}
+        log("Hubbard L=16 %s: %s" % (key, out[key]))
+        del X, Y, W1, W2
+        torch.cuda.empty_cache()
+    out["paper_context"] = "2.04 s per SpMV with 8 FP64 vectors on one CPU node, matrix-free (Sec. 4.2)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +304,8 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
     ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
     ap.add_argument("--fd-only", action="store_true", help="only the FD eigenpairs/s runs (no Anderson step)")
+    ap.add_argument("--hubbard16", action="store_true",
+                    help="only the matrix-free SpMMV / filter step on the Hubbard ring L=16 (D = 165.6M)")
     ap.add_argument("--batch", action="store_true",
                     help="only the batched workload (96 Anderson instances; filter and FD, batched vs one by one)")
     ap.add_argument("--batch-iters", type=int, default=80, help="max outer iterations per batched FD instance")
@@ -298,6 +339,9 @@ def main():
         return
     if args.batch:
         print(json.dumps({"batch": batch_runs(args, fd, np, torch)}), flush=True)
+        return
+    if args.hubbard16:
+        print(json.dumps({"hubbard16": hubbard16_runs(args, fd, np, torch)}), flush=True)
         return
 
     # ---------------------------------------------------------- workload ----
