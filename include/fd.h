@@ -242,8 +242,8 @@ fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_ta
 /* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
  * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
  * D x nb (allocated and freed here) and keeps the fastest in the handle for
- * (dtype, nb); later calls on this matrix use it.  shape (7 ints, may be
- * NULL) receives order, xcd, iters, grid, nontemporal, wide, tile.
+ * (dtype, nb); later calls on this matrix use it.  shape (8 ints, may be
+ * NULL) receives order, xcd, iters, grid, nontemporal, wide, tile, shfl.
  * Synchronizes.                                                            */
 fd_status fd_autotune(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
 
@@ -268,11 +268,14 @@ int32_t fd_syev_last_sweeps(void);
  * a row (two 16-byte loads per gathered row) instead of 16.  Matrix-free
  * Hubbard matrices use xcd (1: remap as above, else none), nontemporal and
  * tile (down-states per tile of the up-hop pass, 0: the matrix's default).
+ * shfl != 0 (16-byte lanes, at least 4 lanes per row): lanes 0..3 of a row
+ * load 4 of its entries at once and hand them to the row's other lanes by
+ * cross-lane permute, instead of every lane loading every entry.
  * Default: order 0, xcd 2, iters 1, grid 1024, nontemporal 1, wide 0,
- * tile 0.  A shape chosen by fd_autotune for a matrix takes precedence for
- * that matrix.  tile outside [0, 2^20]: FD_ERR_INVALID.                    */
+ * tile 0, shfl 1.  A shape chosen by fd_autotune for a matrix takes
+ * precedence for that matrix.  tile outside [0, 2^20]: FD_ERR_INVALID.     */
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal,
-                        int32_t wide, int32_t tile);
+                        int32_t wide, int32_t tile, int32_t shfl);
 
 /* Lehmann intervals (Lehmann 1963; Sec. 2 determines the target and search
  * intervals of FD from them).  V_dev: D x n block (ld >= n, linearly

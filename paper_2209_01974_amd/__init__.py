@@ -90,7 +90,7 @@ _SIGS = {
     "fd_orthog": [_I64, _I32, _P, _I64, _I32, C.c_uint64, C.POINTER(_I32), _P],
     "fd_rayleigh_ritz": [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P],
     "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
-    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32, _I32, _I32],
+    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32],
     "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
     "fd_autotune": [_P, C.c_int, _I32, _P, _P],
     "fd_kpm_moments": [_P, _I32, _P, _I64, _I32, _D, _D, _P, _P, _I64, _P, _P],
@@ -294,9 +294,9 @@ def syev(S, w, U, stream=None) -> None:
 
 
 def spmmv_tune(order: int = 0, xcd: int = 2, iters: int = 1, grid: int = 1024, nontemporal: int = 1,
-               wide: int = 0, tile: int = 0) -> None:
+               wide: int = 0, tile: int = 0, shfl: int = 1) -> None:
     """Launch shape of the sparse kernels (process-wide; results unchanged)."""
-    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide, tile))
+    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide, tile, shfl))
 
 
 def kpm_moments(m: "Matrix", R, nmom: int, alpha: float, beta: float, stream=None) -> np.ndarray:
@@ -365,7 +365,7 @@ def window_count(mu_kpm: np.ndarray, D: int, a: float, b: float) -> float:
 
 def autotune(m: "Matrix", dtype: str = "f64", nb: int = 64, stream=None) -> tuple:
     """Pick the fastest launch shape of the fused step for (m, dtype, nb)."""
-    shape = (C.c_int32 * 7)()
+    shape = (C.c_int32 * 8)()
     _check(lib().fd_autotune(m.handle, FD_F64 if dtype == "f64" else FD_F32, nb, shape, _stream(stream)))
     return tuple(shape)
 

@@ -117,6 +117,9 @@ fd_status upload(fd_matrix m) {
         perm.assign(d.nslots, -1);
         std::copy(S.perm.begin(), S.perm.end(), perm.begin());
     }
+    d.maxlen = 0;
+    for (size_t c = 0; c + 1 < ptr.size(); c++)
+        d.maxlen = std::max<int32_t>(d.maxlen, (int32_t)((ptr[c + 1] - ptr[c]) >> d.cshift));
     std::vector<float> v32(val->size());
     for (size_t i = 0; i < val->size(); i++) v32[i] = (float)(*val)[i];
     const size_t st = std::max<size_t>(1, (size_t)d.stored);
@@ -755,6 +758,7 @@ fd_status fd_autotune(fd_matrix m, fd_dtype dt, int32_t nb, int32_t *shape, void
         shape[4] = t.nontemporal;
         shape[5] = t.wide;
         shape[6] = t.tile;
+        shape[7] = t.shfl;
     }
     return FD_OK;
 }
@@ -889,7 +893,7 @@ fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, dou
 }
 
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal, int32_t wide,
-                        int32_t tile) {
+                        int32_t tile, int32_t shfl) {
     if (order < 0 || order > 1 || xcd < 0 || xcd > 2 || (order == 1 && xcd == 2) || iters < 0 || grid < 0 ||
         grid > (1 << 24) || tile < 0 || tile > (1 << 20))
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
@@ -901,6 +905,7 @@ fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid,
     t.nontemporal = nontemporal != 0;
     t.wide = wide != 0;
     t.tile = tile;
+    t.shfl = shfl != 0;
     return FD_OK;
 }
 

@@ -84,6 +84,7 @@ struct SpmmvTune {
     int nontemporal = 1;  // 1: streamed operands bypass the caches
     int wide = 0;         // 1: 32 bytes per lane (nb >= 16)
     int tile = 0;         // matrix-free Hubbard: down-state tile of the up pass (0: 16)
+    int shfl = 1;         // 1: a row's entries by cross-lane permute (nb with >= 4 lanes per row)
 };
 
 // One layout serves CSR and SELL: "slot" s of the device format belongs to
@@ -94,6 +95,7 @@ struct DevMatrix {
     int64_t D = 0;
     int32_t cshift = 0;
     int64_t nslots = 0;        // D rounded up to a multiple of C
+    int32_t maxlen = 0;        // longest row (C = 1) or chunk
     int64_t stored = 0;        // value slots incl. padding
     uint32_t *ptr = nullptr;   // nchunks + 1
     uint32_t *col = nullptr;   // stored

@@ -47,6 +47,7 @@ struct KArgs {
     int32_t xcd;
     int32_t order;     // 0: a block walks `iters` consecutive groups; 1: grid-stride
     int32_t sg;        // xcd == 2: logical blocks per super-group
+    int32_t maxlen;    // longest row (CSR) or chunk (SELL)
     const T *x; int64_t ldx, bx;
     T *y; int64_t ldy, by;
     const T *z; int64_t ldz, bz;
@@ -60,6 +61,10 @@ template <typename V>
 __device__ __forceinline__ void st(void *p, V x) { *reinterpret_cast<V *>(p) = x; }
 // streamed operands (read or written once per step): non-temporal, so that
 // they do not evict the gathered rows of x from L2 / Infinity Cache
+// acc + a x with one rounding per element (an explicit FMA, so that every
+// variant of the entry loop rounds the same way)
+template <typename V, typename T>
+__device__ __forceinline__ V fmav(T a, V x, V acc) { return __builtin_elementwise_fma((V)a, x, acc); }
 template <typename V, bool NT>
 __device__ __forceinline__ V lds(const void *p) {
     if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
@@ -71,7 +76,7 @@ __device__ __forceinline__ void sts(void *p, V x) {
     else *reinterpret_cast<V *>(p) = x;
 }
 
-template <typename T, int VEC, int G, int MODE, bool PERM, bool NT>
+template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, bool SHFL>
 __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int RPB = 256 / G;
@@ -132,6 +137,43 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
         }
         const T *xq = x + q * VEC;
         V acc0 = (V)0, acc1 = (V)0;
+        if constexpr (SHFL && G >= 4) {
+            // Entries in rounds of 4: lanes 0..3 of the row load one entry
+            // each (one load instruction for the indices, one for the
+            // values, instead of one broadcast load per entry), the other
+            // lanes of the row take them by cross-lane permute, then all 4
+            // gathers go out at once.  The rounds run to the longest row of
+            // the matrix, so every lane of a row takes part in every permute.
+            const int rbase = (int)(threadIdx.x & 63) - q;
+            for (int j0 = 0; j0 < p.maxlen; j0 += 4) {
+                const uint32_t jj = (uint32_t)(j0 + q);
+                uint32_t cm = 0;
+                T am = (T)0;
+                if (q < 4 && jj < len) {
+                    const uint32_t k = base + jj * step;
+                    cm = p.col[k];
+                    am = p.val[k];
+                }
+                uint32_t cc[4];
+                T aa[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    cc[u] = (uint32_t)__shfl((int)cm, rbase + u, 64);
+                    aa[u] = __shfl(am, rbase + u, 64);
+                }
+                V xs[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    xs[u] = ((uint32_t)(j0 + u) < len) ? ld<V>(xq + (int64_t)cc[u] * p.ldx) : (V)0;
+                // even entries to acc0, odd ones to acc1, as in the plain loop
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    if ((uint32_t)(j0 + u) < len) {
+                        if (u & 1) acc1 = fmav(aa[u], xs[u], acc1);
+                        else acc0 = fmav(aa[u], xs[u], acc0);
+                    }
+            }
+        } else {
         uint32_t j = 0;
         for (; j + 4 <= len; j += 4) {
             const uint32_t k = base + j * step;
@@ -143,16 +185,17 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             const V x1 = ld<V>(xq + (int64_t)c1 * p.ldx);
             const V x2 = ld<V>(xq + (int64_t)c2 * p.ldx);
             const V x3 = ld<V>(xq + (int64_t)c3 * p.ldx);
-            acc0 += a0 * x0;
-            acc1 += a1 * x1;
-            acc0 += a2 * x2;
-            acc1 += a3 * x3;
+            acc0 = fmav(a0, x0, acc0);
+            acc1 = fmav(a1, x1, acc1);
+            acc0 = fmav(a2, x2, acc0);
+            acc1 = fmav(a3, x3, acc1);
         }
-        for (; j < len; ++j) {
-            const uint32_t k = base + j * step;
-            const uint32_t cj = p.col[k];
-            const T aj = p.val[k];
-            acc0 += aj * ld<V>(xq + (int64_t)cj * p.ldx);
+        // at most three entries left (j is a multiple of 4): even, odd, even
+        if (j < len) acc0 = fmav(p.val[base + j * step], ld<V>(xq + (int64_t)p.col[base + j * step] * p.ldx), acc0);
+        if (j + 1 < len)
+            acc1 = fmav(p.val[base + (j + 1) * step], ld<V>(xq + (int64_t)p.col[base + (j + 1) * step] * p.ldx), acc1);
+        if (j + 2 < len)
+            acc0 = fmav(p.val[base + (j + 2) * step], ld<V>(xq + (int64_t)p.col[base + (j + 2) * step] * p.ldx), acc0);
         }
         const V acc = acc0 + acc1;
         T *yr = y + row * p.ldy + q * VEC;
@@ -194,6 +237,7 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     p.perm = M.perm;
     p.nslots = M.nslots;
     p.cshift = M.cshift;
+    p.maxlen = M.maxlen;
     constexpr int RPB = 256 / G;
     const int lg = __builtin_ctz((unsigned)c.nb);
     const int di = std::is_same<T, double>::value ? 0 : 1;
@@ -237,7 +281,12 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     dim3 grid((unsigned)gx, (unsigned)c.nbundles), block(256);
     const bool perm = M.perm != nullptr;
     const bool nt = tn.nontemporal != 0;
-#define FD_L(MODE, PERM, NT) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT>), grid, block, 0, s, p)
+    const bool sh = tn.shfl != 0 && G >= 4;
+#define FD_L(MODE, PERM, NT)                                                                                  \
+    do {                                                                                                      \
+        if (sh) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, true>), grid, block, 0, s, p);          \
+        else hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, false>), grid, block, 0, s, p);           \
+    } while (0)
 #define FD_L2(MODE, PERM) \
     if (nt) FD_L(MODE, PERM, true); else FD_L(MODE, PERM, false)
     switch (c.mode * 2 + (perm ? 1 : 0)) {
@@ -280,10 +329,12 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     hipEvent_t e0, e1;
     FD_HIP(hipEventCreate(&e0));
     FD_HIP(hipEventCreate(&e1));
+    // order, xcd, iters, grid, nontemporal, wide, tile, shfl
     const SpmmvTune cands[] = {
-        {0, 2, 1, 512, 1, 0}, {0, 2, 1, 1024, 1, 0}, {0, 2, 1, 2048, 1, 0}, {0, 2, 1, 8192, 1, 0},
-        {0, 2, 2, 2048, 1, 0}, {0, 0, 1, 0, 1, 0},   {0, 1, 1, 0, 1, 0},    {1, 1, 1, 4096, 1, 0},
-        {0, 2, 1, 1024, 1, 1}, {0, 2, 1, 4096, 1, 1}, {0, 0, 1, 0, 1, 1},
+        {0, 2, 1, 512, 1, 0, 0, 1},  {0, 2, 1, 1024, 1, 0, 0, 1}, {0, 2, 1, 2048, 1, 0, 0, 1},
+        {0, 2, 1, 8192, 1, 0, 0, 1}, {0, 2, 2, 2048, 1, 0, 0, 1}, {0, 0, 1, 0, 1, 0, 0, 1},
+        {0, 1, 1, 0, 1, 0, 0, 1},    {1, 1, 1, 4096, 1, 0, 0, 1}, {0, 2, 1, 1024, 1, 1, 0, 0},
+        {0, 2, 1, 4096, 1, 1, 0, 0}, {0, 2, 1, 2048, 1, 0, 0, 0}, {0, 2, 1, 8192, 1, 0, 0, 0},
     };
     // matrix-free Hubbard: down-state tile of the up pass, XCD remap on/off
     const SpmmvTune mf_cands[] = {

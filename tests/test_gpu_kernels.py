@@ -255,17 +255,18 @@ def test_stream_kernels_exact(n):
     assert torch.equal(c, a + 1.5)
 
 
-@pytest.mark.parametrize("order,xcd,iters,grid,nt,wide", [(0, 1, 0, 0, 0, 0), (0, 0, 4, 0, 1, 0),
-                                                          (1, 1, 0, 1024, 1, 0), (1, 0, 0, 96, 0, 0),
-                                                          (0, 2, 1, 64, 1, 1), (0, 0, 1, 0, 1, 1)])
-def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt, wide):
+@pytest.mark.parametrize("order,xcd,iters,grid,nt,wide,shfl", [(0, 1, 0, 0, 0, 0, 0), (0, 0, 4, 0, 1, 0, 0),
+                                                               (1, 1, 0, 1024, 1, 0, 0), (1, 0, 0, 96, 0, 0, 0),
+                                                               (0, 2, 1, 64, 1, 1, 0), (0, 0, 1, 0, 1, 1, 0),
+                                                               (0, 2, 1, 1024, 1, 0, 1), (1, 1, 0, 512, 0, 0, 1)])
+def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt, wide, shfl):
     """Every launch shape computes each row the same way: bitwise equal."""
     m, A = build("hub8", "sell", 32, 256)
     X = dev(start_block(A.D, 16, 1))
     Y0 = torch.empty_like(X)
     fd.spmmv(m, X, Y0)
     try:
-        fd.spmmv_tune(order, xcd, iters, grid, nt, wide)
+        fd.spmmv_tune(order, xcd, iters, grid, nt, wide, 0, shfl)
         Y1 = torch.empty_like(X)
         fd.spmmv(m, X, Y1)
         lo, hi = O.gershgorin(A)
