@@ -268,12 +268,15 @@ int32_t fd_syev_last_sweeps(void);
  * a row (two 16-byte loads per gathered row) instead of 16.  Matrix-free
  * Hubbard matrices use xcd (1: remap as above, else none), nontemporal and
  * tile (down-states per tile of the up-hop pass, 0: the matrix's default).
- * shfl != 0 (16-byte lanes, at least 4 lanes per row): lanes 0..3 of a row
- * load 4 of its entries at once and hand them to the row's other lanes by
- * cross-lane permute, instead of every lane loading every entry.
+ * shfl (entry loop): 0, every lane of a row loads every entry; 1 (at
+ * least 4 lanes per row, else as 0), lanes 0..3 of a row load 4 of its
+ * entries at once and hand them to the row's other lanes by cross-lane
+ * permute; 2 (at least 8 lanes per row, else as 1), the same with lanes
+ * 0..7 and 8 entries at once.
  * Default: order 0, xcd 2, iters 1, grid 1024, nontemporal 1, wide 0,
- * tile 0, shfl 1.  A shape chosen by fd_autotune for a matrix takes
- * precedence for that matrix.  tile outside [0, 2^20]: FD_ERR_INVALID.     */
+ * tile 0, shfl 2.  A shape chosen by fd_autotune for a matrix takes
+ * precedence for that matrix.  tile outside [0, 2^20] or shfl outside
+ * [0, 2]: FD_ERR_INVALID.                                                  */
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal,
                         int32_t wide, int32_t tile, int32_t shfl);
 

@@ -294,7 +294,7 @@ def syev(S, w, U, stream=None) -> None:
 
 
 def spmmv_tune(order: int = 0, xcd: int = 2, iters: int = 1, grid: int = 1024, nontemporal: int = 1,
-               wide: int = 0, tile: int = 0, shfl: int = 1) -> None:
+               wide: int = 0, tile: int = 0, shfl: int = 2) -> None:
     """Launch shape of the sparse kernels (process-wide; results unchanged)."""
     _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide, tile, shfl))
 

@@ -895,7 +895,7 @@ fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, dou
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal, int32_t wide,
                         int32_t tile, int32_t shfl) {
     if (order < 0 || order > 1 || xcd < 0 || xcd > 2 || (order == 1 && xcd == 2) || iters < 0 || grid < 0 ||
-        grid > (1 << 24) || tile < 0 || tile > (1 << 20))
+        grid > (1 << 24) || tile < 0 || tile > (1 << 20) || shfl < 0 || shfl > 2)
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
     SpmmvTune &t = spmmv_tune();
     t.order = order;
@@ -905,7 +905,7 @@ fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid,
     t.nontemporal = nontemporal != 0;
     t.wide = wide != 0;
     t.tile = tile;
-    t.shfl = shfl != 0;
+    t.shfl = shfl;
     return FD_OK;
 }
 

@@ -84,7 +84,7 @@ struct SpmmvTune {
     int nontemporal = 1;  // 1: streamed operands bypass the caches
     int wide = 0;         // 1: 32 bytes per lane (nb >= 16)
     int tile = 0;         // matrix-free Hubbard: down-state tile of the up pass (0: 16)
-    int shfl = 1;         // 1: a row's entries by cross-lane permute (nb with >= 4 lanes per row)
+    int shfl = 2;         // entry loop: 0 plain; 1 permute rounds of 4 (>= 4 lanes per row); 2 of 8 (>= 8)
 };
 
 // One layout serves CSR and SELL: "slot" s of the device format belongs to

@@ -9,9 +9,11 @@
 // Mapping on a 64-wide wavefront: a row of the block (nb values) is split
 // over G lanes that each own VEC consecutive values (16-byte loads when the
 // row is wide enough); a wave covers 64/G rows at a time, a 256-thread block
-// 256/G rows, and each block walks `iters` such row groups.  Matrix entries
-// of a row are broadcast to its G lanes; the gathered rows x[col] are read
-// with one 16-byte load per lane.  With SELL-C-sigma the C rows of a chunk
+// 256/G rows, and each block walks `iters` such row groups.  The first 4
+// or 8 lanes of a row load that many of its entries (column, value) at once
+// and pass them to the row's other lanes by cross-lane permute (with fewer
+// lanes per row, every lane loads every entry as a broadcast); the gathered
+// rows x[col] are read with one 16-byte load per lane.  With SELL-C-sigma the C rows of a chunk
 // read entry j from consecutive addresses (coalesced); CSR is SELL-1-1.
 // The rows in flight form one compact window (small blocks in launch order)
 // so that the gathered neighbours of a row are found in L2 / Infinity Cache;
@@ -76,7 +78,7 @@ __device__ __forceinline__ void sts(void *p, V x) {
     else *reinterpret_cast<V *>(p) = x;
 }
 
-template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, bool SHFL>
+template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, int SH>
 __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int RPB = 256 / G;
@@ -136,42 +138,54 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             if constexpr (MODE == 2 || MODE == 3 || MODE == 5) vi = lds<V, NT>(vr);
         }
         const T *xq = x + q * VEC;
+        // the row's own x (the beta term): loaded with the streams, so that
+        // its latency is not added after the gathers
+        V xi = (V)0;
+        if constexpr (MODE != 0) xi = ld<V>(xq + row * p.ldx);
         V acc0 = (V)0, acc1 = (V)0;
-        if constexpr (SHFL && G >= 4) {
-            // Entries in rounds of 4: lanes 0..3 of the row load one entry
-            // each (one load instruction for the indices, one for the
+        if constexpr (SH != 0) {
+            // Entries in load rounds of LW: lanes 0..LW-1 of the row load one
+            // entry each (one load instruction for the indices, one for the
             // values, instead of one broadcast load per entry), the other
-            // lanes of the row take them by cross-lane permute, then all 4
-            // gathers go out at once.  The rounds run to the longest row of
-            // the matrix, so every lane of a row takes part in every permute.
+            // lanes of the row take them by cross-lane permute, 4 at a time,
+            // and the gathers go out together (the compiler issues all LW
+            // gathers of a round before their FMAs).  The rounds run to the
+            // longest row of the matrix, so every lane of a row takes part in
+            // every permute.
+            constexpr int LW = SH == 2 ? 8 : 4;
+            constexpr int GW = 4;
+            static_assert(G >= LW, "a load round needs LW lanes per row");
             const int rbase = (int)(threadIdx.x & 63) - q;
-            for (int j0 = 0; j0 < p.maxlen; j0 += 4) {
+            for (int j0 = 0; j0 < p.maxlen; j0 += LW) {
                 const uint32_t jj = (uint32_t)(j0 + q);
                 uint32_t cm = 0;
                 T am = (T)0;
-                if (q < 4 && jj < len) {
+                if (q < LW && jj < len) {
                     const uint32_t k = base + jj * step;
                     cm = p.col[k];
                     am = p.val[k];
                 }
-                uint32_t cc[4];
-                T aa[4];
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    cc[u] = (uint32_t)__shfl((int)cm, rbase + u, 64);
-                    aa[u] = __shfl(am, rbase + u, 64);
-                }
-                V xs[4];
+                for (int r0 = 0; r0 < LW; r0 += GW) {
+                    uint32_t cc[GW];
+                    T aa[GW];
 #pragma unroll
-                for (int u = 0; u < 4; u++)
-                    xs[u] = ((uint32_t)(j0 + u) < len) ? ld<V>(xq + (int64_t)cc[u] * p.ldx) : (V)0;
-                // even entries to acc0, odd ones to acc1, as in the plain loop
-#pragma unroll
-                for (int u = 0; u < 4; u++)
-                    if ((uint32_t)(j0 + u) < len) {
-                        if (u & 1) acc1 = fmav(aa[u], xs[u], acc1);
-                        else acc0 = fmav(aa[u], xs[u], acc0);
+                    for (int u = 0; u < GW; u++) {
+                        cc[u] = (uint32_t)__shfl((int)cm, rbase + r0 + u, 64);
+                        aa[u] = __shfl(am, rbase + r0 + u, 64);
                     }
+                    V xs[GW];
+#pragma unroll
+                    for (int u = 0; u < GW; u++)
+                        xs[u] = ((uint32_t)(j0 + r0 + u) < len) ? ld<V>(xq + (int64_t)cc[u] * p.ldx) : (V)0;
+                    // even entries to acc0, odd ones to acc1, as in the plain loop
+#pragma unroll
+                    for (int u = 0; u < GW; u++)
+                        if ((uint32_t)(j0 + r0 + u) < len) {
+                            if ((r0 + u) & 1) acc1 = fmav(aa[u], xs[u], acc1);
+                            else acc0 = fmav(aa[u], xs[u], acc0);
+                        }
+                }
             }
         } else {
         uint32_t j = 0;
@@ -202,7 +216,6 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
         if constexpr (MODE == 0) {
             sts<V, NT>(yr, acc);
         } else {
-            const V xi = ld<V>(xq + row * p.ldx);
             V t = p.a * acc + p.b * xi;
             if constexpr (MODE == 1) {
                 sts<V, NT>(yr, t);
@@ -281,11 +294,15 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     dim3 grid((unsigned)gx, (unsigned)c.nbundles), block(256);
     const bool perm = M.perm != nullptr;
     const bool nt = tn.nontemporal != 0;
-    const bool sh = tn.shfl != 0 && G >= 4;
-#define FD_L(MODE, PERM, NT)                                                                                  \
-    do {                                                                                                      \
-        if (sh) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, true>), grid, block, 0, s, p);          \
-        else hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, false>), grid, block, 0, s, p);           \
+    // entry loop: 0 plain, 1 permute rounds of 4 entries, 2 load rounds of 8;
+    // each form needs its lanes per row, else the next smaller one is used
+    const int sh = (tn.shfl >= 2 && G >= 8) ? 2 : (tn.shfl != 0 && G >= 4 ? 1 : 0);
+    constexpr int S1 = G >= 4 ? 1 : 0, S2 = G >= 8 ? 2 : S1;
+#define FD_L(MODE, PERM, NT)                                                                            \
+    do {                                                                                                \
+        if (sh == 2) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S2>), grid, block, 0, s, p);  \
+        else if (sh == 1) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S1>), grid, block, 0, s, p); \
+        else hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, 0>), grid, block, 0, s, p);        \
     } while (0)
 #define FD_L2(MODE, PERM) \
     if (nt) FD_L(MODE, PERM, true); else FD_L(MODE, PERM, false)
@@ -331,10 +348,11 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     FD_HIP(hipEventCreate(&e1));
     // order, xcd, iters, grid, nontemporal, wide, tile, shfl
     const SpmmvTune cands[] = {
-        {0, 2, 1, 512, 1, 0, 0, 1},  {0, 2, 1, 1024, 1, 0, 0, 1}, {0, 2, 1, 2048, 1, 0, 0, 1},
-        {0, 2, 1, 8192, 1, 0, 0, 1}, {0, 2, 2, 2048, 1, 0, 0, 1}, {0, 0, 1, 0, 1, 0, 0, 1},
-        {0, 1, 1, 0, 1, 0, 0, 1},    {1, 1, 1, 4096, 1, 0, 0, 1}, {0, 2, 1, 1024, 1, 1, 0, 0},
-        {0, 2, 1, 4096, 1, 1, 0, 0}, {0, 2, 1, 2048, 1, 0, 0, 0}, {0, 2, 1, 8192, 1, 0, 0, 0},
+        {0, 2, 1, 512, 1, 0, 0, 2},  {0, 2, 1, 1024, 1, 0, 0, 2}, {0, 2, 1, 2048, 1, 0, 0, 2},
+        {0, 2, 1, 8192, 1, 0, 0, 2}, {0, 2, 2, 2048, 1, 0, 0, 2}, {0, 0, 1, 0, 1, 0, 0, 2},
+        {0, 1, 1, 0, 1, 0, 0, 2},    {1, 1, 1, 4096, 1, 0, 0, 2}, {0, 2, 1, 2048, 1, 0, 0, 1},
+        {0, 2, 1, 8192, 1, 0, 0, 1}, {0, 2, 1, 1024, 1, 1, 0, 0}, {0, 2, 1, 4096, 1, 1, 0, 0},
+        {0, 2, 1, 2048, 1, 0, 0, 0}, {0, 2, 1, 8192, 1, 0, 0, 0},
     };
     // matrix-free Hubbard: down-state tile of the up pass, XCD remap on/off
     const SpmmvTune mf_cands[] = {

@@ -164,6 +164,9 @@ def test_matfree_argument_errors():
     assert e.value.status == fd.FD_ERR_INVALID
     with pytest.raises(fd.FDError):
         fd.spmmv_tune(tile=-1)
+    for bad in (-1, 3):
+        with pytest.raises(fd.FDError):
+            fd.spmmv_tune(shfl=bad)
     fd.spmmv_tune()
 
 

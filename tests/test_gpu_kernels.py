@@ -258,7 +258,10 @@ def test_stream_kernels_exact(n):
 @pytest.mark.parametrize("order,xcd,iters,grid,nt,wide,shfl", [(0, 1, 0, 0, 0, 0, 0), (0, 0, 4, 0, 1, 0, 0),
                                                                (1, 1, 0, 1024, 1, 0, 0), (1, 0, 0, 96, 0, 0, 0),
                                                                (0, 2, 1, 64, 1, 1, 0), (0, 0, 1, 0, 1, 1, 0),
-                                                               (0, 2, 1, 1024, 1, 0, 1), (1, 1, 0, 512, 0, 0, 1)])
+                                                               (0, 2, 1, 1024, 1, 0, 1), (1, 1, 0, 512, 0, 0, 1),
+                                                               (0, 2, 1, 2048, 1, 1, 1), (0, 2, 1, 1024, 1, 0, 2),
+                                                               (0, 2, 1, 8192, 1, 0, 1), (1, 1, 0, 512, 0, 1, 2),
+                                                               (1, 0, 0, 96, 1, 1, 2)])
 def test_launch_shapes_give_identical_results(order, xcd, iters, grid, nt, wide, shfl):
     """Every launch shape computes each row the same way: bitwise equal."""
     m, A = build("hub8", "sell", 32, 256)
