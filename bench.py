@@ -312,8 +312,9 @@ def main():
     ap.add_argument("--adapt", type=int, choices=[0, 1, 2], default=1,
                     help="filter window of the FD runs: 0 fixed, 1 tracked by the N_t-th Ritz value, "
                          "2 tracked by the Lehmann radius")
-    ap.add_argument("--hub-fmt", choices=["csr", "sell", "matfree"], default="matfree",
-                    help="storage of the Hubbard matrices in the FD runs (matfree: tensor-product form)")
+    ap.add_argument("--hub-fmt", choices=["csr", "sell", "matfree"], default="csr",
+                    help="storage of the Hubbard matrices in the FD runs (matfree: tensor-product form, "
+                         "fastest at nb <= 8; csr at nb >= 32)")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
