@@ -1178,6 +1178,7 @@ fd_status fd_batch_create(int32_t n_inst, const fd_matrix *mats, fd_batch *out) 
     BatchDev &d = b->dev;
     d.n_inst = n_inst;
     d.D = D;
+    for (int64_t row = 0; row < D; row++) d.maxlen = std::max<int32_t>(d.maxlen, (int32_t)(ptr[row + 1] - ptr[row]));
     fd_status st = FD_OK;
     auto put = [&](void **dst, const void *src, size_t bytes) {
         if (st != FD_OK) return;

@@ -8,6 +8,8 @@
 //
 // Lane mapping as in the single-matrix kernel: a row of nb values is split
 // over G lanes of VEC values (16 bytes); blockIdx.y selects the bundle.
+// With 4 or more lanes per row, the row's first 4 or 8 lanes load that many
+// entries at once and pass them on by cross-lane permute.
 // Row groups are dealt to the 8 XCDs in interleaved chunks of CHUNK rows, so
 // that the near neighbours of a row (+-1, +-L for a 3D stencil) stay in one
 // XCD's L2.
@@ -29,6 +31,7 @@ template <typename T>
 struct BArgs {
     int64_t D;
     int32_t k, mstride;
+    int32_t maxlen;  // longest row of the union
     const uint32_t *__restrict__ ptr;
     const uint32_t *__restrict__ col;
     const T *__restrict__ val;
@@ -50,6 +53,9 @@ template <typename V>
 __device__ __forceinline__ V ldn(const void *p) { return __builtin_nontemporal_load(reinterpret_cast<const V *>(p)); }
 template <typename V>
 __device__ __forceinline__ void stn(void *p, V x) { __builtin_nontemporal_store(x, reinterpret_cast<V *>(p)); }
+// acc + a x, one rounding per element in every form of the entry loop
+template <typename V, typename T>
+__device__ __forceinline__ V fmab(T a, V x, V acc) { return __builtin_elementwise_fma((V)a, x, acc); }
 
 // MODE 0: y = A x (rows of active instances)
 // MODE 1: y = alpha_i A x + beta_i x
@@ -87,22 +93,59 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
         vi = ldn<V>(vr);
     }
     if constexpr (MODE >= 3) zi = ldn<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+    V xi = (V)0;
+    if constexpr (MODE != 0) xi = ldg<V>(xq + row * p.ldx);
     const uint32_t j0 = p.ptr[row], j1 = p.ptr[row + 1];
     V acc0 = (V)0, acc1 = (V)0;
-    uint32_t jj = j0;
-    for (; jj + 2 <= j1; jj += 2) {
-        const uint32_t c0 = p.col[jj], c1 = p.col[jj + 1];
-        const T e0 = p.val[jj], e1 = p.val[jj + 1];
-        acc0 += e0 * ldg<V>(xq + (int64_t)c0 * p.ldx);
-        acc1 += e1 * ldg<V>(xq + (int64_t)c1 * p.ldx);
+    if constexpr (G >= 4) {
+        // rounds of LW entries: lanes 0..LW-1 of the row load one each, the
+        // row's lanes take them by permute; the rounds run to the longest
+        // row of the union, so all lanes of a live row take part in every
+        // permute (a row's lanes return together, and a permute reads only
+        // lanes of its own row)
+        constexpr int LW = G >= 8 ? 8 : 4;
+        const uint32_t len = j1 - j0;
+        const int rbase = (int)(threadIdx.x & 63) - q;
+        for (int r0 = 0; r0 < p.maxlen; r0 += LW) {
+            const uint32_t jq = (uint32_t)(r0 + q);
+            uint32_t cm = 0;
+            T am = (T)0;
+            if (q < LW && jq < len) {
+                cm = p.col[j0 + jq];
+                am = p.val[j0 + jq];
+            }
+            uint32_t cc[LW];
+            T aa[LW];
+#pragma unroll
+            for (int u = 0; u < LW; u++) {
+                cc[u] = (uint32_t)__shfl((int)cm, rbase + u, 64);
+                aa[u] = __shfl(am, rbase + u, 64);
+            }
+            V xs[LW];
+#pragma unroll
+            for (int u = 0; u < LW; u++) xs[u] = ((uint32_t)(r0 + u) < len) ? ldg<V>(xq + (int64_t)cc[u] * p.ldx) : (V)0;
+#pragma unroll
+            for (int u = 0; u < LW; u++)
+                if ((uint32_t)(r0 + u) < len) {
+                    if (u & 1) acc1 = fmab(aa[u], xs[u], acc1);
+                    else acc0 = fmab(aa[u], xs[u], acc0);
+                }
+        }
+    } else {
+        uint32_t jj = j0;
+        for (; jj + 2 <= j1; jj += 2) {
+            const uint32_t c0 = p.col[jj], c1 = p.col[jj + 1];
+            const T e0 = p.val[jj], e1 = p.val[jj + 1];
+            acc0 = fmab(e0, ldg<V>(xq + (int64_t)c0 * p.ldx), acc0);
+            acc1 = fmab(e1, ldg<V>(xq + (int64_t)c1 * p.ldx), acc1);
+        }
+        if (jj < j1) acc0 = fmab(p.val[jj], ldg<V>(xq + (int64_t)p.col[jj] * p.ldx), acc0);
     }
-    if (jj < j1) acc0 += p.val[jj] * ldg<V>(xq + (int64_t)p.col[jj] * p.ldx);
     const V acc = acc0 + acc1;
     T *yr = p.y + bnd * p.by + row * p.ldy + q * VEC;
     if constexpr (MODE == 0) {
         stn<V>(yr, acc);
     } else {
-        const V xi = ldg<V>(xq + row * p.ldx);
         const double sc = MODE == 1 ? 1.0 : 2.0;
         const T a = (T)(sc * p.alpha[i]), bb = (T)(sc * p.beta[i]);
         V t = a * acc + bb * xi;
@@ -137,6 +180,7 @@ fd_status launch_bt(const BatchDev &B, const T *val, const BatchCall &c, hipStre
     p.D = B.D;
     p.k = c.k;
     p.mstride = B.mstride;
+    p.maxlen = B.maxlen;
     p.ptr = B.ptr; p.col = B.col; p.val = val; p.inst = B.inst;
     p.alpha = B.alpha; p.beta = B.beta; p.deg = B.deg; p.act = B.act; p.mu = B.mu;
     p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;

@@ -162,6 +162,7 @@ struct BatchDev {
     int32_t n_inst = 0;
     int64_t D = 0;
     uint32_t *ptr = nullptr, *col = nullptr;  // D + 1, nnz (columns already shifted)
+    int32_t maxlen = 0;                       // longest row
     double *val64 = nullptr;
     float *val32 = nullptr;
     uint16_t *inst = nullptr;  // row -> instance
