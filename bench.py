@@ -79,16 +79,17 @@ def dense_bytes(D, ns):
 
 
 # ------------------------------------------------------------- helpers ----
-def traffic_from_profile(kernel_src: str):
+def traffic_from_profile(kernel_src: str, site_order: str):
     """HBM bytes per launch of the fused step from the committed rocprofv3
-    PMC summary, if it was taken on the current kernel source."""
+    PMC summary, if it was taken on the current kernel source and the same
+    site numbering of the matrix."""
     path = os.path.join(ROOT, "profiles", "chebyshev_steps_anderson200_nb64_f64_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         prof = json.load(f)
     h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if prof.get("kernel_source_sha256") != h:
+    if prof.get("kernel_source_sha256") != h or prof.get("site_order") != site_order:
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -297,6 +298,8 @@ def main():
     ap.add_argument("--degree", type=int, default=500)
     ap.add_argument("--fmt", choices=["csr", "sell", "pencil"], default="csr",
                     help="storage / walk of the Anderson matrix (pencil: (x, y) tiles of C x sigma over all z)")
+    ap.add_argument("--tiles", default="100x40",
+                    help="Anderson site numbering: TXxTY numbers sites along (x, y) tiles over all z, 0 = natural")
     ap.add_argument("--C", type=int, default=32)
     ap.add_argument("--sigma", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -348,9 +351,13 @@ def main():
     # ---------------------------------------------------------- workload ----
     L, nb, ns, degree = args.L, args.nb, args.ns, args.degree
     t0 = time.time()
-    m = fd.build_matrix("anderson", fmt=args.fmt, C_=args.C, sigma=args.sigma, L=L, t=1.0, W=16.5, seed=1)
+    tiles = (0, 0) if args.tiles in ("0", "") or args.fmt == "pencil" else tuple(int(v) for v in args.tiles.split("x"))
+    m = fd.build_matrix("anderson", fmt=args.fmt, C_=args.C, sigma=args.sigma, L=L, t=1.0, W=16.5, seed=1,
+                        tiles=tiles)
     D, nnz = m.D, m.nnz
-    log("built Anderson L=%d D=%d nnz=%d (%s) in %.1fs" % (L, D, nnz, args.fmt, time.time() - t0))
+    site_order = "(x, y) tiles %dx%d over all z" % tiles if tiles[0] else "natural (x + L y + L^2 z)"
+    log("built Anderson L=%d D=%d nnz=%d (%s, sites %s) in %.1fs" % (L, D, nnz, args.fmt, site_order,
+                                                                     time.time() - t0))
     lam_lo, lam_hi = m.lam_lo, m.lam_hi
     alpha, beta = 2.0 / (lam_hi - lam_lo), -(lam_hi + lam_lo) / (lam_hi - lam_lo)
     g = torch.Generator(device=dev)
@@ -424,7 +431,10 @@ def main():
     avg_launch = t_filter / launches
     achieved = fb / t_filter / 1e9
     per_launch = fb / launches
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2209_01974_amd", "csrc", "fd_spmmv.hip"))
+    traffic = None
+    if (L, nb, args.fmt) == (200, 64, "csr"):
+        traffic = traffic_from_profile(os.path.join(ROOT, "paper_2209_01974_amd", "csrc", "fd_spmmv.hip"),
+                                       site_order)
     n5, n3 = filter_step_counts(degree)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -439,7 +449,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 1), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "anderson3d_L%d_W16.5_seed1" % L, "D": D, "nnz": nnz,
-                      "n_search": ns, "nb": nb, "degree": degree, "format": args.fmt,
+                      "n_search": ns, "nb": nb, "degree": degree, "format": args.fmt, "site_order": site_order,
                       "target": "128 pairs nearest E=0 (damped delta)", "parallelism": "single GPU",
                       "launch_shape": list(shape)},
            "roofline": roofline,
@@ -518,8 +528,8 @@ def main():
         out["cpu_baseline"] = {"value": round(cb / tc / 1e9, 2), "unit": "GB/s", "cores": O.num_threads(),
                                "kind": "oracle",
                                "sample": "unfused FP64 filter, degree %d, one bundle of nb=%d on Anderson L=%d "
-                                         "(%.1f s); same algorithmic byte count as the GPU filter"
-                                         % (args.cpu_degree, nb, L, tc)}
+                                         "(natural site numbering; %.1f s); same algorithmic byte count as the "
+                                         "GPU filter" % (args.cpu_degree, nb, L, tc)}
         log("cpu baseline %.2f GB/s in %.1fs" % (cb / tc / 1e9, tc))
 
     print(json.dumps(out), flush=True)

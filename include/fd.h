@@ -73,6 +73,14 @@ typedef enum {
  *   hopping -t, on-site energy W (u_{i+skip} - 1/2), u_k the k-th output
  *   (from 0) of SplitMix64 seeded with `seed` (top 53 bits times 2^-53),
  *   L >= 3, skip >= 0 (draws already used, e.g. for L and W themselves).
+ *   tile_x, tile_y (both 0: the numbering above): sites numbered along a
+ *   walk of (x, y) tiles of tile_x by tile_y sites instead, tiles in
+ *   x-then-y order, each tile over all z (z outermost inside the tile, then
+ *   y, then x); row r is the r-th site of the walk.  The matrix is P A P^T
+ *   of the naturally numbered one (the same entries, each site keeps its
+ *   on-site energy), so its spectrum is the same; a site's lattice
+ *   neighbours lie within tile_x * tile_y rows except across tile edges.
+ *   Not with FD_FMT_PENCIL (which walks the natural numbering).
  * FD_DIAGONAL: n entries from `diag` (host).
  * FD_USER_CSR: D rows, rowptr[D+1] (int64), col (uint32, ascending per row),
  *   val (double); host arrays, copied.  D < 2^32.                          */
@@ -88,6 +96,7 @@ typedef struct {
     const uint32_t *col;    /* FD_USER_CSR */
     const double *val;      /* FD_USER_CSR */
     int64_t skip;           /* FD_ANDERSON_3D */
+    int32_t tile_x, tile_y; /* FD_ANDERSON_3D: tiled site numbering (0, 0: natural) */
 } fd_model_params;
 
 typedef struct fd_matrix_s *fd_matrix; /* opaque, owned by the library */

@@ -41,7 +41,8 @@ class ModelParams(C.Structure):
     _fields_ = [("model", C.c_int), ("L", C.c_int32), ("n_up", C.c_int32), ("n_dn", C.c_int32),
                 ("periodic", C.c_int32), ("t", C.c_double), ("U", C.c_double), ("W", C.c_double),
                 ("seed", C.c_uint64), ("n", C.c_int64), ("diag", C.c_void_p), ("D", C.c_int64),
-                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p), ("skip", C.c_int64)]
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p), ("skip", C.c_int64),
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32)]
 
 
 class SolveParams(C.Structure):
@@ -214,16 +215,19 @@ class Matrix:
 
 def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host_only: bool = False,
                  L: int = 0, n_up: int = 0, n_dn: int = 0, periodic: bool = True, t: float = 1.0,
-                 U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None, skip: int = 0) -> Matrix:
+                 U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None, skip: int = 0,
+                 tiles=(0, 0)) -> Matrix:
     """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"} and fmt in
     {"csr", "sell", "matfree", "pencil"} ("matfree": Hubbard only, C_ = default up-pass tile;
-    "pencil": Anderson only, C_ x sigma = (x, y) tile of the walk)."""
+    "pencil": Anderson only, C_ x sigma = (x, y) tile of the walk).  tiles = (tile_x, tile_y):
+    Anderson sites numbered along the tile walk ((0, 0): natural numbering)."""
     p = ModelParams()
     keep = []
     codes = {"hubbard": FD_HUBBARD_RING, "anderson": FD_ANDERSON_3D, "diagonal": FD_DIAGONAL, "csr": FD_USER_CSR}
     p.model = codes[model]
     p.L, p.n_up, p.n_dn, p.periodic = L, n_up, n_dn, int(periodic)
     p.t, p.U, p.W, p.seed, p.skip = t, U, W, seed, skip
+    p.tile_x, p.tile_y = int(tiles[0]), int(tiles[1])
     if diag is not None:
         d = np.ascontiguousarray(diag, dtype=np.float64)
         keep.append(d)

@@ -619,7 +619,15 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
     }
     switch (p->model) {
         case FD_HUBBARD_RING: st = build_hubbard(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->csr); break;
-        case FD_ANDERSON_3D: st = build_anderson(p->L, p->t, p->W, p->seed, p->skip, m->csr); break;
+        case FD_ANDERSON_3D:
+            if (p->tile_x < 0 || p->tile_y < 0 || (p->tile_x == 0) != (p->tile_y == 0))
+                st = fail(FD_ERR_INVALID, "Anderson: tile_x and tile_y both 0 (natural numbering) or both >= 1");
+            else if (p->tile_x > 0 && fmt == FD_FMT_PENCIL)
+                st = fail(FD_ERR_INVALID, "Anderson: the pencil walk needs the natural site numbering");
+            else
+                st = build_anderson(p->L, p->t, p->W, p->seed, p->skip, m->csr);
+            if (st == FD_OK && p->tile_x > 0) st = relabel_tiles(p->L, p->tile_x, p->tile_y, m->csr);
+            break;
         case FD_DIAGONAL: st = build_diagonal(p->n, p->diag, m->csr); break;
         case FD_USER_CSR: st = build_user(p->D, p->rowptr, p->col, p->val, m->csr); break;
         default: st = fail(FD_ERR_INVALID, "fd_build_matrix: unknown model");

@@ -366,15 +366,28 @@ fd_status fill_sell(const HostCSR &A, HostSELL &S) {
     return FD_OK;
 }
 
-// Traversal order of the 3D lattice in pencils: (x, y) tiles of tx by ty
-// sites, each running over all z, tiles in x-then-y order.  Rows stay the
-// CSR rows (C = 1); only the order in which the kernels walk them changes.
+// Walk of the L^3 lattice in pencils: (x, y) tiles of tx by ty sites, tiles
+// in x-then-y order, each tile running over all z (z outermost inside the
+// tile, then y, then x).  walk[r] = natural index x + L y + L^2 z of the r-th
+// site; tiles wider than the lattice cover it whole.
+static void tile_walk(int L, int tx, int ty, int32_t *walk) {
+    tx = std::min(tx, L);
+    ty = std::min(ty, L);
+    const int64_t L1 = L, L2 = L1 * L1;
+    int64_t r = 0;
+    for (int y0 = 0; y0 < L; y0 += ty)
+        for (int x0 = 0; x0 < L; x0 += tx)
+            for (int64_t z = 0; z < L; z++)
+                for (int y = y0; y < std::min(L, y0 + ty); y++)
+                    for (int x = x0; x < std::min(L, x0 + tx); x++) walk[r++] = (int32_t)(x + L1 * y + L2 * z);
+}
+
+// Pencil order: rows stay the CSR rows (C = 1); only the order in which the
+// kernels walk them changes (the row permutation is the tile walk).
 fd_status build_pencil(const HostCSR &A, int L, int tx, int ty, HostSELL &S) {
     const int64_t D = A.D;
     if (L < 3 || (int64_t)L * L * L != D || tx < 1 || ty < 1)
         return fail(FD_ERR_INVALID, "pencil order: need the L^3 lattice and tiles of at least one site");
-    tx = std::min(tx, L);  // a tile wider than the lattice covers it whole
-    ty = std::min(ty, L);
     S.C = 1;
     S.sigma = 1;
     try {
@@ -382,14 +395,54 @@ fd_status build_pencil(const HostCSR &A, int L, int tx, int ty, HostSELL &S) {
     } catch (...) {
         return fail(FD_ERR_OOM, "pencil order: host allocation");
     }
-    const int64_t L1 = L, L2 = L1 * L1;
-    int64_t r = 0;
-    for (int y0 = 0; y0 < L; y0 += ty)
-        for (int x0 = 0; x0 < L; x0 += tx)
-            for (int64_t z = 0; z < L; z++)
-                for (int y = y0; y < std::min(L, y0 + ty); y++)
-                    for (int x = x0; x < std::min(L, x0 + tx); x++) S.perm[r++] = (int32_t)(x + L1 * y + L2 * z);
+    tile_walk(L, tx, ty, S.perm.data());
     return fill_sell(A, S);
+}
+
+// Tiled site numbering: the r-th site of the tile walk becomes row r, i.e.
+// B = P A P^T with P the walk's permutation (B_rs = A_{walk[r], walk[s]}),
+// columns ascending per row.  Same entries, same spectrum; a site's lattice
+// neighbours lie within tx ty rows of it except across tile edges.
+fd_status relabel_tiles(int L, int tx, int ty, HostCSR &A) {
+    const int64_t D = A.D;
+    if (L < 3 || (int64_t)L * L * L != D || tx < 1 || ty < 1)
+        return fail(FD_ERR_INVALID, "tiled numbering: need the L^3 lattice and tiles of at least one site");
+    HostCSR B;
+    std::vector<int32_t> walk, inv;
+    try {
+        walk.resize(D);
+        inv.resize(D);
+        B.rowptr.resize(D + 1);
+        B.col.resize(A.col.size());
+        B.val.resize(A.val.size());
+    } catch (...) {
+        return fail(FD_ERR_OOM, "tiled numbering: host allocation");
+    }
+    tile_walk(L, tx, ty, walk.data());
+    for (int64_t r = 0; r < D; r++) inv[walk[r]] = (int32_t)r;
+    B.D = D;
+    B.rowptr[0] = 0;
+    for (int64_t r = 0; r < D; r++) B.rowptr[r + 1] = B.rowptr[r] + (A.rowptr[walk[r] + 1] - A.rowptr[walk[r]]);
+    parallel_for(D, [&](int64_t r0, int64_t r1) {
+        std::vector<std::pair<uint32_t, double>> row;
+        for (int64_t r = r0; r < r1; r++) {
+            const int64_t o = walk[r];
+            row.clear();
+            for (int64_t k = A.rowptr[o]; k < A.rowptr[o + 1]; k++) row.emplace_back((uint32_t)inv[A.col[k]], A.val[k]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<uint32_t, double> &a, const std::pair<uint32_t, double> &b) {
+                          return a.first < b.first;
+                      });
+            int64_t k = B.rowptr[r];
+            for (const auto &e : row) {
+                B.col[k] = e.first;
+                B.val[k] = e.second;
+                k++;
+            }
+        }
+    });
+    A = std::move(B);
+    return FD_OK;
 }
 
 void gershgorin(const HostCSR &A, double &lo, double &hi) {

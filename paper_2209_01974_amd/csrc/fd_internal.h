@@ -66,6 +66,7 @@ fd_status build_user(int64_t D, const int64_t *rowptr, const uint32_t *col, cons
 fd_status build_sell(const HostCSR &A, int C, int sigma, HostSELL &S);
 fd_status fill_sell(const HostCSR &A, HostSELL &S);  // chunks from S.C and S.perm
 fd_status build_pencil(const HostCSR &A, int L, int tx, int ty, HostSELL &S);
+fd_status relabel_tiles(int L, int tx, int ty, HostCSR &A);  // sites numbered along the tile walk
 void gershgorin(const HostCSR &A, double &lo, double &hi);
 fd_status cheb_coeffs(int kind, double a, double b, int n, double *mu);
 

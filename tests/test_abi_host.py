@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 import paper_2209_01974_amd as fd
+from lattice_walk import permuted_csr, tile_walk
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -193,6 +194,33 @@ def test_anderson_batch_instance_draws():
     inst = anderson_batch(range(100, 196))
     assert len(inst) == 96
     assert all(20 <= q["L"] <= 64 and 2.0 <= q["W"] < 20.0 and q["skip"] == 2 for q in inst)
+
+
+@pytest.mark.parametrize("L,tx,ty", [(6, 4, 3), (5, 2, 2), (6, 1, 1), (5, 9, 2), (7, 7, 7)])
+def test_anderson_tiled_numbering_is_the_permuted_matrix(L, tx, ty):
+    """Tiled site numbering: the matrix is P A P^T of the naturally numbered
+    oracle matrix, bit for bit; one tile over the whole (x, y) plane walks
+    the natural order itself."""
+    A = O.anderson(L, 1.0, 6.0, 3)
+    p = tile_walk(L, tx, ty)
+    assert np.array_equal(p, [x + L * y + L * L * z for y0 in range(0, L, ty) for x0 in range(0, L, tx)
+                              for z in range(L) for y in range(y0, min(L, y0 + ty))
+                              for x in range(x0, min(L, x0 + tx))])
+    assert np.array_equal(np.sort(p), np.arange(A.D))
+    m = fd.build_matrix("anderson", host_only=True, L=L, t=1.0, W=6.0, seed=3, tiles=(tx, ty))
+    _same_csr(m, permuted_csr(A, p))
+    if tx >= L and ty >= L:
+        assert np.array_equal(p, np.arange(A.D))
+        _same_csr(m, A)
+
+
+def test_anderson_tiled_numbering_argument_errors():
+    for tiles in ((3, 0), (0, 2), (-1, -1)):
+        with pytest.raises(fd.FDError) as e:
+            fd.build_matrix("anderson", host_only=True, L=5, t=1.0, W=1.0, tiles=tiles)
+        assert e.value.status == fd.FD_ERR_INVALID
+    with pytest.raises(fd.FDError):
+        fd.build_matrix("anderson", fmt="pencil", C_=2, sigma=2, host_only=True, L=5, t=1.0, W=1.0, tiles=(2, 2))
 
 
 def test_pencil_order_is_the_csr_in_a_lattice_walk():

@@ -3,7 +3,10 @@ the launch configuration the benchmark times (autotuned shape), checked on
 sampled rows that the oracle computes one by one from the definition.
 
 * 3D Anderson L=200 (D = 8,000,000, nnz = 56,000,000, W = 16.5, seed 1):
-  SpMMV and degree-3 and degree-6 filters (every step form) on nb = 64.
+  SpMMV and degree-3 and degree-6 filters (every step form) on nb = 64, in
+  the natural site numbering and in the tiled one (100 x 40 tiles), the
+  latter against the natural oracle with the block permuted:
+  (P A P^T X)[r] = (A P^T X)[walk[r]].
 * Hubbard ring L=14, 7 up + 7 down, U=8 (D = 11,778,624, nnz = 189,364,032):
   SpMMV on nb = 32 with integer-valued blocks, bit-exact in FP64 and FP32,
   stored (CSR) and matrix-free; degree-3 and degree-4 matrix-free filters on
@@ -14,6 +17,7 @@ import pytest
 
 import oracle as O
 from fd_inputs import int_block, start_block
+from lattice_walk import tile_walk
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -68,6 +72,47 @@ def test_anderson200_filter_sampled(anderson200, degree, nrows):
     rows = sample_rows(A.D, 2)[:nrows]
     got = Vd[torch.from_numpy(rows).cuda()].cpu().numpy()
     ref = O.cheb_filter_rows(A, V, mu, alpha, beta, rows)
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def anderson200_tiled(anderson200):
+    m = fd.build_matrix("anderson", L=200, t=1.0, W=16.5, seed=1, tiles=(100, 40))
+    assert (m.D, m.nnz) == (8_000_000, 56_000_000)
+    walk = tile_walk(200, 100, 40)
+    inv = np.empty_like(walk)
+    inv[walk] = np.arange(walk.size)
+    return m, anderson200[1], walk, inv
+
+
+def test_anderson200_tiled_spmmv_nb64_sampled(anderson200_tiled):
+    m, A, walk, inv = anderson200_tiled
+    fd.autotune(m, "f64", 64)
+    X = start_block(A.D, 64, 23)
+    Yd = torch.empty((A.D, 64), dtype=torch.float64, device="cuda")
+    fd.spmmv(m, torch.from_numpy(X).cuda(), Yd)
+    rows = sample_rows(A.D, 3)
+    got = Yd[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref = O.spmmv_rows(A, X[inv], walk[rows])
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("degree,nrows", [(3, 400), (6, 150)])
+def test_anderson200_tiled_filter_sampled(anderson200_tiled, degree, nrows):
+    m, A, walk, inv = anderson200_tiled
+    fd.autotune(m, "f64", 64)
+    alpha, beta = O.scaling(*O.gershgorin(A))
+    mu = O.cheb_coeffs(1, beta, 0.0, degree)
+    V = start_block(A.D, 64, 24)
+    Vd = torch.from_numpy(V).cuda()
+    W1 = torch.empty_like(Vd)
+    W2 = torch.empty_like(Vd)
+    fd.cheb_filter(m, Vd, mu, alpha, beta, W1, W2, 64)
+    rows = sample_rows(A.D, 4)[:nrows]
+    got = Vd[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref = O.cheb_filter_rows(A, V[inv], mu, alpha, beta, walk[rows])
     err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert err.max() <= 1e-12
 

@@ -9,6 +9,7 @@ import pytest
 
 import oracle as O
 from fd_inputs import int_block, start_block
+from lattice_walk import anderson_tiled
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -31,6 +32,9 @@ MATS = {
     "hub8": (dict(model="hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0), lambda: O.hubbard(8, 4, 4, 1.0, 4.0)),
     "hub7": (dict(model="hubbard", L=7, n_up=3, n_dn=2, t=1.0, U=2.5), lambda: O.hubbard(7, 3, 2, 1.0, 2.5)),
     "and13": (dict(model="anderson", L=13, t=1.0, W=16.5, seed=1), lambda: O.anderson(13, 1.0, 16.5, 1)),
+    # sites numbered along (x, y) tiles of 5 x 4 (ragged at the lattice edge)
+    "and12t": (dict(model="anderson", L=12, t=1.0, W=16.5, seed=1, tiles=(5, 4)),
+               lambda: anderson_tiled(12, 1.0, 16.5, 1, 5, 4)),
 }
 FMTS = [("csr", 1, 1), ("sell", 32, 256), ("sell", 64, 1), ("sell", 8, 1 << 20)]
 
@@ -52,7 +56,7 @@ def test_spmmv_fp64_parity(name, fmt, C_, sigma, nb):
     assert relerr(Y.cpu().numpy(), O.spmmv(A, X)) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["hub8", "and13"])
+@pytest.mark.parametrize("name", ["hub8", "and13", "and12t"])
 @pytest.mark.parametrize("fmt,C_,sigma", FMTS[:2])
 @pytest.mark.parametrize("nb", [1, 4, 8, 64])
 def test_spmmv_integer_bit_exact(name, fmt, C_, sigma, nb):
@@ -60,6 +64,9 @@ def test_spmmv_integer_bit_exact(name, fmt, C_, sigma, nb):
     if name == "and13":
         kw = dict(kw, W=0.0)  # integer values
         A = O.anderson(13, 1.0, 0.0, 1)
+    elif name == "and12t":
+        kw = dict(kw, W=0.0)
+        A = anderson_tiled(12, 1.0, 0.0, 1, 5, 4)
     else:
         A = MATS[name][1]()
     m = fd.build_matrix(fmt=fmt, C_=C_, sigma=sigma, **kw)
@@ -103,7 +110,7 @@ def test_spmmv_ld_and_errors():
 
 
 # ------------------------------------------------------------------ filter --
-@pytest.mark.parametrize("name", ["hub8", "and13"])
+@pytest.mark.parametrize("name", ["hub8", "and13", "and12t"])
 @pytest.mark.parametrize("fmt,C_,sigma", FMTS[:2])
 @pytest.mark.parametrize("nb,nbund,concurrent", [(1, 2, False), (8, 3, True), (16, 2, False), (64, 1, False)])
 def test_filter_fp64_parity(name, fmt, C_, sigma, nb, nbund, concurrent):
