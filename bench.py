@@ -91,7 +91,7 @@ def traffic_from_profile(kernel_src: str, site_order: str):
     h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     if prof.get("kernel_source_sha256") != h or prof.get("site_order") != site_order:
         return None
-    return prof.get("hbm_bytes_per_launch")
+    return prof.get("hbm_bytes_per_launch"), prof.get("launch_shape")
 
 
 def fd_runs(args, fd, np):
@@ -368,11 +368,13 @@ def main():
         c = torch.empty_like(a)
         fd.stream(0, a, c, stream=stream)
         torch.cuda.synchronize()
+        shape = fd.autotune(m, "f64", nb, stream=stream)
         V1 = torch.randn((D, nb), generator=g, dtype=torch.float64, device=dev)
         Z1, Z2 = torch.empty_like(V1), torch.empty_like(V1)
         fd.cheb_filter(m, V1, fd.cheb_coeffs(1, beta, 0.0, 12), alpha, beta, Z1, Z2, nb, stream=stream)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_sample": True, "copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+        print(json.dumps({"pmc_sample": True, "launch_shape": list(shape), "copy_bytes_read": n * 8,
+                          "copy_bytes_written": n * 8,
                           "launches_mode5": 5, "launches_mode4": 5,
                           "algorithmic_bytes_mode5": fused_bytes(nnz, D, nb, 8, 5),
                           "algorithmic_bytes_mode4": fused_bytes(nnz, D, nb, 8, 3),
@@ -431,17 +433,19 @@ def main():
     avg_launch = t_filter / launches
     achieved = fb / t_filter / 1e9
     per_launch = fb / launches
-    traffic = None
+    traffic, traffic_shape = None, None
     if (L, nb, args.fmt) == (200, 64, "csr"):
-        traffic = traffic_from_profile(os.path.join(ROOT, "paper_2209_01974_amd", "csrc", "fd_spmmv.hip"),
-                                       site_order)
+        tp = traffic_from_profile(os.path.join(ROOT, "paper_2209_01974_amd", "csrc", "fd_spmmv.hip"), site_order)
+        if tp is not None:
+            traffic, traffic_shape = tp
     n5, n3 = filter_step_counts(degree)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_spmmv<double,2,32,MODE 4|5> (Chebyshev steps, FP64, nb=64; per launch averaged "
                           "over a filter application: %d steps with the V update, %d without, 2 first steps)"
                           % (n5, n3),
-                "algorithmic_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_launch * 1e6, 2)}
+                "algorithmic_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_launch * 1e6, 2),
+                "traffic_launch_shape": traffic_shape}
     del W
     torch.cuda.empty_cache()
 

@@ -348,9 +348,10 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     FD_HIP(hipEventCreate(&e1));
     // order, xcd, iters, grid, nontemporal, wide, tile, shfl
     const SpmmvTune cands[] = {
-        {0, 2, 1, 512, 1, 0, 0, 2},  {0, 2, 1, 1024, 1, 0, 0, 2}, {0, 2, 1, 2048, 1, 0, 0, 2},
-        {0, 2, 1, 8192, 1, 0, 0, 2}, {0, 2, 2, 2048, 1, 0, 0, 2}, {0, 0, 1, 0, 1, 0, 0, 2},
-        {0, 1, 1, 0, 1, 0, 0, 2},    {1, 1, 1, 4096, 1, 0, 0, 2}, {0, 2, 1, 2048, 1, 0, 0, 1},
+        {0, 2, 1, 256, 1, 0, 0, 2},  {0, 2, 1, 512, 1, 0, 0, 2},  {0, 2, 1, 1024, 1, 0, 0, 2},
+        {0, 2, 1, 2048, 1, 0, 0, 2}, {0, 2, 1, 8192, 1, 0, 0, 2}, {0, 2, 2, 2048, 1, 0, 0, 2},
+        {0, 0, 1, 0, 1, 0, 0, 2},    {0, 1, 1, 0, 1, 0, 0, 2},    {1, 1, 1, 4096, 1, 0, 0, 2},
+        {0, 2, 1, 512, 1, 0, 0, 1},  {0, 2, 1, 1024, 1, 0, 0, 1}, {0, 2, 1, 2048, 1, 0, 0, 1},
         {0, 2, 1, 8192, 1, 0, 0, 1}, {0, 2, 1, 1024, 1, 1, 0, 0}, {0, 2, 1, 4096, 1, 1, 0, 0},
         {0, 2, 1, 2048, 1, 0, 0, 0}, {0, 2, 1, 8192, 1, 0, 0, 0},
     };
