@@ -13,7 +13,9 @@ residual 1e-9 ||H||, target window tracked during the iteration.  Labels:
 log2 of the degree factor (relative to the rule) with the fewest SpMMVs to
 convergence over a sweep, and log2 of the true N_t-th distance over the
 rule's estimate.  Evaluation instances are larger (Hubbard L = 12, Anderson
-L in [32, 48]) and not seen in training.
+L in [32, 48]) and not seen in training; their windows must hold 2 N_t
+eigenvalues by a fine KPM count (1024 moments), so that every instance is a
+solvable problem.
 """
 from __future__ import annotations
 
@@ -24,7 +26,7 @@ import time
 
 import numpy as np
 
-from . import FD_OK, MLP_NPARAMS, build_matrix, mlp_adam, mlp_forward, mlp_grad, pick_degree, solve
+from . import FD_OK, MLP_NPARAMS, build_matrix, kpm_moments, mlp_adam, mlp_forward, mlp_grad, pick_degree, solve
 
 FACTORS = np.array([0.5, 0.71, 1.0, 1.41, 2.0])
 NT, NS, NB = 8, 32, 16
@@ -44,9 +46,12 @@ def sample(rng, big: bool):
     return kw
 
 
-def instance(rng, big: bool, max_degree: int):
-    """A matrix and a target window whose rule degree stays below max_degree."""
-    for _ in range(20):
+def instance(rng, big: bool, max_degree: int, strict: bool = False):
+    """A matrix and a target window whose rule degree stays below max_degree.
+    strict: the window must also hold 2 N_t eigenvalues by a KPM count of
+    1024 moments (the 64 moments of the features smear the density by about
+    a twentieth of the spectrum, so windows in gaps pass the coarse count)."""
+    for _ in range(40):
         kw = sample(rng, big)
         m = build_matrix(**kw)
         lo, hi = m.lam_lo, m.lam_hi
@@ -57,8 +62,31 @@ def instance(rng, big: bool, max_degree: int):
             # a valid problem: the window holds at least 2 N_t eigenvalues
             # (KPM count from the same moments the features come from)
             if deg <= max_degree and window_count_from_features(feat, m.D) >= 2 * NT:
+                if strict and window_count(m, wl, wh) < 2 * NT:
+                    continue
+                kw["tau"], kw["window"] = tau, [wl, wh]
                 return kw, m, (wl, wh), deg, r0, feat
     raise RuntimeError("no instance found")
+
+
+def window_count(m, wl: float, wh: float, nmom: int = 1024, nvec: int = 16, seed: int = 5) -> float:
+    """KPM estimate of the number of eigenvalues in [wl, wh]: Jackson-damped
+    Chebyshev moments of nvec random N(0, 1) vectors (stochastic trace),
+    integrated against the window's indicator."""
+    import torch
+    lo, hi = m.lam_lo, m.lam_hi
+    alpha, beta = 2.0 / (hi - lo), -(hi + lo) / (hi - lo)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    R = torch.randn((m.D, nvec), generator=g, dtype=torch.float64, device="cuda")
+    mu = kpm_moments(m, R, nmom, alpha, beta)
+    n1 = nmom + 1.0
+    k = np.arange(nmom)
+    q = np.pi / n1
+    jack = ((n1 - k) * np.cos(k * q) + np.sin(k * q) / np.tan(q)) / n1
+    ta, tb = np.arccos(np.clip(alpha * wl + beta, -1, 1)), np.arccos(np.clip(alpha * wh + beta, -1, 1))
+    c = np.where(k == 0, (ta - tb) / np.pi, 2.0 * (np.sin(k * ta) - np.sin(k * tb)) / (np.maximum(k, 1) * np.pi))
+    return float(m.D * np.dot(c, jack * mu) / mu[0])
 
 
 def window_count_from_features(feat, D: int) -> float:
@@ -187,10 +215,10 @@ def evaluate(params: str, n: int, seed: int):
     rng = np.random.default_rng(seed)
     rows = []
     for k in range(n):
-        kw, m, win, deg, r0, feat = instance(rng, True, 6000)
+        kw, m, win, deg, r0, feat = instance(rng, True, 6000, strict=True)
         rr = run(m, win, 0, None, 40)
         rp = run(m, win, 0, P, 40)
-        row = dict(model=kw["model"], L=kw["L"], D=m.D, rule=dict(ok=rr.status == FD_OK, degree=rr.stats["degree"],
+        row = dict(model=kw["model"], L=kw["L"], D=m.D, params=kw, rule=dict(ok=rr.status == FD_OK, degree=rr.stats["degree"],
                    spmmv=rr.stats["spmmv_count"], t=rr.stats["t_total"], resid=rr.stats["max_resid"] / rr.stats["norm_H"]),
                    picker=dict(ok=rp.status == FD_OK, degree=rp.stats["degree"], spmmv=rp.stats["spmmv_count"],
                                t=rp.stats["t_total"], resid=rp.stats["max_resid"] / rp.stats["norm_H"]))
