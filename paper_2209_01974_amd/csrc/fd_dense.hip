@@ -188,10 +188,29 @@ __global__ __launch_bounds__(512) void k_rotate(double *__restrict__ X, int64_t 
     extern __shared__ double sX[];
     const int64_t r0 = (int64_t)blockIdx.x * TM;
     const int m4 = (m + 3) & ~3;
-    for (int e = threadIdx.x; e < TM * m4; e += 512) {
-        const int r = e / m4, k = e - r * m4;
-        const int64_t rr = r0 + r;
-        sX[r * ls + k] = (rr < D && k < m) ? X[rr * ldx + k] : 0.0;
+    // stage the row tile in LDS, 16 loads per thread in flight at a time
+    const int tot = TM * m4;
+    for (int base = 0; base < tot; base += 16 * 512) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int e = base + u * 512 + (int)threadIdx.x;
+            double x = 0.0;
+            if (e < tot) {
+                const int r = e / m4, k = e - r * m4;
+                const int64_t rr = r0 + r;
+                if (rr < D && k < m) x = X[rr * ldx + k];
+            }
+            v[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int e = base + u * 512 + (int)threadIdx.x;
+            if (e < tot) {
+                const int r = e / m4;
+                sX[r * ls + (e - r * m4)] = v[u];
+            }
+        }
     }
     __syncthreads();
     constexpr int RB = TM / 16;
@@ -211,12 +230,15 @@ __global__ __launch_bounds__(512) void k_rotate(double *__restrict__ X, int64_t 
         cc[q] = (cb0 + q) * 16 + li;
         cv[q] = (q < g) && (cc[q] < n);
     }
-    for (int k0 = 0; k0 < m4; k0 += 4) {
-        const int kk = k0 + lk;
-        const bool kv = kk < m;
-        double b[4];
+    // Q streams from L2 for every row tile: the next k-step's entries are
+    // loaded while the matrix cores work on the current ones
+    double b[4], bn[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) b[q] = (kv && cv[q]) ? Q[(int64_t)kk * ldq + cc[q]] : 0.0;
+    for (int q = 0; q < 4; q++) b[q] = (lk < m && cv[q]) ? Q[(int64_t)lk * ldq + cc[q]] : 0.0;
+    for (int k0 = 0; k0 < m4; k0 += 4) {
+        const int kk = k0 + lk, kn = kk + 4;
+#pragma unroll
+        for (int q = 0; q < 4; q++) bn[q] = (kn < m && cv[q]) ? Q[(int64_t)kn * ldq + cc[q]] : 0.0;
 #pragma unroll
         for (int rb = 0; rb < RB; rb++) {
             const double a = sX[(rb * 16 + li) * ls + kk];
@@ -224,6 +246,8 @@ __global__ __launch_bounds__(512) void k_rotate(double *__restrict__ X, int64_t 
             for (int q = 0; q < 4; q++)
                 if (q < g) acc[rb][q] = mfma16x16x4(a, b[q], acc[rb][q]);
         }
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] = bn[q];
     }
 #pragma unroll
     for (int rb = 0; rb < RB; rb++)

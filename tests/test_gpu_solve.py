@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 from fd_inputs import start_block
+from lattice_walk import anderson_tiled, tile_walk
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -122,6 +123,24 @@ def test_anderson_nearest_tau_delta_filter():
     assert r.status == fd.FD_OK, r.stats
     want = np.sort(ev[np.argsort(np.abs(ev), kind="stable")[:8]])
     check_pairs(A, r, want, r.stats["norm_H"])
+
+
+def test_anderson_tiled_numbering_same_pairs():
+    """The tiled site numbering is P A P^T: the same eigenvalues nearest 0
+    as the dense natural spectrum, and eigenvectors that are the tiled
+    matrix's own (checked with a fresh SpMMV of the permuted oracle matrix)
+    and, mapped back through the walk, the natural matrix's."""
+    A = O.anderson(12, 1.0, 16.5, 1)
+    ev = dense_spectrum("and12", A)
+    B = anderson_tiled(12, 1.0, 16.5, 1, 5, 4)
+    m = fd.build_matrix("anderson", L=12, t=1.0, W=16.5, seed=1, tiles=(5, 4))
+    r = fd.solve(m, 0.0, 0.0, 8, 64, 16, 400, max_iter=100, tol=1e-9, V0=start_block(A.D, 64, 2))
+    assert r.status == fd.FD_OK, r.stats
+    want = np.sort(ev[np.argsort(np.abs(ev), kind="stable")[:8]])
+    check_pairs(B, r, want, r.stats["norm_H"])
+    X = np.empty_like(r.evecs.cpu().numpy())
+    X[tile_walk(12, 5, 4)] = r.evecs.cpu().numpy()  # row r of the walk is site walk[r]
+    assert np.linalg.norm(O.spmmv(A, X) - X * r.evals, axis=0).max() <= 1e-9 * r.stats["norm_H"]
 
 
 def test_solve_errors_and_not_converged():
