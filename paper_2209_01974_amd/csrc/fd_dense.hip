@@ -275,16 +275,16 @@ fd_status rotate(int64_t D, int m, int n, double *X, int64_t ldx, const double *
     const int ncb = (n + 15) / 16;
     const int g = std::min(4, (ncb + 7) / 8);
     if (m <= 256) {
-        size_t sh = (size_t)64 * ls * sizeof(double);
-        FD_HIP(hipFuncSetAttribute((const void *)k_rotate<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)sh));
-        hipLaunchKernelGGL(k_rotate<64>, dim3((unsigned)((D + 63) / 64)), dim3(512), sh, s, X, ldx, D, m, n,
-                           Q, ldq, ls, g);
-    } else {
         size_t sh = (size_t)32 * ls * sizeof(double);
         FD_HIP(hipFuncSetAttribute((const void *)k_rotate<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)sh));
         hipLaunchKernelGGL(k_rotate<32>, dim3((unsigned)((D + 31) / 32)), dim3(512), sh, s, X, ldx, D, m, n,
+                           Q, ldq, ls, g);
+    } else {
+        size_t sh = (size_t)16 * ls * sizeof(double);
+        FD_HIP(hipFuncSetAttribute((const void *)k_rotate<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)sh));
+        hipLaunchKernelGGL(k_rotate<16>, dim3((unsigned)((D + 15) / 16)), dim3(512), sh, s, X, ldx, D, m, n,
                            Q, ldq, ls, g);
     }
     FD_HIP(hipGetLastError());
