@@ -123,7 +123,7 @@ __global__ __launch_bounds__(64) void k_gram(const double *__restrict__ X, int64
 }
 
 __global__ void k_gram_reduce(const double *__restrict__ P, int S, int ntiles, int m, int n,
-                              bool sym, int nt_n, double *__restrict__ G, int64_t ldg) {
+                              bool sym, int nt_n, int te, double *__restrict__ G, int64_t ldg) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)m * n) return;
     int i = (int)(e / n), j = (int)(e % n);
@@ -132,7 +132,7 @@ __global__ void k_gram_reduce(const double *__restrict__ P, int S, int ntiles, i
         i = j;
         j = t;
     }
-    const int ti = i / GT, tj = j / GT;
+    const int ti = i / te, tj = j / te;
     int tile;
     if (sym) {
         // upper-triangle tiles listed row by row: (0,0..T-1), (1,1..T-1), ...
@@ -140,10 +140,92 @@ __global__ void k_gram_reduce(const double *__restrict__ P, int S, int ntiles, i
     } else {
         tile = ti * nt_n + tj;
     }
-    const int64_t off = (int64_t)tile * (GT * GT) + (i % GT) * GT + (j % GT);
+    const int64_t tsz = (int64_t)te * te;
+    const int64_t off = (int64_t)tile * tsz + (i % te) * te + (j % te);
     double s = 0.0;
-    for (int k = 0; k < S; k++) s += P[(int64_t)k * ntiles * (GT * GT) + off];
+    for (int k = 0; k < S; k++) s += P[(int64_t)k * ntiles * tsz + off];
     G[(e / n) * ldg + (e % n)] = s;
+}
+
+// Gram products with both sides at least 128 wide: a block of 4 waves owns
+// a 128 x 128 tile of the result (a 64 x 64 quarter per wave) over a slice
+// of rows.  The rows of the tile's 128 + 128 columns go through LDS in
+// chunks of 16, so that each value loaded from memory feeds two waves'
+// matrix cores; the next chunk is loaded into registers while the current
+// one is multiplied.
+constexpr int GB = 128;      // block tile edge
+constexpr int GK = 16;        // rows per chunk
+constexpr int GLD = GB + 16; // LDS row stride (doubles): alternate rows on the two bank halves
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_big(const double *__restrict__ X, int64_t ldx,
+                                                  const double *__restrict__ Y, int64_t ldy, int64_t D,
+                                                  int m, int n, int64_t rps, TileList tl,
+                                                  double *__restrict__ P) {
+    __shared__ double sA[GK * GLD];
+    __shared__ double sB[GK * GLD];
+    const int tile = blockIdx.x;
+    const int64_t slice = blockIdx.y;
+    const int ti = tl.ti[tile], tj = tl.tj[tile];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int64_t r0 = slice * rps;
+    const int64_t r1 = min(D, r0 + rps);
+    // staging map: element u of a thread is row (u * 256 + t) / 128, column
+    // (u * 256 + t) % 128 of the chunk: 8 per operand, coalesced along rows
+    const int scol = t & (GB - 1), srow = t >> 7;  // srow in {0, 1}
+    const int ca = ti * GB + scol, cb = tj * GB + scol;
+    const bool va = ca < m, vb = cb < n;
+    double ra[GK / 2], rb[GK / 2];
+    auto fetch = [&](int64_t c0) {
+#pragma unroll
+        for (int u = 0; u < GK / 2; u++) {
+            const int64_t r = c0 + 2 * u + srow;
+            const bool rv = r < r1;
+            ra[u] = (rv && va) ? X[r * ldx + ca] : 0.0;
+            rb[u] = (rv && vb) ? Y[r * ldy + cb] : 0.0;
+        }
+    };
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = (dbl4)0.0;
+    fetch(r0);
+    for (int64_t c0 = r0; c0 < r1; c0 += GK) {
+        __syncthreads();  // the previous chunk is no longer read
+#pragma unroll
+        for (int u = 0; u < GK / 2; u++) {
+            sA[(2 * u + srow) * GLD + scol] = ra[u];
+            sB[(2 * u + srow) * GLD + scol] = rb[u];
+        }
+        __syncthreads();
+        if (c0 + GK < r1) fetch(c0 + GK);
+#pragma unroll
+        for (int ks = 0; ks < GK / 4; ks++) {
+            const int k = ks * 4 + lk;
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                a[q] = sA[k * GLD + wi * 64 + q * 16 + li];
+                b[q] = sB[k * GLD + wj * 64 + q * 16 + li];
+            }
+#pragma unroll
+            for (int qa = 0; qa < 4; qa++)
+#pragma unroll
+                for (int qb = 0; qb < 4; qb++) acc[qa][qb] = mfma16x16x4(a[qa], b[qb], acc[qa][qb]);
+        }
+    }
+    double *out = P + ((int64_t)slice * tl.n + tile) * (GB * GB);
+#pragma unroll
+    for (int qa = 0; qa < 4; qa++)
+#pragma unroll
+        for (int qb = 0; qb < 4; qb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int il = wi * 64 + qa * 16 + (lane >> 4) + 4 * r;
+                const int jl = wj * 64 + qb * 16 + (lane & 15);
+                out[il * GB + jl] = acc[qa][qb][r];
+            }
 }
 
 }  // namespace
@@ -153,7 +235,9 @@ fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const doub
     if (m < 1 || n < 1 || m > 512 || n > 512 || D < 1)
         return fail(FD_ERR_INVALID, "gram: need 1 <= m, n <= 512 and D >= 1");
     if (sym && m != n) return fail(FD_ERR_INVALID, "gram: symmetric product needs m == n");
-    const int ntm = (m + GT - 1) / GT, ntn = (n + GT - 1) / GT;
+    const bool big = m >= GB && n >= GB;
+    const int te = big ? GB : GT;
+    const int ntm = (m + te - 1) / te, ntn = (n + te - 1) / te;
     TileList tl;
     tl.n = 0;
     for (int a = 0; a < ntm; a++)
@@ -162,18 +246,23 @@ fd_status gram(int64_t D, int m, int n, const double *X, int64_t ldx, const doub
             tl.tj[tl.n] = (unsigned char)b;
             tl.n++;
         }
-    int64_t target = std::max<int64_t>(1, 2048 / tl.n);
+    // slices of rows: about 2048 waves in all (512 blocks of 4 for big tiles)
+    int64_t target = std::max<int64_t>(1, (big ? 512 : 2048) / tl.n);
     int64_t rps = std::max<int64_t>(256, (D + target - 1) / target);
-    rps = (rps + 3) / 4 * 4;
+    rps = (rps + GK - 1) / GK * GK;
     int64_t S = (D + rps - 1) / rps;
-    double *P = (double *)workspace((size_t)S * tl.n * GT * GT * sizeof(double), 0);
+    double *P = (double *)workspace((size_t)S * tl.n * te * te * sizeof(double), 0);
     if (!P) return fail(FD_ERR_OOM, "gram: workspace");
-    hipLaunchKernelGGL(k_gram, dim3(tl.n, (unsigned)S), dim3(64), 0, s, X, ldx, Y, ldy, D, m, n, rps,
-                       tl, P);
+    if (big)
+        hipLaunchKernelGGL(k_gram_big, dim3(tl.n, (unsigned)S), dim3(256), 0, s, X, ldx, Y, ldy, D, m, n, rps,
+                           tl, P);
+    else
+        hipLaunchKernelGGL(k_gram, dim3(tl.n, (unsigned)S), dim3(64), 0, s, X, ldx, Y, ldy, D, m, n, rps,
+                           tl, P);
     FD_HIP(hipGetLastError());
     const int64_t tot = (int64_t)m * n;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, P, (int)S,
-                       tl.n, m, n, sym, ntn, G, ldg);
+                       tl.n, m, n, sym, ntn, te, G, ldg);
     FD_HIP(hipGetLastError());
     return FD_OK;
 }

@@ -162,7 +162,8 @@ def test_filter_fp32_error():
 
 # -------------------------------------------------------------- dense FP64 --
 @pytest.mark.parametrize("D,m_,n", [(10007, 64, 64), (5001, 17, 33), (4096, 256, 256), (333, 1, 5),
-                                    (70000, 128, 100), (2000, 512, 512)])
+                                    (70000, 128, 100), (2000, 512, 512), (70001, 300, 130), (123457, 512, 512),
+                                    (9, 128, 128)])
 def test_gram_parity_and_reproducible(D, m_, n):
     X = start_block(D, m_, 1)
     Y = start_block(D, n, 2)
