@@ -459,6 +459,32 @@ def main():
            "roofline": roofline,
            "hbm_frac_of_step": round(value / HBM_PEAK_GBS, 4)}
 
+    # ------------------------------------------- site numbering check ----
+    # the same degree-20 filter on one bundle with the tiled and the natural
+    # numbering of the lattice (each with its autotuned launch shape)
+    if tiles[0] and not args.no_sweep:
+        mn = fd.build_matrix("anderson", L=L, t=1.0, W=16.5, seed=1)
+        cmp_ = {}
+        for name, mm in (("tiled", m), ("natural", mn)):
+            sh = fd.autotune(mm, "f64", nb, stream=stream)
+            X = torch.empty((D, nb), dtype=torch.float64, device=dev).normal_(generator=g)
+            Z1, Z2 = torch.empty_like(X), torch.empty_like(X)
+            mu = fd.cheb_coeffs(1, beta, 0.0, 20)
+            fd.cheb_filter(mm, X, mu, alpha, beta, Z1, Z2, nb, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fd.cheb_filter(mm, X, mu, alpha, beta, Z1, Z2, nb, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tf = e0.elapsed_time(e1) * 1e-3
+            cmp_[name] = {"step_us": round(tf / 20 * 1e6, 1), "GBs": round(filter_bytes(nnz, D, nb, 8, 20) / tf / 1e9, 1),
+                          "launch_shape": list(sh)}
+            del X, Z1, Z2
+        del mn
+        out["site_order_compare"] = cmp_
+        log("degree-20 filter, nb=%d: tiled %.0f us, natural %.0f us per step"
+            % (nb, cmp_["tiled"]["step_us"], cmp_["natural"]["step_us"]))
+
     # ---------------------------------------------------------- sweep ----
     if not args.no_sweep:
         sweep = []
