@@ -402,11 +402,6 @@ struct PairList {
 
 __device__ __forceinline__ int grp_index(int l, int I, int J) { return l < JB ? I * JB + l : J * JB + (l - JB); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 __global__ __launch_bounds__(256) void k_bj_solve(int np, const double *__restrict__ A, PairList pl,
                                                   double *__restrict__ Rbuf, double thr2) {
     __shared__ double red[2][256];
