@@ -317,8 +317,9 @@ fd_status fd_lehmann(int64_t D, int32_t n, const double *V_dev, const double *W_
 fd_status fd_orthog(int64_t D, int32_t ns, double *V_dev, int64_t ldv, int32_t method,
                     uint64_t seed, int32_t *rank, void *stream);
 
-/* Rayleigh-Ritz step, Sec. 2 ("a single additional SpMV provides the Ritz
- * values"): W = A V (FP64 SpMMV), H = V^t W, H = Y diag(theta) Y^t,
+/* Rayleigh-Ritz step (Sec. 2: after each orthogonalization one more SpMMV
+ * of the search block gives the Ritz values): W = A V (FP64 SpMMV),
+ * H = V^t W, H = Y diag(theta) Y^t,
  * V <- V Y, W <- W Y, rho_j = ||W_j - theta_j V_j||_2.  V must have
  * orthonormal columns.  V, W: device D x ns blocks with the same ld; ns a
  * multiple of nb (nb in {1,...,64}, the bundle width used for A V).
