@@ -72,6 +72,9 @@ fd_status upload_tables(fd_matrix m) {
     d.nu = T.nu;
     d.nd = T.nd;
     d.U = T.U;
+    d.mf_maxu = d.mf_maxd = 0;
+    for (size_t i = 0; i + 1 < T.off_u.size(); i++) d.mf_maxu = std::max(d.mf_maxu, T.off_u[i + 1] - T.off_u[i]);
+    for (size_t i = 0; i + 1 < T.off_d.size(); i++) d.mf_maxd = std::max(d.mf_maxd, T.off_d[i + 1] - T.off_d[i]);
     std::vector<float> u32(T.val_u.begin(), T.val_u.end()), d32(T.val_d.begin(), T.val_d.end());
     FD_TRY(to_device(&d.mu, T.mu));
     FD_TRY(to_device(&d.md, T.md));

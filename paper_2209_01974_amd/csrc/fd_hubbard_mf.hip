@@ -17,7 +17,9 @@
 // traffic over a stored-matrix step is one more read and write of y, against
 // the matrix and the strided up-hop gathers it saves.  Lane mapping as in
 // the stored-matrix kernel: a row of nb values is split over G lanes of VEC
-// values each; blockIdx.y selects the bundle.
+// values each; blockIdx.y selects the bundle.  With 4 or more lanes per row
+// the row's first 4 or 8 lanes load that many hops (target, element) at once
+// and pass them on by cross-lane permute.
 #include "fd_internal.h"
 
 namespace fd {
@@ -37,6 +39,7 @@ struct MfArgs {
     int64_t nu, nd, D, nlog;  // nlog: logical rows of pass 2 (ntiles nu tile_b)
     int64_t tile_b;
     int64_t nblk, q8;         // blocks per bundle, floor(nblk / 8)
+    int32_t maxu, maxd;       // most hops of an up / down state
     const uint64_t *__restrict__ mu;
     const uint64_t *__restrict__ md;
     const int32_t *__restrict__ off_u;
@@ -55,6 +58,72 @@ struct MfArgs {
 
 template <typename V>
 __device__ __forceinline__ V ld(const void *p) { return *reinterpret_cast<const V *>(p); }
+// acc + e x with one rounding per element in every form of the hop loop
+template <typename V, typename T>
+__device__ __forceinline__ V fmah(T e, V x, V acc) { return __builtin_elementwise_fma((V)e, x, acc); }
+
+// Hops h of one row, h = 0 .. len-1 at tables idx[j0 + h], val[j0 + h]: the
+// gathered row of hop h is xq + (base + idx * stride) * ldx.  Even hops go
+// to acc0, odd ones to acc1.  SH 1 / 2: lanes 0..LW-1 of the row (LW = 4 /
+// 8, q < LW) load one hop each per round and the row's lanes take them by
+// permute; the rounds run to maxlen, the most hops of any state, so that
+// every lane of a live row takes part in every permute.  SH 0: every lane
+// loads every hop (broadcast).
+template <typename T, typename V, int G, int SH>
+__device__ __forceinline__ void hop_sum(const int32_t *__restrict__ idx, const T *__restrict__ val, int32_t j0,
+                                        int32_t len, int32_t maxlen, const T *xq, int64_t base, int64_t stride,
+                                        int64_t ldx, int q, V &acc0, V &acc1) {
+    if constexpr (SH != 0) {
+        constexpr int LW = SH == 2 ? 8 : 4;
+        static_assert(G >= LW, "a load round needs LW lanes per row");
+        const int rbase = (int)(threadIdx.x & 63) - q;
+        for (int r0 = 0; r0 < maxlen; r0 += LW) {
+            int32_t cm = 0;
+            T em = (T)0;
+            if (q < LW && r0 + q < len) {
+                cm = idx[j0 + r0 + q];
+                em = val[j0 + r0 + q];
+            }
+            int32_t cc[LW];
+            T ee[LW];
+#pragma unroll
+            for (int u = 0; u < LW; u++) {
+                cc[u] = __shfl(cm, rbase + u, 64);
+                ee[u] = __shfl(em, rbase + u, 64);
+            }
+            V xs[LW];
+#pragma unroll
+            for (int u = 0; u < LW; u++) xs[u] = (r0 + u < len) ? ld<V>(xq + (base + (int64_t)cc[u] * stride) * ldx) : (V)0;
+#pragma unroll
+            for (int u = 0; u < LW; u++)
+                if (r0 + u < len) {
+                    if (u & 1) acc1 = fmah(ee[u], xs[u], acc1);
+                    else acc0 = fmah(ee[u], xs[u], acc0);
+                }
+        }
+    } else {
+        int32_t h = 0;
+        // four hops per round, all loads of a round independent
+        for (; h + 4 <= len; h += 4) {
+            const int32_t c0 = idx[j0 + h], c1 = idx[j0 + h + 1], c2 = idx[j0 + h + 2], c3 = idx[j0 + h + 3];
+            const T e0 = val[j0 + h], e1 = val[j0 + h + 1], e2 = val[j0 + h + 2], e3 = val[j0 + h + 3];
+            const V x0 = ld<V>(xq + (base + (int64_t)c0 * stride) * ldx);
+            const V x1 = ld<V>(xq + (base + (int64_t)c1 * stride) * ldx);
+            const V x2 = ld<V>(xq + (base + (int64_t)c2 * stride) * ldx);
+            const V x3 = ld<V>(xq + (base + (int64_t)c3 * stride) * ldx);
+            acc0 = fmah(e0, x0, acc0);
+            acc1 = fmah(e1, x1, acc1);
+            acc0 = fmah(e2, x2, acc0);
+            acc1 = fmah(e3, x3, acc1);
+        }
+        // at most three hops left (h is a multiple of 4): even, odd, even
+        if (h < len) acc0 = fmah(val[j0 + h], ld<V>(xq + (base + (int64_t)idx[j0 + h] * stride) * ldx), acc0);
+        if (h + 1 < len)
+            acc1 = fmah(val[j0 + h + 1], ld<V>(xq + (base + (int64_t)idx[j0 + h + 1] * stride) * ldx), acc1);
+        if (h + 2 < len)
+            acc0 = fmah(val[j0 + h + 2], ld<V>(xq + (base + (int64_t)idx[j0 + h + 2] * stride) * ldx), acc0);
+    }
+}
 template <typename V, bool NT>
 __device__ __forceinline__ V lds(const void *p) {
     if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
@@ -82,7 +151,7 @@ __device__ __forceinline__ int64_t logical_block(int64_t bid, int64_t q8) {
 //   MODE 0: y = s           MODE 1: y = a s + b x
 //   MODE 2: y = a s + b x - v        MODE 3, 4, 5: y = a s + b x - z
 // with s = (I x H_dn + U D) x.  y may alias z (same element read first).
-template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
+template <typename T, int VEC, int G, int MODE, bool XCD, bool NT, int SH>
 __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
     typedef typename VT<T, VEC>::type V;
     constexpr int RPB = 256 / G;
@@ -99,27 +168,8 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
     if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + s * p.ldz + q * VEC);
     const V xi = ld<V>(xq + s * p.ldx);
     V acc0 = (p.U * (T)__popcll(p.mu[a] & p.md[b])) * xi, acc1 = (V)0;
-    const int64_t row0 = a * p.nd;
-    const int32_t j1 = p.off_d[b + 1];
-    int32_t j = p.off_d[b];
-    // four hops per round, all loads of a round independent
-    for (; j + 4 <= j1; j += 4) {
-        const int32_t c0 = p.idx_d[j], c1 = p.idx_d[j + 1], c2 = p.idx_d[j + 2], c3 = p.idx_d[j + 3];
-        const T e0 = p.val_d[j], e1 = p.val_d[j + 1], e2 = p.val_d[j + 2], e3 = p.val_d[j + 3];
-        const V x0 = ld<V>(xq + (row0 + c0) * p.ldx), x1 = ld<V>(xq + (row0 + c1) * p.ldx);
-        const V x2 = ld<V>(xq + (row0 + c2) * p.ldx), x3 = ld<V>(xq + (row0 + c3) * p.ldx);
-        acc0 += e0 * x0;
-        acc1 += e1 * x1;
-        acc0 += e2 * x2;
-        acc1 += e3 * x3;
-    }
-    for (; j + 2 <= j1; j += 2) {
-        const int32_t c0 = p.idx_d[j], c1 = p.idx_d[j + 1];
-        const T e0 = p.val_d[j], e1 = p.val_d[j + 1];
-        acc0 += e0 * ld<V>(xq + (row0 + c0) * p.ldx);
-        acc1 += e1 * ld<V>(xq + (row0 + c1) * p.ldx);
-    }
-    if (j < j1) acc0 += p.val_d[j] * ld<V>(xq + (row0 + p.idx_d[j]) * p.ldx);
+    const int32_t j0 = p.off_d[b];
+    hop_sum<T, V, G, SH>(p.idx_d, p.val_d, j0, p.off_d[b + 1] - j0, p.maxd, xq, a * p.nd, 1, p.ldx, q, acc0, acc1);
     V r = acc0 + acc1;
     if constexpr (MODE >= 1) r = p.a * r + p.b * xi;
     if constexpr (MODE >= 2) r -= zi;
@@ -132,7 +182,7 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
 //   MODE 2: y = t, v = cv v + cx x + ct t
 //   MODE 3: y = t, v = v + ct t
 //   MODE 5: y = t, v = v + cx x + ct t
-template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
+template <typename T, int VEC, int G, int MODE, bool XCD, bool NT, int SH>
 __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     typedef typename VT<T, VEC>::type V;
     constexpr int RPB = 256 / G;
@@ -164,25 +214,8 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     if constexpr (MODE == 2 || MODE == 5) xi = ld<V>(xq + s * p.ldx);
     const V yi = lds<V, NT>(yr);
     V acc0 = (V)0, acc1 = (V)0;
-    const int32_t j1 = p.off_u[a + 1];
-    int32_t j = p.off_u[a];
-    for (; j + 4 <= j1; j += 4) {
-        const int32_t c0 = p.idx_u[j], c1 = p.idx_u[j + 1], c2 = p.idx_u[j + 2], c3 = p.idx_u[j + 3];
-        const T e0 = p.val_u[j], e1 = p.val_u[j + 1], e2 = p.val_u[j + 2], e3 = p.val_u[j + 3];
-        const V x0 = ld<V>(xq + ((int64_t)c0 * p.nd + b) * p.ldx), x1 = ld<V>(xq + ((int64_t)c1 * p.nd + b) * p.ldx);
-        const V x2 = ld<V>(xq + ((int64_t)c2 * p.nd + b) * p.ldx), x3 = ld<V>(xq + ((int64_t)c3 * p.nd + b) * p.ldx);
-        acc0 += e0 * x0;
-        acc1 += e1 * x1;
-        acc0 += e2 * x2;
-        acc1 += e3 * x3;
-    }
-    for (; j + 2 <= j1; j += 2) {
-        const int32_t c0 = p.idx_u[j], c1 = p.idx_u[j + 1];
-        const T e0 = p.val_u[j], e1 = p.val_u[j + 1];
-        acc0 += e0 * ld<V>(xq + ((int64_t)c0 * p.nd + b) * p.ldx);
-        acc1 += e1 * ld<V>(xq + ((int64_t)c1 * p.nd + b) * p.ldx);
-    }
-    if (j < j1) acc0 += p.val_u[j] * ld<V>(xq + ((int64_t)p.idx_u[j] * p.nd + b) * p.ldx);
+    const int32_t j0 = p.off_u[a];
+    hop_sum<T, V, G, SH>(p.idx_u, p.val_u, j0, p.off_u[a + 1] - j0, p.maxu, xq, b, p.nd, p.ldx, q, acc0, acc1);
     V t;
     if constexpr (MODE == 0) t = yi + (acc0 + acc1);
     else t = yi + p.a * (acc0 + acc1);
@@ -192,31 +225,44 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     if constexpr (MODE == 5) sts<V, NT>(vr, vi + p.cx * xi + p.ct * t);
 }
 
-template <typename T, int VEC, int G, int MODE, bool XCD, bool NT>
+template <typename T, int VEC, int G, int MODE, bool XCD, bool NT, int SH>
 fd_status launch_mode(const MfArgs<T> &p, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
     MfArgs<T> p1 = p, p2 = p;
     p1.nblk = g1;
     p1.q8 = g1 / 8;
     p2.nblk = g2;
     p2.q8 = g2 / 8;
-    hipLaunchKernelGGL((k_mf_down<T, VEC, G, MODE, XCD, NT>), dim3((unsigned)g1, nbund), dim3(256), 0, s, p1);
+    hipLaunchKernelGGL((k_mf_down<T, VEC, G, MODE, XCD, NT, SH>), dim3((unsigned)g1, nbund), dim3(256), 0, s, p1);
     FD_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_mf_up<T, VEC, G, MODE, XCD, NT>), dim3((unsigned)g2, nbund), dim3(256), 0, s, p2);
+    hipLaunchKernelGGL((k_mf_up<T, VEC, G, MODE, XCD, NT, SH>), dim3((unsigned)g2, nbund), dim3(256), 0, s, p2);
     FD_HIP(hipGetLastError());
     return FD_OK;
 }
 
-template <typename T, int VEC, int G, bool XCD, bool NT>
-fd_status launch_x(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+template <typename T, int VEC, int G, bool XCD, bool NT, int SH>
+fd_status launch_m(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
     switch (mode) {
-        case 0: return launch_mode<T, VEC, G, 0, XCD, NT>(p, nbund, g1, g2, s);
-        case 1: return launch_mode<T, VEC, G, 1, XCD, NT>(p, nbund, g1, g2, s);
-        case 2: return launch_mode<T, VEC, G, 2, XCD, NT>(p, nbund, g1, g2, s);
-        case 3: return launch_mode<T, VEC, G, 3, XCD, NT>(p, nbund, g1, g2, s);
-        case 4: return launch_mode<T, VEC, G, 4, XCD, NT>(p, nbund, g1, g2, s);
-        case 5: return launch_mode<T, VEC, G, 5, XCD, NT>(p, nbund, g1, g2, s);
+        case 0: return launch_mode<T, VEC, G, 0, XCD, NT, SH>(p, nbund, g1, g2, s);
+        case 1: return launch_mode<T, VEC, G, 1, XCD, NT, SH>(p, nbund, g1, g2, s);
+        case 2: return launch_mode<T, VEC, G, 2, XCD, NT, SH>(p, nbund, g1, g2, s);
+        case 3: return launch_mode<T, VEC, G, 3, XCD, NT, SH>(p, nbund, g1, g2, s);
+        case 4: return launch_mode<T, VEC, G, 4, XCD, NT, SH>(p, nbund, g1, g2, s);
+        case 5: return launch_mode<T, VEC, G, 5, XCD, NT, SH>(p, nbund, g1, g2, s);
     }
     return fail(FD_ERR_INVALID, "matrix-free SpMMV: bad mode");
+}
+
+// hop loop: permute rounds of 8 need 8 lanes per row, rounds of 4 need 4;
+// with fewer lanes the next smaller form runs
+template <typename T, int VEC, int G, bool XCD, bool NT>
+fd_status launch_x(const MfArgs<T> &p, int mode, int sh, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+    if constexpr (G >= 8) {
+        if (sh >= 2) return launch_m<T, VEC, G, XCD, NT, 2>(p, mode, nbund, g1, g2, s);
+    }
+    if constexpr (G >= 4) {
+        if (sh >= 1) return launch_m<T, VEC, G, XCD, NT, 1>(p, mode, nbund, g1, g2, s);
+    }
+    return launch_m<T, VEC, G, XCD, NT, 0>(p, mode, nbund, g1, g2, s);
 }
 
 template <typename T, int VEC, int G>
@@ -231,6 +277,8 @@ fd_status launch_mf_t(const DevMatrix &M, const T *val_u, const T *val_d, const 
     const int64_t ntiles = (M.nd + p.tile_b - 1) / p.tile_b;
     p.nlog = ntiles * M.nu * p.tile_b;
     p.nblk = p.q8 = 0;
+    p.maxu = M.mf_maxu;
+    p.maxd = M.mf_maxd;
     p.mu = M.mu;
     p.md = M.md;
     p.off_u = M.off_u;
@@ -250,12 +298,13 @@ fd_status launch_mf_t(const DevMatrix &M, const T *val_u, const T *val_d, const 
     if (g1 > 0x7fffffff || g2 > 0x7fffffff || c.nbundles < 1 || c.nbundles > 65535)
         return fail(FD_ERR_UNSUPPORTED, "matrix-free SpMMV: grid too large");
     const bool xcd = tn.xcd == 1, nt = tn.nontemporal != 0;
+    const int sh = tn.shfl;
     if (xcd) {
-        if (nt) return launch_x<T, VEC, G, true, true>(p, c.mode, c.nbundles, g1, g2, s);
-        return launch_x<T, VEC, G, true, false>(p, c.mode, c.nbundles, g1, g2, s);
+        if (nt) return launch_x<T, VEC, G, true, true>(p, c.mode, sh, c.nbundles, g1, g2, s);
+        return launch_x<T, VEC, G, true, false>(p, c.mode, sh, c.nbundles, g1, g2, s);
     }
-    if (nt) return launch_x<T, VEC, G, false, true>(p, c.mode, c.nbundles, g1, g2, s);
-    return launch_x<T, VEC, G, false, false>(p, c.mode, c.nbundles, g1, g2, s);
+    if (nt) return launch_x<T, VEC, G, false, true>(p, c.mode, sh, c.nbundles, g1, g2, s);
+    return launch_x<T, VEC, G, false, false>(p, c.mode, sh, c.nbundles, g1, g2, s);
 }
 
 }  // namespace

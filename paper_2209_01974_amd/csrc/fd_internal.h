@@ -115,6 +115,7 @@ struct DevMatrix {
     double *val_u64 = nullptr, *val_d64 = nullptr;
     float *val_u32 = nullptr, *val_d32 = nullptr;
     int32_t mf_tile = 16;  // default down-state tile of the up pass
+    int32_t mf_maxu = 0, mf_maxd = 0;  // most hops of an up / down state
 };
 
 }  // namespace fd

@@ -356,10 +356,14 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
         {0, 2, 1, 2048, 1, 0, 0, 0}, {0, 2, 1, 8192, 1, 0, 0, 0},
     };
     // matrix-free Hubbard: down-state tile of the up pass, XCD remap on/off
+    // matrix-free Hubbard: xcd (remap), nontemporal, wide, tile (down states
+    // per tile of the up pass), shfl (hop loop)
     const SpmmvTune mf_cands[] = {
-        {0, 0, 1, 0, 1, 0, 16}, {0, 0, 1, 0, 1, 0, 64}, {0, 0, 1, 0, 1, 0, 256}, {0, 1, 1, 0, 1, 0, 4},
-        {0, 1, 1, 0, 1, 0, 16}, {0, 1, 1, 0, 1, 0, 64}, {0, 1, 1, 0, 0, 0, 16}, {0, 0, 1, 0, 0, 0, 64},
-        {0, 1, 1, 0, 1, 1, 16},
+        {0, 0, 1, 0, 1, 0, 16, 1}, {0, 0, 1, 0, 1, 0, 64, 1},  {0, 0, 1, 0, 1, 0, 256, 1},
+        {0, 1, 1, 0, 1, 0, 4, 1},  {0, 1, 1, 0, 1, 0, 16, 1},  {0, 1, 1, 0, 1, 0, 64, 1},
+        {0, 1, 1, 0, 0, 0, 16, 1}, {0, 0, 1, 0, 0, 0, 64, 1},  {0, 1, 1, 0, 1, 1, 16, 1},
+        {0, 0, 1, 0, 1, 0, 64, 2}, {0, 1, 1, 0, 1, 0, 16, 2},  {0, 0, 1, 0, 1, 0, 64, 0},
+        {0, 1, 1, 0, 1, 0, 16, 0},
     };
     const SpmmvTune *cb = M.matfree ? mf_cands : cands;
     const SpmmvTune *ce = M.matfree ? mf_cands + sizeof(mf_cands) / sizeof(mf_cands[0])
