@@ -80,7 +80,9 @@ typedef enum {
  *   of the naturally numbered one (the same entries, each site keeps its
  *   on-site energy), so its spectrum is the same; a site's lattice
  *   neighbours lie within tile_x * tile_y rows except across tile edges.
- *   Not with FD_FMT_PENCIL (which walks the natural numbering).
+ *   Not with FD_FMT_PENCIL (which walks the natural numbering).  L^3 must
+ *   stay below 2^31 for the tiled numbering and the pencil walk
+ *   (FD_ERR_UNSUPPORTED otherwise).
  * FD_DIAGONAL: n entries from `diag` (host).
  * FD_USER_CSR: D rows, rowptr[D+1] (int64), col (uint32, ascending per row),
  *   val (double); host arrays, copied.  D < 2^32.                          */

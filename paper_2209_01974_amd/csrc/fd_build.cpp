@@ -388,6 +388,7 @@ fd_status build_pencil(const HostCSR &A, int L, int tx, int ty, HostSELL &S) {
     const int64_t D = A.D;
     if (L < 3 || (int64_t)L * L * L != D || tx < 1 || ty < 1)
         return fail(FD_ERR_INVALID, "pencil order: need the L^3 lattice and tiles of at least one site");
+    if (D >= (int64_t(1) << 31)) return fail(FD_ERR_UNSUPPORTED, "pencil order: the walk is indexed in int32");
     S.C = 1;
     S.sigma = 1;
     try {
@@ -407,6 +408,7 @@ fd_status relabel_tiles(int L, int tx, int ty, HostCSR &A) {
     const int64_t D = A.D;
     if (L < 3 || (int64_t)L * L * L != D || tx < 1 || ty < 1)
         return fail(FD_ERR_INVALID, "tiled numbering: need the L^3 lattice and tiles of at least one site");
+    if (D >= (int64_t(1) << 31)) return fail(FD_ERR_UNSUPPORTED, "tiled numbering: the walk is indexed in int32");
     HostCSR B;
     std::vector<int32_t> walk, inv;
     try {
