@@ -277,8 +277,9 @@ int32_t fd_syev_last_sweeps(void);
  * `grid` rows each (0 = 1024).  nontemporal != 0: operands that are streamed
  * once bypass the caches.  wide != 0 (nb >= 16): each lane owns 32 bytes of
  * a row (two 16-byte loads per gathered row) instead of 16.  Matrix-free
- * Hubbard matrices use xcd (1: remap as above, else none), nontemporal and
- * tile (down-states per tile of the up-hop pass, 0: the matrix's default).
+ * Hubbard matrices use xcd (1: remap as above, else none), nontemporal,
+ * wide, shfl (for their hop tables) and tile (down-states per tile of the
+ * up-hop pass, 0: the matrix's default).
  * shfl (entry loop): 0, every lane of a row loads every entry; 1 (at
  * least 4 lanes per row, else as 0), lanes 0..3 of a row load 4 of its
  * entries at once and hand them to the row's other lanes by cross-lane
