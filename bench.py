@@ -2,8 +2,9 @@
 """Benchmark of the filter-diagonalization (FD) hot path on one MI355X.
 
 A step is one FD outer iteration on the 3D Anderson lattice L=200 (D = 8.0M,
-7-point hopping t=1, periodic, disorder W=16.5 drawn with seed 1), with
-N_s = 512 search vectors in 8 bundles of nb = 64, target "nearest E = 0":
+7-point hopping t=1, periodic, disorder W=16.5 drawn with seed 1), target
+"nearest E = 0", with N_s search vectors in bundles of nb = 64 (default
+N_s = 128, two bundles; --ns 512 for the full search space):
   coefficients (Jackson-damped delta at E=0, degree 500, host)
   -> Chebyshev filter (500 fused SpMMV steps per bundle)
   -> SVQB2 orthogonalization (MFMA Gram + GPU Jacobi + MFMA rotation)
@@ -15,10 +16,13 @@ with kappa = 5 for the steps that update V and kappa = 3 for the others --
 V takes two terms every other step -- plus the dense passes) divided by the
 step's wall time.
 
-Extra fields: a SpMMV / filter bandwidth sweep over nb and precision, the FD
-eigenpairs/s comparison FP64 vs mixed precision (Hubbard ring L=8, and L=14
-with --hubbard14), the roofline of the dominant kernel (the fused Chebyshev
-step) and the CPU oracle baseline.
+Extra fields: a SpMMV / filter bandwidth sweep over nb and precision with the
+device STREAM ceilings (copy, triad, read-only, write-only); the FD
+eigenpairs/s comparison FP64 vs mixed precision on the Hubbard ring L=8 and
+L=14 (the mixed-precision workload: 64 pairs in [-1, 1], per-pair errors of
+the mixed run against the FP64 run); the roofline of the dominant kernel
+(the fused Chebyshev step) and the CPU oracle baseline (host STREAM, SpMMV
+per nb, filter and FD samples).
 """
 from __future__ import annotations
 
@@ -36,8 +40,11 @@ METRIC = "SpMMV GB/s (% of HBM peak); FD eigenpairs/s at residual 1e-9, mixed vs
 HBM_PEAK_GBS = 8000.0
 
 
+T_START = time.time()
+
+
 def log(*a):
-    print("[bench]", *a, file=sys.stderr, flush=True)
+    print("[bench] %6.1fs" % (time.time() - T_START), *a, file=sys.stderr, flush=True)
 
 
 # ----------------------------------------------------------- byte counts ----
@@ -96,37 +103,49 @@ def traffic_from_profile(kernel_src: str, site_order: str):
 
 def fd_runs(args, fd, np):
     """FD to residual 1e-9 ||H||, FP64 filter vs FP32 filter (mixed), same
-    start block, window, degree and interval rule; eigenpairs per second."""
+    start block, window, degree and interval rule; eigenpairs per second.
+    Per pair: |lambda_mixed - lambda_FP64| / ||H|| and both residuals."""
     from fd_inputs import start_block
     fdres = {}
     # (name, model, window, N_t, N_s, nb, degree)
     runs = [("hubbard8", dict(L=8, n_up=4, n_dn=4, U=4.0), -0.5, 0.5, 16, 128, 16, 100)]
-    if args.hubbard14:
+    if not args.no_hub14:
         runs.append(("hubbard14", dict(L=14, n_up=7, n_dn=7, U=8.0), -1.0, 1.0, 64, 256, 32, 800))
     for name, kw, lo, hi, nt, nsr, nbr, deg in runs:
-        mh = fd.build_matrix("hubbard", fmt=args.hub_fmt, t=1.0, **kw)
+        t0 = time.time()
+        mh = fd.build_matrix("hubbard", fmt=args.hub_fmt, t=1.0, config_order=args.hub_order, **kw)
+        log("FD %s: matrix built in %.1fs (D=%d)" % (name, time.time() - t0, mh.D))
         V0 = start_block(mh.D, nsr, 0) if mh.D * nsr <= 50_000_000 else None
         res = {}
-        evs = {}
+        out = {}
         for prec, label in ((0, "fp64"), (1, "mixed")):
-            r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=200, tol=1e-9, precision=prec, V0=V0,
+            r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=40, tol=1e-9, precision=prec, V0=V0,
                          seed=0, want_vectors=False, adapt=args.adapt)
             st = r.stats
             res[label] = {"converged": r.status == fd.FD_OK, "eigenpairs_per_s": round(nt / st["t_total"], 4),
                           "t_total_s": round(st["t_total"], 3), "iters": st["iters"],
                           "iters_fp32": st["iters_fp32"], "spmmv": st["spmmv_count"],
                           "t_filter_s": round(st["t_filter"], 3), "t_orthog_s": round(st["t_orthog"], 3),
-                          "t_rr_s": round(st["t_rr"], 3), "max_resid_rel": st["max_resid"] / st["norm_H"]}
-            evs[label] = r.evals
-            normH = st["norm_H"]
+                          "t_rr_s": round(st["t_rr"], 3), "max_resid_rel": st["max_resid"] / st["norm_H"],
+                          "norm_H": st["norm_H"]}
+            out[label] = r
             log("FD %s %s: %s" % (name, label, res[label]))
-        res["config"] = {"D": mh.D, "nnz": mh.nnz, "format": args.hub_fmt, "window": [lo, hi], "n_target": nt,
-                         "n_search": nsr,
-                         "nb": nbr, "degree": deg,
+        normH = res["fp64"]["norm_H"]
+        e64, emx = out["fp64"].evals, out["mixed"].evals
+        res["config"] = {"D": mh.D, "nnz": mh.nnz, "format": args.hub_fmt, "labels": ["ranked", "rcm"][args.hub_order],
+                         "window": [lo, hi], "n_target": nt, "n_search": nsr, "nb": nbr, "degree": deg,
                          "window_rule": {0: "fixed", 1: "ritz", 2: "lehmann"}[args.adapt]}
-        res["mixed_vs_fp64_max_rel_eval_diff"] = float(np.max(np.abs(evs["mixed"] - evs["fp64"])) / normH)
+        res["per_pair"] = {"eval_fp64": [float(x) for x in e64],
+                           "abs_diff_mixed_vs_fp64_rel": [float(abs(a - b) / normH) for a, b in zip(emx, e64)],
+                           "resid_fp64_rel": [float(x / normH) for x in out["fp64"].resid],
+                           "resid_mixed_rel": [float(x / normH) for x in out["mixed"].resid]}
+        res["mixed_vs_fp64_max_rel_eval_diff"] = max(res["per_pair"]["abs_diff_mixed_vs_fp64_rel"])
+        res["E0_found"] = bool(np.abs(e64).min() <= 1e-10 * normH and np.abs(emx).min() <= 1e-10 * normH)
         res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
+        log("FD %s: mixed/FP64 speedup %.3f, max |dlambda|/||H|| %.2e, E=0 found %s"
+            % (name, res["speedup_mixed_over_fp64"], res["mixed_vs_fp64_max_rel_eval_diff"], res["E0_found"]))
         fdres[name] = res
+        del mh
     return fdres
 
 
@@ -287,6 +306,115 @@ def hubbard16_runs(args, fd, np, torch):
     return out
 
 
+def cpu_baseline(args, np, L, nb, alpha, beta, fdres):
+    """The oracle on the host cores beside the GPU run (Sec. 3.2's STREAM b_m
+    and kappa, measured on the host): a bounded sample of about 20-30 s.
+    Headline value: the unfused FP64 filter on one nb-wide bundle of the
+    Anderson workload (degree --cpu-degree), in the same algorithmic GB/s as
+    the GPU's.  Extras: host STREAM triad, SpMMV per nb, one full filter of
+    the Hubbard L=8 workload, its FD solve, and the per-step time of the
+    Hubbard L=14 filter with the FD time extrapolated from it."""
+    import platform
+    import subprocess
+    # threads pinned one per core, the -O3 x86-64-v3 copy of the oracle
+    os.environ.setdefault("OMP_PLACES", "cores")
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    os.environ["FD_ORACLE_FAST"] = "1"
+    import oracle as O
+    from fd_inputs import start_block
+    res = {}
+    try:
+        lscpu = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True).stdout
+        cores = {tuple(x.split(",")) for x in lscpu.splitlines() if x and not x.startswith("#")}
+        res["host_physical_cores"] = len(cores)
+    except OSError:
+        res["host_physical_cores"] = None
+    res["host_cpu"] = platform.processor() or platform.machine()
+
+    def med(f, n=3):
+        f()
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    # host STREAM triad on 3 x 1 GiB
+    n = 1 << 27
+    a, b, c = np.ones(n), np.full(n, 2.0), np.empty(n)
+    t = med(lambda: O.stream_triad(a, b, c, 0.5))
+    bm = 3 * n * 8 / t / 1e9
+    res["stream_triad_GBs"] = round(bm, 2)
+    del a, b, c
+    t0 = time.time()
+    A = O.anderson(L, 1.0, 16.5, 1)
+    log("cpu: oracle Anderson matrix built in %.1fs, STREAM triad %.1f GB/s" % (time.time() - t0, bm))
+    D, nnz = A.D, A.rowptr[-1]
+    # SpMMV per nb (natural numbering)
+    sp = {}
+    for w in (1, 4, 8, 16, 32, 64):
+        X = np.random.default_rng(0).standard_normal((D, w))
+        ts = med(lambda: O.spmmv(A, X), 2)
+        sp[str(w)] = {"s": round(ts, 4), "GBs": round(spmmv_bytes(nnz, D, w, 8) / ts / 1e9, 2)}
+        del X
+    res["spmmv_anderson"] = sp
+    log("cpu: SpMMV %s" % sp)
+    # headline: the unfused filter on one bundle
+    Vc = np.random.default_rng(0).standard_normal((D, nb))
+    mu = O.cheb_coeffs(1, beta, 0.0, args.cpu_degree)
+    t0 = time.perf_counter()
+    O.cheb_filter(A, Vc, mu, alpha, beta)
+    tc = time.perf_counter() - t0
+    cb = filter_bytes(nnz, D, nb, 8, args.cpu_degree)
+    # the paper's kappa from the same run: vector traffic per step and row
+    # and vector at the STREAM bandwidth, after the matrix bytes
+    step_t = tc / args.cpu_degree
+    res["kappa_host"] = round((step_t * bm * 1e9 - (nnz * 12 + 4 * (D + 1))) / (D * nb * 8), 2)
+    res.update({"value": round(cb / tc / 1e9, 2), "unit": "GB/s", "cores": O.num_threads(), "kind": "oracle",
+                "sample": "unfused FP64 filter, degree %d, one bundle of nb=%d on Anderson L=%d (natural site "
+                          "numbering; %.1f s); same algorithmic byte count as the GPU filter"
+                          % (args.cpu_degree, nb, L, tc)})
+    del Vc, A
+    # the remaining samples only while the whole run stays well inside its
+    # time limit
+    if time.time() - T_START > args.cpu_deadline:
+        res["skipped"] = "Hubbard samples (run time past %d s)" % args.cpu_deadline
+        return res
+    # Hubbard L=8: one full filter (degree 100, N_s = 128) and the FD solve
+    H8 = O.hubbard(8, 4, 4, 1.0, 4.0)
+    a8, b8 = O.scaling(*O.gershgorin(H8))
+    V8 = start_block(H8.D, 128, 0)
+    res["filter_hubbard8_s"] = round(med(lambda: O.cheb_filter(H8, V8, O.cheb_coeffs(0, a8 * -0.5 + b8,
+                                                                                     a8 * 0.5 + b8, 100),
+                                                              a8, b8), 2), 4)
+    t0 = time.perf_counter()
+    r8 = O.fd_solve(H8, V8, -0.5, 0.5, 16, 100, 1e-9, max_iter=80, adapt=1)
+    res["fd_hubbard8"] = {"s": round(time.perf_counter() - t0, 3), "iters": r8.iters, "converged": r8.converged,
+                          "eigenpairs_per_s": round(16 / (time.perf_counter() - t0), 3)}
+    log("cpu: Hubbard L=8 filter %.3fs, FD %s" % (res["filter_hubbard8_s"], res["fd_hubbard8"]))
+    # Hubbard L=14: two steps of the filter on one bundle of 32, extrapolated
+    if not args.no_hub14 and time.time() - T_START < args.cpu_deadline:
+        t0 = time.time()
+        H14 = O.hubbard(14, 7, 7, 1.0, 8.0)
+        a14, b14 = O.scaling(*O.gershgorin(H14))
+        X = np.random.default_rng(0).standard_normal((H14.D, 32))
+        t0 = time.perf_counter()
+        O.cheb_filter(H14, X, O.cheb_coeffs(0, b14 - a14, b14 + a14, 2), a14, b14)
+        t2 = (time.perf_counter() - t0) / 2
+        g = fdres.get("hubbard14", {}).get("fp64", {})
+        n_spmmv = g.get("spmmv")
+        res["hubbard14"] = {"step_s_nb32": round(t2, 3),
+                            "filter_s_extrapolated": round(t2 * 800 * 8, 1),
+                            "fd_s_extrapolated": round(t2 * n_spmmv, 1) if n_spmmv else None,
+                            "note": "per-step time of the oracle's unfused filter on one bundle of 32 (2 steps "
+                                    "timed); filter = 800 steps x 8 bundles; FD = the GPU FP64 run's SpMMV count "
+                                    "x step time (T_FD ~ n_SpMV T_SpMV, Sec. 4.3), extrapolated"}
+        log("cpu: Hubbard L=14 %s" % res["hubbard14"])
+        del H14, X
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +422,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, default=200)
     ap.add_argument("--nb", type=int, default=64)
-    ap.add_argument("--ns", type=int, default=512)
+    ap.add_argument("--ns", type=int, default=128)
     ap.add_argument("--degree", type=int, default=500)
     ap.add_argument("--fmt", choices=["csr", "sell", "pencil"], default="csr",
                     help="storage / walk of the Anderson matrix (pencil: (x, y) tiles of C x sigma over all z)")
@@ -305,7 +433,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the nb / precision sweep")
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
-    ap.add_argument("--hubbard14", action="store_true", help="also run FD on the Hubbard ring L=14")
+    ap.add_argument("--no-hub14", action="store_true",
+                    help="skip the FD runs on the Hubbard ring L=14 (the mixed-precision workload)")
+    ap.add_argument("--hub-order", type=int, choices=[0, 1], default=0,
+                    help="Hubbard basis labels of the FD runs: 0 ranked, 1 reverse Cuthill-McKee")
+    ap.add_argument("--site-compare", action="store_true",
+                    help="also time a degree-20 filter with the tiled and the natural Anderson numbering")
     ap.add_argument("--fd-only", action="store_true", help="only the FD eigenpairs/s runs (no Anderson step)")
     ap.add_argument("--hubbard16", action="store_true",
                     help="only the matrix-free SpMMV / filter step on the Hubbard ring L=16 (D = 165.6M)")
@@ -319,6 +452,8 @@ def main():
                     help="storage of the Hubbard matrices in the FD runs (matfree: tensor-product form, "
                          "fastest at nb <= 8; csr at nb >= 32)")
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
+    ap.add_argument("--cpu-deadline", type=int, default=440,
+                    help="skip the CPU baseline's Hubbard samples once the run has taken this many seconds")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
                          "filter on one nb=64 FP64 bundle of the workload; prints the sizes and exits")
@@ -462,7 +597,7 @@ def main():
     # ------------------------------------------- site numbering check ----
     # the same degree-20 filter on one bundle with the tiled and the natural
     # numbering of the lattice (each with its autotuned launch shape)
-    if tiles[0] and not args.no_sweep:
+    if tiles[0] and args.site_compare:
         mn = fd.build_matrix("anderson", L=L, t=1.0, W=16.5, seed=1)
         cmp_ = {}
         for name, mm in (("tiled", m), ("natural", mn)):
@@ -492,7 +627,8 @@ def main():
         a = torch.empty(D * 64, dtype=torch.float64, device=dev).normal_()
         b = torch.empty_like(a).normal_()
         c = torch.empty_like(a)
-        for op, name, nbytes in ((0, "stream_copy_GBs", 2), (1, "stream_triad_GBs", 3)):
+        for op, name, nbytes in ((0, "stream_copy_GBs", 2), (1, "stream_triad_GBs", 3), (2, "stream_read_GBs", 1),
+                                 (3, "stream_write_GBs", 1)):
             for _ in range(3):
                 fd.stream(op, a, c, b, 0.5, stream=stream)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -502,7 +638,8 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             out[name] = round(nbytes * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-        log("STREAM copy %.0f GB/s, triad %.0f GB/s" % (out["stream_copy_GBs"], out["stream_triad_GBs"]))
+        log("STREAM copy %.0f GB/s, triad %.0f GB/s, read-only %.0f GB/s, write-only %.0f GB/s"
+            % (out["stream_copy_GBs"], out["stream_triad_GBs"], out["stream_read_GBs"], out["stream_write_GBs"]))
         del a, b, c
         for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
             for w in (1, 4, 8, 16, 32, 64):
@@ -545,22 +682,7 @@ def main():
 
     # ------------------------------------------------------- CPU oracle ----
     if not args.no_cpu:
-        import oracle as O
-        t0 = time.time()
-        A = O.anderson(L, 1.0, 16.5, 1)
-        log("oracle matrix built in %.1fs" % (time.time() - t0))
-        Vc = np.random.default_rng(0).standard_normal((D, nb))
-        mu = O.cheb_coeffs(1, beta, 0.0, args.cpu_degree)
-        t0 = time.perf_counter()
-        O.cheb_filter(A, Vc, mu, alpha, beta)
-        tc = time.perf_counter() - t0
-        cb = filter_bytes(nnz, D, nb, 8, args.cpu_degree)
-        out["cpu_baseline"] = {"value": round(cb / tc / 1e9, 2), "unit": "GB/s", "cores": O.num_threads(),
-                               "kind": "oracle",
-                               "sample": "unfused FP64 filter, degree %d, one bundle of nb=%d on Anderson L=%d "
-                                         "(natural site numbering; %.1f s); same algorithmic byte count as the "
-                                         "GPU filter" % (args.cpu_degree, nb, L, tc)}
-        log("cpu baseline %.2f GB/s in %.1fs" % (cb / tc / 1e9, tc))
+        out["cpu_baseline"] = cpu_baseline(args, np, L, nb, alpha, beta, out.get("fd", {}))
 
     print(json.dumps(out), flush=True)
 

@@ -69,6 +69,15 @@ typedef enum {
  *   in increasing integer order; row = rank(up) * C(L, n_dn) + rank(down).
  *   The diagonal U * (number of doubly occupied sites) is always stored.
  *   D = C(L, n_up) C(L, n_dn) (the Hubbard dimension of Sec. 4.1).
+ *   config_order 1: each species' configurations are labelled in reverse
+ *   Cuthill-McKee order of that species' hop graph instead of by rank
+ *   (breadth-first from a pseudo-peripheral configuration, neighbours by
+ *   increasing hop count, then rank; the visiting order reversed), and row
+ *   = label(up) * C(L, n_dn) + label(down).  The matrix is then P A P^T of
+ *   the ranked one, entry for entry; configurations one hop apart get
+ *   nearby labels, so an up hop's gathered rows lie within a few hundred
+ *   slabs of C(L, n_dn) rows.  fd_matrix_export_configs returns the
+ *   configuration of every label.  config_order 0 is the ranked basis.
  * FD_ANDERSON_3D: site (x,y,z) -> x + L y + L^2 z, periodic nearest-neighbour
  *   hopping -t, on-site energy W (u_{i+skip} - 1/2), u_k the k-th output
  *   (from 0) of SplitMix64 seeded with `seed` (top 53 bits times 2^-53),
@@ -99,6 +108,7 @@ typedef struct {
     const double *val;      /* FD_USER_CSR */
     int64_t skip;           /* FD_ANDERSON_3D */
     int32_t tile_x, tile_y; /* FD_ANDERSON_3D: tiled site numbering (0, 0: natural) */
+    int32_t config_order;   /* FD_HUBBARD_RING: 0 ranked, 1 reverse Cuthill-McKee labels */
 } fd_model_params;
 
 typedef struct fd_matrix_s *fd_matrix; /* opaque, owned by the library */
@@ -151,6 +161,12 @@ fd_status fd_matrix_export_csr(fd_matrix m, int64_t *rowptr, uint32_t *col, doub
  * FD_ERR_INVALID.                                                           */
 fd_status fd_matrix_export_sell(fd_matrix m, int32_t *perm, int64_t *chunk_ptr,
                                 int32_t *chunk_len, uint32_t *col, double *val);
+
+/* FD_HUBBARD_RING (any format): the spin configuration (L-bit mask) of
+ * every up label into up[C(L, n_up)] and of every down label into
+ * dn[C(L, n_dn)], caller host arrays; row a * C(L, n_dn) + b of the matrix is
+ * the Fock state (up[a], dn[b]).  Other models: FD_ERR_INVALID.            */
+fd_status fd_matrix_export_configs(fd_matrix m, uint64_t *up, uint64_t *dn);
 
 void fd_matrix_free(fd_matrix m);
 
@@ -259,9 +275,13 @@ fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_ta
 fd_status fd_autotune(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
 
 /* STREAM-style bandwidth kernels on device arrays of n doubles (n even,
- * 16-byte aligned): op 0 copies c = a, op 1 is the triad c = a + scalar b.
- * The paper measures its memory bandwidth b_m with STREAM (Sec. 3.3,
- * Table 4); these give the same figure for the GPU's HBM.                  */
+ * 16-byte aligned): op 0 copies c = a, op 1 is the triad c = a + scalar b,
+ * op 2 only reads a (each thread writes one 16-byte partial sum into c, so
+ * n >= 2^19 and c holds at least that many values; a stays unchanged), op 3
+ * only writes (c = scalar; a and b unused, may be NULL).  The paper
+ * measures its memory bandwidth b_m with STREAM (Sec. 3.2, Eq. EstimateT,
+ * Table 4); these give the same figure for the GPU's HBM, and the read-only
+ * and write-only passes bound kernels whose traffic is mostly one way.     */
 fd_status fd_stream(int32_t op, int64_t n, const double *a_dev, const double *b_dev, double *c_dev,
                     double scalar, void *stream);
 
@@ -350,6 +370,11 @@ typedef struct {
                               eigenvalues (fd_lehmann; Sec. 2)              */
     const float *picker_dev; /* degree 0: degree-picker parameters (device,
                               FD_MLP_NPARAMS) or NULL for the KPM rule     */
+    int32_t interval;      /* scaling interval of the filter: 0 Gershgorin;
+                              k in [1, 512]: k Lanczos steps (fd_lanczos,
+                              seed 1), [theta_1 - r_1, theta_k + r_k] widened
+                              by 1 % of its width, inside the Gershgorin
+                              interval (Sec. 2: a few steps of Lanczos)    */
 } fd_solve_params;
 
 typedef struct {
@@ -358,10 +383,25 @@ typedef struct {
     int32_t iters_fp32;   /* of which in FP32 (precision 1)                   */
     int64_t spmmv_count;  /* SpMMVs on nb-vector bundles                      */
     double t_filter, t_orthog, t_rr, t_total; /* seconds                      */
-    double norm_H;        /* max(|lam_lo|, |lam_hi|) of the Gershgorin bound  */
+    double norm_H;        /* ||H|| of the test rho <= tol ||H||: the largest
+                             |Ritz value| of 40 Lanczos steps (fd_lanczos,
+                             seed 1), a lower bound of ||H||_2            */
     double max_resid;     /* largest rho among the returned pairs             */
     int32_t degree;       /* filter degree used                               */
 } fd_solve_stats;
+
+/* k steps of Lanczos (Sec. 2: spectral bounds from "a few steps of
+ * Lanczos"), FP64, full reorthogonalization (classical Gram-Schmidt against
+ * all earlier basis vectors, twice), start vector u_i = 2 U_i - 1 with U_i
+ * the i-th output (from 0) of SplitMix64(seed), top 53 bits times 2^-53.
+ * Stops early when the new vector's norm drops to 1e-12 of the largest
+ * |alpha| (an invariant subspace).  Outputs (caller host arrays of k):
+ * theta ascending Ritz values of the tridiagonal, resid their bounds
+ * beta_k |s_kj| (each theta_j has an eigenvalue within resid_j); *steps the
+ * steps taken (<= min(k, D)).  1 <= k <= 512.  Allocates (k + 1) D doubles
+ * of device memory for the basis.  Synchronizes.                           */
+fd_status fd_lanczos(fd_matrix m, int32_t k, uint64_t seed, double *theta_host, double *resid_host,
+                     int32_t *steps, void *stream);
 
 /* Plain FD (Alg. 1 caption): Gershgorin inclusion interval, alpha and beta,
  * start block V0_host (D x N_s row-major host array) or, if NULL, N(0,1)
@@ -370,7 +410,11 @@ typedef struct {
  * the window -> filter with the window's Jackson-damped indicator
  * coefficients.  Outputs: evals_host[N_t] ascending, evecs_dev (device
  * D x N_t, ld N_t) or NULL, resid_host[N_t] or NULL, stats or NULL.  Returns
- * FD_ERR_NOT_CONVERGED (outputs written) if max_iter is reached.          */
+ * FD_ERR_NOT_CONVERGED (outputs written) if max_iter is reached, or
+ * earlier once the FP64 filter stagnates: the largest residual of the
+ * targets has not fallen below 0.9 of its best value for 10 iterations.
+ * Non-finite data anywhere in the iteration (e.g. NaN in V0_host, or a
+ * filter that overflowed) give FD_ERR_BREAKDOWN.                           */
 fd_status fd_solve(fd_matrix m, const fd_solve_params *params, const double *V0_host,
                    double *evals_host, double *evecs_dev, double *resid_host,
                    fd_solve_stats *stats);
@@ -443,6 +487,12 @@ typedef struct {
 fd_status fd_solve_batch(fd_batch b, const fd_solve_params *params, const double *V0_host,
                          double *evals_host, double *evecs_dev, double *resid_host,
                          fd_solve_stats *stats, fd_batch_stats *bstats);
+
+/* Test hook for the out-of-memory path: while bytes > 0, every device
+ * buffer that fd_solve, fd_solve_batch or fd_lanczos would allocate above
+ * that size fails with FD_ERR_OOM (nothing is allocated); 0 lifts the limit.
+ * Process-wide.  bytes < 0: FD_ERR_INVALID.                                 */
+fd_status fd_debug_alloc_limit(int64_t bytes);
 
 const char *fd_last_error(void);
 

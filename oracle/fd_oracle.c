@@ -340,6 +340,14 @@ void orc_sell_fill(int64_t D, const int64_t *rowptr, const uint32_t *col,
 }
 
 /* ------------------------------------------------------------------------ */
+/* STREAM triad c = a + s b (Sec. 3.2 measures b_m with STREAM).           */
+void orc_triad(int64_t n, const double *a, const double *b, double *c, double s)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) c[i] = a[i] + s * b[i];
+}
+
+/* ------------------------------------------------------------------------ */
 /* y = A x on row-major blocks: y[i*ldy + c] = sum_k val[k] x[col[k]*ldx + c]
  * (Eq. SpMVprocess applied to each of the nb vectors).                     */
 void orc_spmmv(int64_t D, const int64_t *rowptr, const uint32_t *col,

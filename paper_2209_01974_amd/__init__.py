@@ -42,14 +42,15 @@ class ModelParams(C.Structure):
                 ("periodic", C.c_int32), ("t", C.c_double), ("U", C.c_double), ("W", C.c_double),
                 ("seed", C.c_uint64), ("n", C.c_int64), ("diag", C.c_void_p), ("D", C.c_int64),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p), ("skip", C.c_int64),
-                ("tile_x", C.c_int32), ("tile_y", C.c_int32)]
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("config_order", C.c_int32)]
 
 
 class SolveParams(C.Structure):
     _fields_ = [("tau_lo", C.c_double), ("tau_hi", C.c_double), ("n_target", C.c_int32),
                 ("n_search", C.c_int32), ("nb", C.c_int32), ("degree", C.c_int32),
                 ("max_iter", C.c_int32), ("tol", C.c_double), ("precision", C.c_int32),
-                ("ortho", C.c_int32), ("seed", C.c_uint64), ("adapt", C.c_int32), ("picker_dev", C.c_void_p)]
+                ("ortho", C.c_int32), ("seed", C.c_uint64), ("adapt", C.c_int32), ("picker_dev", C.c_void_p),
+                ("interval", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -82,6 +83,9 @@ _SIGS = {
     "fd_matrix_info": [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D)],
     "fd_matrix_export_csr": [_P, _P, _P, _P],
     "fd_matrix_export_sell": [_P, _P, _P, _P, _P, _P],
+    "fd_matrix_export_configs": [_P, _P, _P],
+    "fd_lanczos": [_P, _I32, C.c_uint64, _P, _P, C.POINTER(_I32), _P],
+    "fd_debug_alloc_limit": [_I64],
     "fd_spmmv": [_P, C.c_int, _I32, _P, _I64, _P, _I64, _P],
     "fd_cheb_filter": [_P, C.c_int, _I32, _I32, _P, _I64, _P, _I32, _D, _D, _P, _P, _I64, _P],
     "fd_cheb_coeffs": [_I32, _D, _D, _I32, _P],
@@ -201,6 +205,13 @@ class Matrix:
                                            col.ctypes.data, val.ctypes.data))
         return perm, cptr, clen, col, val
 
+    def export_configs(self, n_up_configs: int, n_dn_configs: int):
+        """Spin configuration (bit mask) of every up and down label of a Hubbard matrix."""
+        up = np.empty(n_up_configs, np.uint64)
+        dn = np.empty(n_dn_configs, np.uint64)
+        _check(lib().fd_matrix_export_configs(self._h, up.ctypes.data, dn.ctypes.data))
+        return up, dn
+
     def free(self):
         if self._h:
             lib().fd_matrix_free(self._h)
@@ -216,7 +227,7 @@ class Matrix:
 def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host_only: bool = False,
                  L: int = 0, n_up: int = 0, n_dn: int = 0, periodic: bool = True, t: float = 1.0,
                  U: float = 0.0, W: float = 0.0, seed: int = 0, diag=None, csr=None, skip: int = 0,
-                 tiles=(0, 0)) -> Matrix:
+                 tiles=(0, 0), config_order: int = 0) -> Matrix:
     """fd_build_matrix for model in {"hubbard", "anderson", "diagonal", "csr"} and fmt in
     {"csr", "sell", "matfree", "pencil"} ("matfree": Hubbard only, C_ = default up-pass tile;
     "pencil": Anderson only, C_ x sigma = (x, y) tile of the walk).  tiles = (tile_x, tile_y):
@@ -228,6 +239,7 @@ def build_matrix(model: str, fmt: str = "csr", C_: int = 1, sigma: int = 1, host
     p.L, p.n_up, p.n_dn, p.periodic = L, n_up, n_dn, int(periodic)
     p.t, p.U, p.W, p.seed, p.skip = t, U, W, seed, skip
     p.tile_x, p.tile_y = int(tiles[0]), int(tiles[1])
+    p.config_order = int(config_order)
     if diag is not None:
         d = np.ascontiguousarray(diag, dtype=np.float64)
         keep.append(d)
@@ -399,6 +411,20 @@ def lehmann(V, W, rho: float, stream=None):
     return lo[:nl.value].copy(), up[:nu.value].copy()
 
 
+def lanczos(m: Matrix, k: int = 40, seed: int = 1, stream=None):
+    """fd_lanczos: (theta ascending, residual bounds) of k Lanczos steps."""
+    th = np.empty(k)
+    rs = np.empty(k)
+    n = _I32()
+    _check(lib().fd_lanczos(m.handle, k, seed, th.ctypes.data, rs.ctypes.data, C.byref(n), _stream(stream)))
+    return th[:n.value].copy(), rs[:n.value].copy()
+
+
+def debug_alloc_limit(nbytes: int) -> None:
+    """fd_debug_alloc_limit: make solver buffers above nbytes fail (0: off)."""
+    _check(lib().fd_debug_alloc_limit(nbytes))
+
+
 def syev_last_sweeps() -> int:
     return int(lib().fd_syev_last_sweeps())
 
@@ -434,13 +460,13 @@ class SolveResult:
 def solve(m: Matrix, tau_lo: float, tau_hi: float, n_target: int, n_search: int, nb: int, degree: int,
           max_iter: int = 50, tol: float = 1e-9, precision: int = 0, ortho: int = FD_ORTHO_SVQB2,
           seed: int = 0, V0: np.ndarray | None = None, want_vectors: bool = True,
-          adapt: int = 0, picker=None) -> SolveResult:
+          adapt: int = 0, picker=None, interval: int = 0) -> SolveResult:
     """fd_solve; V0 is a host D x n_search float64 array (or None).  degree 0
     picks the degree from KPM moments (picker: GPU float32 parameter tensor
     of the degree-picker network, or None for the plain rule)."""
     import torch
     p = SolveParams(tau_lo, tau_hi, n_target, n_search, nb, degree, max_iter, tol, precision, ortho, seed, adapt,
-                    C.c_void_p(picker.data_ptr()) if picker is not None else None)
+                    C.c_void_p(picker.data_ptr()) if picker is not None else None, interval)
     ev = np.full(n_target, np.nan)
     rs = np.full(n_target, np.nan)
     vecs = torch.empty((m.D, n_target), dtype=torch.float64, device="cuda") if want_vectors else None

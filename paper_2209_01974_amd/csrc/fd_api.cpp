@@ -1,5 +1,6 @@
 // libfd C ABI: handles, argument checks, the Chebyshev filter loop, the
 // orthogonalization and Rayleigh-Ritz steps and the FD driver.
+#include <atomic>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -264,7 +265,7 @@ fd_status orthog_impl(int64_t D, int ns, double *V, int64_t ldv, int method, uin
         bool ok = true;
         for (int pass = 0; pass < 2 && ok; pass++) {
             FD_TRY(gram(D, ns, ns, V, ldv, V, ldv, b.G, ns, true, s));
-            FD_TRY(cholqr_transform(ns, b.G, b.Q, b.ints, s));
+            FD_TRY(cholqr_transform(ns, b.G, b.Q, b.ints, pass == 1, s));
             int okh = 0;
             FD_HIP(hipMemcpyAsync(&okh, b.ints, sizeof(int), hipMemcpyDeviceToHost, s));
             FD_HIP(hipStreamSynchronize(s));
@@ -332,7 +333,7 @@ fd_status lehmann_impl(int64_t D, int n, const double *V, const double *W, int64
     FD_TRY(gram(D, n, n, V, ld, W, ld, G1, n, false, s));
     FD_TRY(gram(D, n, n, V, ld, V, ld, G0, n, true, s));
     FD_TRY(lehmann_pencil(n, G2, G1, G0, rho, B, S, s));
-    FD_TRY(cholqr_transform(n, B, Q, ok, s));
+    FD_TRY(cholqr_transform(n, B, Q, ok, false, s));
     int okh = 0;
     FD_HIP(hipMemcpyAsync(&okh, ok, sizeof(int), hipMemcpyDeviceToHost, s));
     FD_HIP(hipStreamSynchronize(s));
@@ -415,20 +416,125 @@ double kpm_radius(const std::vector<double> &mu, int64_t D, double alpha, double
     return r1;
 }
 
+// Test hook: device buffers of the solvers larger than this many bytes fail
+// as if the device were out of memory (0: no limit).
+std::atomic<int64_t> g_alloc_limit{0};
+
 struct DevBuf {
     void *p = nullptr;
     ~DevBuf() {
         if (p) (void)hipFree(p);
     }
     fd_status alloc(size_t bytes, const char *what) {
+        const int64_t lim = g_alloc_limit.load();
+        if (lim > 0 && (int64_t)bytes > lim)
+            return fail(FD_ERR_OOM, std::string("cannot allocate ") + what + " (allocation limit set)");
         if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
-            return fail(FD_ERR_OOM, std::string("fd_solve: cannot allocate ") + what);
+            return fail(FD_ERR_OOM, std::string("cannot allocate ") + what);
         }
         return FD_OK;
     }
 };
+
+// k steps of Lanczos with full reorthogonalization (classical Gram-Schmidt
+// against every earlier basis vector, twice) from the seeded start vector
+// (Sec. 2: the spectral bounds come from a few Lanczos steps).  Stops early
+// when the new vector's norm drops to 1e-12 of the largest |alpha|
+// (invariant subspace).  theta: Ritz values of the tridiagonal, ascending;
+// resid: their residual bounds beta_k |s_kj|.  Synchronizes.
+// M's rows gather x at the row indices M.col, shifted by -xoff (a slice of a
+// block-diagonal stack whose columns carry the slice's first row).
+fd_status lanczos_impl(const DevMatrix &M, int64_t xoff, int k, uint64_t seed, std::vector<double> &theta,
+                       std::vector<double> &resid, hipStream_t s) {
+    const int64_t D = M.D;
+    if (k < 1 || k > 512) return fail(FD_ERR_INVALID, "Lanczos: need 1 <= k <= 512");
+    k = (int)std::min<int64_t>(k, D);
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (D + 8191) / 8192));
+    DevBuf Q;
+    FD_TRY(Q.alloc((size_t)(k + 1) * D * 8, "the Lanczos basis"));
+    double *Qd = (double *)Q.p;
+    // small device buffers: c (k), partial sums (nblk k), T (k k), U (k k), w (k)
+    const size_t nsmall = (size_t)k + (size_t)nblk * k + 2 * (size_t)k * k + k;
+    double *c = (double *)workspace(nsmall * sizeof(double), 9);
+    if (!c) return fail(FD_ERR_OOM, "Lanczos: workspace");
+    double *P = c + k, *T = P + (size_t)nblk * k, *U = T + (size_t)k * k, *w = U + (size_t)k * k;
+    auto norm_of = [&](const double *v, double &out) -> fd_status {
+        FD_TRY(lz_dots(D, 1, v, v, c, P, nblk, s));
+        double h = 0.0;
+        FD_HIP(hipMemcpyAsync(&h, c, sizeof(double), hipMemcpyDeviceToHost, s));
+        FD_HIP(hipStreamSynchronize(s));
+        out = std::sqrt(h);
+        return FD_OK;
+    };
+    FD_TRY(lz_start(D, Qd, seed, s));
+    double b0 = 0.0;
+    FD_TRY(norm_of(Qd, b0));
+    if (!(b0 > 0.0)) return fail(FD_ERR_BREAKDOWN, "Lanczos: zero start vector");
+    FD_TRY(lz_scale(D, Qd, 1.0 / b0, s));
+    std::vector<double> alpha(k, 0.0), beta(k, 0.0);
+    int steps = k;
+    for (int j = 0; j < k; j++) {
+        double *qj = Qd + (int64_t)j * D, *wv = Qd + (int64_t)(j + 1) * D;
+        SpmmvCall call;
+        call.mode = 0;
+        call.nb = 1;
+        call.x = qj - xoff;
+        call.ldx = 1;
+        call.y = wv;
+        call.ldy = 1;
+        FD_TRY(launch_spmmv(M, FD_F64, call, s));
+        for (int pass = 0; pass < 2; pass++) {
+            FD_TRY(lz_dots(D, j + 1, Qd, wv, c, P, nblk, s));
+            FD_TRY(lz_sub(D, j + 1, Qd, c, wv, s));
+            double cj = 0.0;
+            FD_HIP(hipMemcpyAsync(&cj, c + j, sizeof(double), hipMemcpyDeviceToHost, s));
+            FD_HIP(hipStreamSynchronize(s));
+            alpha[j] += cj;
+        }
+        FD_TRY(norm_of(wv, beta[j]));
+        double amax = 0.0;
+        for (int i = 0; i <= j; i++) amax = std::max(amax, std::fabs(alpha[i]));
+        if (!std::isfinite(beta[j]) || !std::isfinite(alpha[j]))
+            return fail(FD_ERR_BREAKDOWN, "Lanczos: non-finite recurrence");
+        if (beta[j] <= 1e-12 * amax) {
+            steps = j + 1;
+            break;
+        }
+        FD_TRY(lz_scale(D, wv, 1.0 / beta[j], s));
+    }
+    std::vector<double> Th((size_t)steps * steps, 0.0);
+    for (int i = 0; i < steps; i++) {
+        Th[(size_t)i * steps + i] = alpha[i];
+        if (i + 1 < steps) Th[(size_t)i * steps + i + 1] = Th[(size_t)(i + 1) * steps + i] = beta[i];
+    }
+    FD_HIP(hipMemcpyAsync(T, Th.data(), Th.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    FD_TRY(syev(steps, T, steps, w, U, steps, s));
+    theta.assign(steps, 0.0);
+    std::vector<double> Uh((size_t)steps * steps);
+    FD_HIP(hipMemcpyAsync(theta.data(), w, steps * sizeof(double), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipMemcpyAsync(Uh.data(), U, Uh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    resid.assign(steps, 0.0);
+    for (int j = 0; j < steps; j++) resid[j] = beta[steps - 1] * std::fabs(Uh[(size_t)(steps - 1) * steps + j]);
+    return FD_OK;
+}
+
+// ||H|| of the convergence test: the largest |Ritz value| of 40 Lanczos
+// steps from SplitMix64 seed 1, a lower bound of ||H||_2, so that
+// rho <= tol ||H|| is never looser than the target.  Cached in the handle.
+constexpr int kNormSteps = 40;
+constexpr uint64_t kNormSeed = 1;
+fd_status lanczos_norm(fd_matrix m, double &out, hipStream_t s) {
+    if (!(m->lz_norm >= 0.0)) {
+        std::vector<double> th, rs;
+        FD_TRY(lanczos_impl(m->dev, 0, kNormSteps, kNormSeed, th, rs, s));
+        m->lz_norm = std::max(std::fabs(th.front()), std::fabs(th.back()));
+    }
+    out = m->lz_norm;
+    return FD_OK;
+}
 
 }  // namespace
 }  // namespace fd
@@ -438,6 +544,7 @@ struct fd_batch_s {
     int device = -1;
     std::vector<int64_t> off;  // n_inst + 1 row offsets
     std::vector<double> lam_lo, lam_hi;
+    std::vector<double> lz_norm;  // per instance ||H|| estimate (Lanczos), filled on first use
     fd::BatchDev dev;
     int32_t mu_cap = 0;  // entries allocated in dev.mu
     hipStream_t cap = nullptr;  // capture-only stream
@@ -600,7 +707,7 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
     if (!m) return fail(FD_ERR_OOM, "fd_build_matrix: host allocation");
     fd_status st;
     if (fmt == FD_FMT_MATFREE) {
-        st = hubbard_tables(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->hub);
+        st = hubbard_tables(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, p->config_order, m->hub);
         m->fmt = fmt;
         if (st == FD_OK) {
             m->D = m->hub.nu * m->hub.nd;
@@ -621,7 +728,10 @@ fd_status fd_build_matrix(const fd_model_params *p, fd_format fmt, int32_t C, in
         return FD_OK;
     }
     switch (p->model) {
-        case FD_HUBBARD_RING: st = build_hubbard(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, m->csr); break;
+        case FD_HUBBARD_RING:
+            st = build_hubbard(p->L, p->n_up, p->n_dn, p->periodic != 0, p->t, p->U, p->config_order, m->csr,
+                               m->cfg_up, m->cfg_dn);
+            break;
         case FD_ANDERSON_3D:
             if (p->tile_x < 0 || p->tile_y < 0 || (p->tile_x == 0) != (p->tile_y == 0))
                 st = fail(FD_ERR_INVALID, "Anderson: tile_x and tile_y both 0 (natural numbering) or both >= 1");
@@ -688,6 +798,16 @@ fd_status fd_matrix_export_sell(fd_matrix m, int32_t *perm, int64_t *cptr, int32
     std::memcpy(clen, S.chunk_len.data(), S.chunk_len.size() * sizeof(int32_t));
     std::memcpy(col, S.col.data(), S.col.size() * sizeof(uint32_t));
     std::memcpy(val, S.val.data(), S.val.size() * sizeof(double));
+    return FD_OK;
+}
+
+fd_status fd_matrix_export_configs(fd_matrix m, uint64_t *up, uint64_t *dn) {
+    if (!m || !up || !dn) return fail(FD_ERR_INVALID, "fd_matrix_export_configs: null argument");
+    const std::vector<uint64_t> &cu = m->fmt == FD_FMT_MATFREE ? m->hub.mu : m->cfg_up;
+    const std::vector<uint64_t> &cd = m->fmt == FD_FMT_MATFREE ? m->hub.md : m->cfg_dn;
+    if (cu.empty()) return fail(FD_ERR_INVALID, "fd_matrix_export_configs: not a Hubbard matrix");
+    std::memcpy(up, cu.data(), cu.size() * sizeof(uint64_t));
+    std::memcpy(dn, cd.data(), cd.size() * sizeof(uint64_t));
     return FD_OK;
 }
 
@@ -962,6 +1082,18 @@ fd_status fd_rayleigh_ritz(fd_matrix m, int32_t ns, int32_t nb, double *V, doubl
     return rr_impl(m, ns, nb, V, W, ld, theta, resid, (hipStream_t)stream);
 }
 
+fd_status fd_lanczos(fd_matrix m, int32_t k, uint64_t seed, double *theta, double *resid, int32_t *steps,
+                     void *stream) {
+    FD_TRY(need_device(m));
+    if (!theta || !resid || !steps) return fail(FD_ERR_INVALID, "fd_lanczos: null output");
+    std::vector<double> th, rs;
+    FD_TRY(lanczos_impl(m->dev, 0, k, seed, th, rs, (hipStream_t)stream));
+    std::copy(th.begin(), th.end(), theta);
+    std::copy(rs.begin(), rs.end(), resid);
+    *steps = (int32_t)th.size();
+    return FD_OK;
+}
+
 fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, double *evals, double *evecs,
                    double *resid, fd_solve_stats *stats) {
     FD_TRY(need_device(m));
@@ -978,10 +1110,25 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     if (!(hi > lo)) return fail(FD_ERR_INVALID, "fd_solve: spectrum interval is a point");
     const int64_t D = m->dev.D;
     if (ns > D) return fail(FD_ERR_INVALID, "fd_solve: N_s > D");
-    const double t0 = now();
-    const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
-    const double normH = std::max(std::fabs(lo), std::fabs(hi));
     if (P->adapt < 0 || P->adapt > 2) return fail(FD_ERR_INVALID, "fd_solve: adapt must be 0, 1 or 2");
+    if (P->interval < 0 || P->interval > 512) return fail(FD_ERR_INVALID, "fd_solve: interval must be in [0, 512]");
+    const double t0 = now();
+    hipStream_t s = nullptr;
+    double normH = 0.0;
+    FD_TRY(lanczos_norm(m, normH, s));
+    // scaling interval: Gershgorin, or (interval = k > 0) the k-step Lanczos
+    // interval widened by the residual bounds and 1 % of its width, inside
+    // the Gershgorin one
+    double slo = lo, shi = hi;
+    if (P->interval > 0) {
+        std::vector<double> th, rs;
+        FD_TRY(lanczos_impl(m->dev, 0, P->interval, kNormSeed, th, rs, s));
+        const double a = th.front() - rs.front(), b = th.back() + rs.back(), w = 0.01 * (b - a);
+        slo = std::max(lo, a - w);
+        shi = std::min(hi, b + w);
+        if (!(shi > slo)) return fail(FD_ERR_BREAKDOWN, "fd_solve: empty Lanczos interval");
+    }
+    const double alpha = 2.0 / (shi - slo), beta = -(shi + slo) / (shi - slo);
     int degree = P->degree;
     double r0 = -1.0;
     if (degree == 0)
@@ -1004,7 +1151,6 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     } else {
         FD_TRY(set_coeffs(P->tau_lo, P->tau_hi));
     }
-    hipStream_t s = nullptr;
     // Workspaces: all bundles in one launch when W1/W2 for every bundle fit in
     // 512 MB; otherwise bundle by bundle with nb-wide W1/W2.
     const bool concurrent = (size_t)D * ns * 8 * 2 <= (512ull << 20);
@@ -1039,6 +1185,12 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     const char *tr = std::getenv("FD_TRACE");
     const bool trace = tr && tr[0] == '1';
     double prev_max = INFINITY;
+    // stagnation: the largest residual of the targets has not dropped below
+    // 0.9 of its best value for kStall iterations (FP64 filter)
+    constexpr int kStall = 10;
+    double best_max = INFINITY;
+    int stall = 0;
+    bool stagnated = false;
     const double tol = P->tol * normH;
     bool converged = false;
     int it = 0;
@@ -1087,13 +1239,25 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
                          st.t_orthog, st.t_rr, lrs, now() - t0);
             std::fflush(stderr);
         }
-        if (converged || it >= P->max_iter) break;
+        if (!fp32) {
+            if (mx < 0.9 * best_max) {
+                best_max = mx;
+                stall = 0;
+            } else {
+                stall++;
+            }
+        }
+        stagnated = !converged && stall >= kStall;
+        if (converged || it >= P->max_iter || stagnated) break;
         // mixed precision: leave FP32 once the residual is near what an FP32
         // filter can deliver (1e-6 ||H||), or once it stalls (under 10 %
         // progress per iteration) below 1e-3 ||H||
         if (fp32 && std::isfinite(mx) &&
-            (mx <= 1e-6 * normH || (mx > 0.9 * prev_max && mx < 1e-3 * normH)))
+            (mx <= 1e-6 * normH || (mx > 0.9 * prev_max && mx < 1e-3 * normH))) {
             fp32 = false;
+            best_max = mx;
+            stall = 0;
+        }
         prev_max = mx;
         if (P->adapt == 1 && P->tau_hi > P->tau_lo && (int)sel.size() == nt) {
             // target window: tau +- distance of the N_t-th nearest Ritz value
@@ -1142,7 +1306,15 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     }
     st.t_total = now() - t0;
     if (stats) *stats = st;
-    if (!converged) return fail(FD_ERR_NOT_CONVERGED, "fd_solve: not converged within max_iter");
+    if (!converged)
+        return fail(FD_ERR_NOT_CONVERGED, stagnated ? "fd_solve: stagnated (no 10% progress in 10 iterations)"
+                                                    : "fd_solve: not converged within max_iter");
+    return FD_OK;
+}
+
+fd_status fd_debug_alloc_limit(int64_t bytes) {
+    if (bytes < 0) return fail(FD_ERR_INVALID, "fd_debug_alloc_limit: bytes must be >= 0");
+    g_alloc_limit.store(bytes);
     return FD_OK;
 }
 
@@ -1319,6 +1491,7 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
         if (p.nb != nb || p.n_search != ns || p.n_target != nt || p.ortho != ortho)
             return fail(FD_ERR_INVALID, "fd_solve_batch: nb, N_s, N_t and ortho must agree across instances");
         if (p.precision != 0) return fail(FD_ERR_UNSUPPORTED, "fd_solve_batch: FP64 only (precision 0)");
+        if (p.interval != 0) return fail(FD_ERR_UNSUPPORTED, "fd_solve_batch: Gershgorin scaling only (interval 0)");
         if (p.degree < 2 || p.degree > 100000) return fail(FD_ERR_INVALID, "fd_solve_batch: degree must be in [2, 1e5]");
         if (p.max_iter < 0 || !(p.tol > 0) || (p.adapt != 0 && p.adapt != 1))
             return fail(FD_ERR_INVALID, "fd_solve_batch: bad max_iter, tol or adapt");
@@ -1342,11 +1515,31 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
         if (whi > wlo) return cheb_coeffs(0, a, std::max(a, std::min(1.0, alpha[i] * whi + beta[i])), P[i].degree, m);
         return cheb_coeffs(1, a, 0.0, P[i].degree, m);
     };
+    if (b->lz_norm.empty()) {
+        // ||H|| of each instance as in fd_solve: 40 Lanczos steps on the
+        // instance's rows of the stacked matrix (its columns carry the
+        // instance's first row, so the gathered vector is shifted by it)
+        std::vector<double> nrm(n);
+        for (int i = 0; i < n; i++) {
+            DevMatrix v;
+            v.D = b->off[i + 1] - b->off[i];
+            v.nslots = v.D;
+            v.maxlen = b->dev.maxlen;
+            v.ptr = b->dev.ptr + b->off[i];
+            v.col = b->dev.col;
+            v.val64 = b->dev.val64;
+            v.val32 = b->dev.val32;
+            std::vector<double> th, rs;
+            FD_TRY(lanczos_impl(v, b->off[i], kNormSteps, kNormSeed, th, rs, s));
+            nrm[i] = std::max(std::fabs(th.front()), std::fabs(th.back()));
+        }
+        b->lz_norm = nrm;
+    }
     for (int i = 0; i < n; i++) {
         const double lo = b->lam_lo[i], hi = b->lam_hi[i];
         alpha[i] = 2.0 / (hi - lo);
         beta[i] = -(hi + lo) / (hi - lo);
-        normH[i] = std::max(std::fabs(lo), std::fabs(hi));
+        normH[i] = b->lz_norm[i];
         deg[i] = P[i].degree;
         FD_TRY(set_coeffs(i, P[i].tau_lo, P[i].tau_hi));
     }
@@ -1408,7 +1601,7 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
                 for (int i = 0; i < n; i++) mk_h[i] = !done[i] && !failed[i];
                 FD_HIP(hipMemcpy(Mkd, mk_h.data(), n * 4, hipMemcpyHostToDevice));
                 FD_TRY(seg_gram(b->dev, ns, Vd, Vd, ns, Mkd, Pd, Gd, s));
-                FD_TRY(batched_cholinv(n, ns, Gd, Qd, Okd, Mkd, s));
+                FD_TRY(batched_cholinv(n, ns, Gd, Qd, Okd, Mkd, pass == 1, s));
                 FD_HIP(hipMemcpyAsync(ok_h.data(), Okd, n * 4, hipMemcpyDeviceToHost, s));
                 FD_HIP(hipStreamSynchronize(s));
                 for (int i = 0; i < n; i++)

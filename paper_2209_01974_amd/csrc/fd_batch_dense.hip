@@ -154,18 +154,35 @@ __global__ void k_sym_b(int n_inst, int n, double *G) {
 }
 
 // G = R^t R (R upper), then Q = R^-1, per instance; ok[i] = 0 if a pivot
-// is not positive.
+// falls to 1e-14 n of its own diagonal entry or below, or (near_identity,
+// the second CholQR pass) if an entry of G is more than 0.5 from the
+// identity.
 __global__ __launch_bounds__(256) void k_cholinv_b(int n, double *__restrict__ Gall, double *__restrict__ Qall,
-                                                   int32_t *__restrict__ ok, const int32_t *__restrict__ mask) {
+                                                   int32_t *__restrict__ ok, const int32_t *__restrict__ mask,
+                                                   int near_identity) {
     const int i = blockIdx.x;
     if (mask && !mask[i]) return;
     double *G = Gall + (int64_t)i * n * n, *Q = Qall + (int64_t)i * n * n;
     __shared__ int good;
+    __shared__ double d0[NMAX];
     if (threadIdx.x == 0) good = 1;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) d0[k] = G[k * n + k];
     __syncthreads();
+    if (near_identity) {
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const double dev = G[e] - ((e / n == e % n) ? 1.0 : 0.0);
+            if (!(fabs(dev) <= 0.5)) good = 0;
+        }
+        __syncthreads();
+        if (!good) {
+            if (threadIdx.x == 0) ok[i] = 0;
+            return;
+        }
+    }
+    const double rel = 1e-14 * (double)n;
     for (int k = 0; k < n; k++) {
         const double piv = G[k * n + k];
-        if (!(piv > 0.0)) {
+        if (!(piv > rel * d0[k])) {
             if (threadIdx.x == 0) good = 0;
             break;
         }
@@ -424,9 +441,10 @@ fd_status batched_sym(int n_inst, int n, double *G, hipStream_t s) {
     return FD_OK;
 }
 
-fd_status batched_cholinv(int n_inst, int n, double *G, double *Q, int32_t *ok, const int32_t *mask, hipStream_t s) {
+fd_status batched_cholinv(int n_inst, int n, double *G, double *Q, int32_t *ok, const int32_t *mask,
+                          bool second_pass, hipStream_t s) {
     if (n < 1 || n > NMAX) return fail(FD_ERR_INVALID, "batched Cholesky: n must be in [1, 64]");
-    hipLaunchKernelGGL(k_cholinv_b, dim3(n_inst), dim3(256), 0, s, n, G, Q, ok, mask);
+    hipLaunchKernelGGL(k_cholinv_b, dim3(n_inst), dim3(256), 0, s, n, G, Q, ok, mask, second_pass ? 1 : 0);
     FD_HIP(hipGetLastError());
     return FD_OK;
 }

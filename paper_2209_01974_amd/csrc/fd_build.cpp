@@ -116,18 +116,115 @@ void species_hops(int L, int N, bool periodic, double t, std::vector<uint64_t> &
     }
 }
 
+// Breadth-first labels of the hop graph of one species (reverse
+// Cuthill-McKee): a pseudo-peripheral start (repeated breadth-first sweeps
+// from the farthest, least-connected configuration), neighbours visited by
+// increasing degree and then rank, the visiting order reversed.  Configurations
+// one hop apart then get nearby labels, so that the rows a hop connects are
+// close in memory.  Disconnected parts are taken in rank order.  Returns
+// lab[rank] = label.
+std::vector<uint32_t> bfs_labels(const std::vector<uint32_t> &off, const std::vector<Hop> &hops) {
+    const int64_t n = (int64_t)off.size() - 1;
+    auto deg = [&](int64_t k) { return off[k + 1] - off[k]; };
+    std::vector<int64_t> level(n, -1), order;
+    order.reserve(n);
+    // one sweep from `start` over its component; returns the last level
+    auto sweep = [&](int64_t start, std::vector<int64_t> &out) {
+        out.clear();
+        out.push_back(start);
+        level[start] = 0;
+        std::vector<std::pair<uint32_t, uint32_t>> nb;
+        for (size_t h = 0; h < out.size(); h++) {
+            const int64_t k = out[h];
+            nb.clear();
+            for (uint32_t j = off[k]; j < off[k + 1]; j++)
+                if (level[hops[j].rank] < 0) nb.push_back({deg(hops[j].rank), hops[j].rank});
+            std::sort(nb.begin(), nb.end());
+            for (auto &e : nb)
+                if (level[e.second] < 0) {
+                    level[e.second] = level[k] + 1;
+                    out.push_back(e.second);
+                }
+        }
+        return level[out.back()];
+    };
+    std::vector<int64_t> comp;
+    for (int64_t s0 = 0; s0 < n; s0++) {
+        if (level[s0] >= 0) continue;
+        int64_t start = s0;
+        int64_t ecc = sweep(start, comp);
+        for (int round = 0; round < 4; round++) {
+            // least-connected configuration of the last level
+            int64_t cand = comp.back();
+            for (int64_t k : comp)
+                if (level[k] == ecc && (deg(k) < deg(cand) || (deg(k) == deg(cand) && k < cand))) cand = k;
+            for (int64_t k : comp) level[k] = -1;
+            const int64_t e2 = sweep(cand, comp);
+            if (e2 <= ecc) {
+                if (e2 < ecc) {  // keep the earlier start
+                    for (int64_t k : comp) level[k] = -1;
+                    sweep(start, comp);
+                }
+                break;
+            }
+            start = cand;
+            ecc = e2;
+        }
+        order.insert(order.end(), comp.begin(), comp.end());
+    }
+    std::vector<uint32_t> lab(n);
+    for (int64_t i = 0; i < n; i++) lab[order[i]] = (uint32_t)(n - 1 - i);
+    return lab;
+}
+
+// Species tables in label order: masks[label], hops of each label with their
+// targets as labels, sorted by label.
+void relabel_species(const std::vector<uint32_t> &lab, std::vector<uint64_t> &masks, std::vector<uint32_t> &off,
+                     std::vector<Hop> &hops) {
+    const int64_t n = (int64_t)masks.size();
+    std::vector<int64_t> inv(n);
+    for (int64_t k = 0; k < n; k++) inv[lab[k]] = k;
+    std::vector<uint64_t> m2(n);
+    std::vector<uint32_t> o2(n + 1, 0);
+    std::vector<Hop> h2;
+    h2.reserve(hops.size());
+    for (int64_t l = 0; l < n; l++) {
+        const int64_t k = inv[l];
+        m2[l] = masks[k];
+        const size_t b = h2.size();
+        for (uint32_t j = off[k]; j < off[k + 1]; j++) h2.push_back({lab[hops[j].rank], hops[j].el});
+        std::sort(h2.begin() + b, h2.end(), [](const Hop &x, const Hop &y) { return x.rank < y.rank; });
+        o2[l + 1] = (uint32_t)h2.size();
+    }
+    masks.swap(m2);
+    off.swap(o2);
+    hops.swap(h2);
+}
+
+// One species: configurations, hop lists, in the requested label order
+// (0 rank order, 1 breadth-first).
+void species(int L, int N, bool periodic, double t, int order, std::vector<uint64_t> &masks,
+             std::vector<uint32_t> &off, std::vector<Hop> &hops) {
+    species_hops(L, N, periodic, t, masks, off, hops);
+    if (order == 1) relabel_species(bfs_labels(off, hops), masks, off, hops);
+}
+
 }  // namespace
 
-fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, HostCSR &A) {
+fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, int order, HostCSR &A,
+                        std::vector<uint64_t> &cfg_up, std::vector<uint64_t> &cfg_dn) {
     if (L < 3 || L > 62 || nup < 0 || nup > L || ndn < 0 || ndn > L)
         return fail(FD_ERR_INVALID, "Hubbard: need 3 <= L <= 62 and 0 <= n_up, n_dn <= L");
+    if (order != 0 && order != 1) return fail(FD_ERR_INVALID, "Hubbard: config_order must be 0 or 1");
     uint64_t nu = binom().c[L][nup], nd = binom().c[L][ndn];
     if (nu * nd >= (1ULL << 32)) return fail(FD_ERR_UNSUPPORTED, "Hubbard: D >= 2^32");
     std::vector<uint64_t> mu, md;
     std::vector<uint32_t> ou, od;
     std::vector<Hop> hu, hd;
-    species_hops(L, nup, periodic, t, mu, ou, hu);
-    species_hops(L, ndn, periodic, t, md, od, hd);
+    species(L, nup, periodic, t, order, mu, ou, hu);
+    species(L, ndn, periodic, t, order, md, od, hd);
+    cfg_up = mu;
+    cfg_dn = md;
     int64_t D = (int64_t)(nu * nd);
     A.D = D;
     try {
@@ -185,15 +282,16 @@ fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double
     return FD_OK;
 }
 
-fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, HubbardTables &T) {
+fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, int order, HubbardTables &T) {
     if (L < 3 || L > 62 || nup < 0 || nup > L || ndn < 0 || ndn > L)
         return fail(FD_ERR_INVALID, "Hubbard: need 3 <= L <= 62 and 0 <= n_up, n_dn <= L");
+    if (order != 0 && order != 1) return fail(FD_ERR_INVALID, "Hubbard: config_order must be 0 or 1");
     if ((uint64_t)binom().c[L][nup] * binom().c[L][ndn] >= (1ULL << 32))
         return fail(FD_ERR_UNSUPPORTED, "Hubbard: D >= 2^32");
     std::vector<uint32_t> ou, od;
     std::vector<Hop> hu, hd;
-    species_hops(L, nup, periodic, t, T.mu, ou, hu);
-    species_hops(L, ndn, periodic, t, T.md, od, hd);
+    species(L, nup, periodic, t, order, T.mu, ou, hu);
+    species(L, ndn, periodic, t, order, T.md, od, hd);
     T.nu = (int64_t)T.mu.size();
     T.nd = (int64_t)T.md.size();
     T.U = U;

@@ -774,13 +774,33 @@ __global__ void k_svqb_q(int n, const double *d, const double *lam, const double
 }
 
 // G = R^t R (R upper), then Q = R^-1; ok = 0 if a pivot is not positive
-__global__ __launch_bounds__(1024) void k_cholinv(int n, double *G, double *Q, int *ok) {
+// Cholesky G = R^t R (upper R in place) and Q = R^-1.  *ok = 0 when a pivot
+// falls to 1e-14 n of the matrix's own diagonal entry or below (the block is
+// numerically rank deficient: its Gram matrix carries no information in
+// that direction, and CholQR would return a non-orthonormal block), or, with
+// near_identity set (the second pass of CholQR2), when some entry of G is
+// more than 0.5 away from the identity (the first pass has already failed).
+__global__ __launch_bounds__(1024) void k_cholinv(int n, double *G, double *Q, int *ok, int near_identity) {
     __shared__ int good;
+    __shared__ double d0[512];
     if (threadIdx.x == 0) good = 1;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) d0[k] = G[k * n + k];
     __syncthreads();
+    if (near_identity) {
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const double dev = G[e] - ((e / n == e % n) ? 1.0 : 0.0);
+            if (!(fabs(dev) <= 0.5)) good = 0;
+        }
+        __syncthreads();
+        if (!good) {
+            if (threadIdx.x == 0) *ok = 0;
+            return;
+        }
+    }
+    const double rel = 1e-14 * (double)n;
     for (int k = 0; k < n; k++) {
         const double piv = G[k * n + k];
-        if (!(piv > 0.0)) {
+        if (!(piv > rel * d0[k])) {
             if (threadIdx.x == 0) good = 0;
             break;
         }
@@ -829,8 +849,9 @@ fd_status svqb_transform(int n, double *G, double *Q, double *work, int *keep, i
     return FD_OK;
 }
 
-fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, hipStream_t s) {
-    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), 0, s, n, G, Q, ok_dev);
+fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, bool second_pass, hipStream_t s) {
+    if (n > 512) return fail(FD_ERR_INVALID, "CholQR: n > 512");
+    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), 0, s, n, G, Q, ok_dev, second_pass ? 1 : 0);
     FD_HIP(hipGetLastError());
     return FD_OK;
 }
@@ -923,6 +944,94 @@ fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double 
 
 fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_block, dim3((unsigned)((D * n + 255) / 256)), dim3(256), 0, s, D, n, src, lds, dst, ldd);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+// ------------------------------------------------------------- Lanczos ----
+// Vectors of the Lanczos basis are stored one after another (vector t at
+// Q + t * D, each contiguous), so the SpMV on one of them and the
+// projections below read whole rows of memory.
+namespace {
+// P[t * nblk + b] = sum over rows of block b of Q_t[i] w[i], t = blockIdx.y
+__global__ __launch_bounds__(256) void k_lz_proj(int64_t D, const double *__restrict__ Q,
+                                                 const double *__restrict__ w, int64_t rpb, double *__restrict__ P) {
+    const int t = blockIdx.y;
+    const double *q = Q + (int64_t)t * D;
+    const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = min(D, r0 + rpb);
+    double acc = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) acc += q[r] * w[r];
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P[(int64_t)t * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_lz_final(int nblk, int n, const double *__restrict__ P, double *__restrict__ c) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; b++) acc += P[(int64_t)t * nblk + b];
+    c[t] = acc;
+}
+
+// w[i] -= sum_t Q_t[i] c[t]
+__global__ __launch_bounds__(256) void k_lz_sub(int64_t D, int n, const double *__restrict__ Q,
+                                                const double *__restrict__ c, double *__restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= D) return;
+    double acc = 0.0;
+    for (int t = 0; t < n; t++) acc = fma(Q[(int64_t)t * D + i], c[t], acc);
+    w[i] -= acc;
+}
+
+__global__ __launch_bounds__(256) void k_lz_scale(int64_t D, double *__restrict__ w, double f) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < D) w[i] *= f;
+}
+
+// u_i = 2 U_i - 1, U_i the i-th output (from 0) of SplitMix64(seed)
+__device__ __forceinline__ uint64_t lz_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(256) void k_lz_start(int64_t D, double *__restrict__ q, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= D) return;
+    const uint64_t z = lz_mix(seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL);
+    q[i] = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+}  // namespace
+
+fd_status lz_dots(int64_t D, int n, const double *Q, const double *w, double *c, double *P, int nblk,
+                  hipStream_t s) {
+    const int64_t rpb = (D + nblk - 1) / nblk;
+    hipLaunchKernelGGL(k_lz_proj, dim3((unsigned)nblk, (unsigned)n), dim3(256), 0, s, D, Q, w, rpb, P);
+    FD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lz_final, dim3((n + 63) / 64), dim3(64), 0, s, nblk, n, P, c);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status lz_sub(int64_t D, int n, const double *Q, const double *c, double *w, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_sub, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, D, n, Q, c, w);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status lz_scale(int64_t D, double *w, double f, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_scale, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, D, w, f);
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
+fd_status lz_start(int64_t D, double *q, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_start, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, D, q, seed);
     FD_HIP(hipGetLastError());
     return FD_OK;
 }
@@ -1039,10 +1148,21 @@ __global__ __launch_bounds__(256) void k_stream(int op, int64_t n2, const d2v *_
                                                 const d2v *__restrict__ b, d2v *__restrict__ c, double sc) {
     const int64_t stride = (int64_t)gridDim.x * 256 * 4;
     int64_t i = (int64_t)blockIdx.x * 256 * 4 + threadIdx.x;
+    d2v acc = (d2v)0;
     for (; i + 3 * 256 < n2; i += stride) {
         d2v r[4];
+        if (op == 3) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) __builtin_nontemporal_store((d2v)sc, c + i + u * 256);
+            continue;
+        }
 #pragma unroll
         for (int u = 0; u < 4; u++) r[u] = __builtin_nontemporal_load(a + i + u * 256);
+        if (op == 2) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc += r[u];
+            continue;
+        }
         if (op == 1) {
 #pragma unroll
             for (int u = 0; u < 4; u++) r[u] += sc * __builtin_nontemporal_load(b + i + u * 256);
@@ -1051,20 +1171,32 @@ __global__ __launch_bounds__(256) void k_stream(int op, int64_t n2, const d2v *_
         for (int u = 0; u < 4; u++) __builtin_nontemporal_store(r[u], c + i + u * 256);
     }
     for (; i < n2; i += 256) {  // tail: the remaining elements of this block's last tile
+        if (op == 3) {
+            __builtin_nontemporal_store((d2v)sc, c + i);
+            continue;
+        }
         d2v r = __builtin_nontemporal_load(a + i);
+        if (op == 2) {
+            acc += r;
+            continue;
+        }
         if (op == 1) r += sc * __builtin_nontemporal_load(b + i);
         __builtin_nontemporal_store(r, c + i);
     }
+    // read-only pass: one partial sum per thread, so that the loads stay live
+    if (op == 2) c[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc;
 }
 
 }  // namespace
 
 fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s) {
-    if (n < 2 || (n & 1) || (op != 0 && op != 1) || !a || !c || (op == 1 && !b) ||
+    if (n < 2 || (n & 1) || op < 0 || op > 3 || !c || (op != 3 && !a) || (op == 1 && !b) ||
         ((uintptr_t)a | (uintptr_t)c | (uintptr_t)b) % 16)
-        return fail(FD_ERR_INVALID, "stream: need even n, 16-byte aligned arrays, op 0 or 1");
+        return fail(FD_ERR_INVALID, "stream: need even n, 16-byte aligned arrays, op 0..3");
     const int64_t n2 = n / 2;
     const int64_t g = std::max<int64_t>(1, std::min<int64_t>((n2 + 1023) / 1024, 16384));
+    // the read-only pass writes one partial sum (16 bytes) per thread into c
+    if (op == 2 && g * 256 > n2) return fail(FD_ERR_INVALID, "stream: read-only pass needs n >= 2^19");
     hipLaunchKernelGGL(k_stream, dim3((unsigned)g), dim3(256), 0, s, op, n2, (const d2v *)a, (const d2v *)b,
                        (d2v *)c, sc);
     FD_HIP(hipGetLastError());

@@ -44,7 +44,11 @@ struct HostSELL {
     std::vector<double> val;
 };
 
-fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, HostCSR &A);
+// order 0: spin configurations labelled by rank; 1: breadth-first labels of
+// each species' hop graph (reverse Cuthill-McKee).  cfg_up / cfg_dn receive
+// the configuration (bit mask) of each label; row (a, b) = a n_dn + b.
+fd_status build_hubbard(int L, int nup, int ndn, bool periodic, double t, double U, int order, HostCSR &A,
+                        std::vector<uint64_t> &cfg_up, std::vector<uint64_t> &cfg_dn);
 
 // Tensor-product form of the Hubbard ring: H = H_up x I + I x H_dn + U D.
 // Per spin species, the configurations one hop away (rank, element), sorted.
@@ -56,7 +60,7 @@ struct HubbardTables {
     std::vector<int32_t> idx_u, idx_d;      // hop targets (ranks)
     std::vector<double> val_u, val_d;       // hop elements
 };
-fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, HubbardTables &T);
+fd_status hubbard_tables(int L, int nup, int ndn, bool periodic, double t, double U, int order, HubbardTables &T);
 int64_t hubbard_tables_nnz(const HubbardTables &T);  // non-zeros of the full matrix
 void hubbard_tables_gershgorin(const HubbardTables &T, double &lo, double &hi);
 fd_status build_anderson(int L, double t, double W, uint64_t seed, int64_t skip, HostCSR &A);
@@ -125,8 +129,10 @@ struct fd_matrix_s {
     fd::HostCSR csr;
     fd::HostSELL sell;
     fd::HubbardTables hub;
+    std::vector<uint64_t> cfg_up, cfg_dn;  // Hubbard: spin configuration of each label
     int64_t D = 0, nnz = 0, stored = 0;
     double lam_lo = 0, lam_hi = 0;
+    double lz_norm = -1.0;  // ||H|| estimate of the convergence test (lazily, by Lanczos)
     int device = -1;
     fd::DevMatrix dev;
 };
@@ -190,7 +196,9 @@ fd_status seg_rotate(const BatchDev &B, int n, double *X, int64_t ld, const doub
 fd_status seg_resid(const BatchDev &B, int n, const double *V, const double *W, int64_t ld, const double *theta,
                     const int32_t *mask, double *P, double *rho, hipStream_t s);
 fd_status batched_sym(int n_inst, int n, double *G, hipStream_t s);
-fd_status batched_cholinv(int n_inst, int n, double *G, double *Q, int32_t *ok, const int32_t *mask, hipStream_t s);
+// as cholqr_transform, one matrix per instance (mask[i] = 0: skipped)
+fd_status batched_cholinv(int n_inst, int n, double *G, double *Q, int32_t *ok, const int32_t *mask,
+                          bool second_pass, hipStream_t s);
 fd_status batched_syev(int n_inst, int n, const double *S, double *w, double *U, const int32_t *mask, hipStream_t s);
 // SVQB transform Q of each instance from its Gram matrix G (overwritten);
 // rank[i]: directions above the clipping floor.  d: n_inst x n, lam: n_inst x n.
@@ -224,7 +232,10 @@ fd_status col_resid(int64_t D, int n, const double *V, const double *W, int64_t 
 // the rank in *rank_dev (device int) and a keep-mask (device int[n]).
 fd_status svqb_transform(int n, double *G, double *Q, double *work, int *keep, int *rank_dev,
                          hipStream_t s);
-fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, hipStream_t s);
+// CholQR transform Q = R^-1 from the Gram matrix (overwritten); *ok_dev = 0
+// on a relative pivot below 1e-14 n, or (second_pass) when G is not within
+// 0.5 of the identity entrywise.
+fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, bool second_pass, hipStream_t s);
 fd_status refill_random(int64_t D, int n, double *V, int64_t ldv, const int *keep,
                         uint64_t seed, hipStream_t s);
 fd_status fill_normal(int64_t D, int n, double *V, int64_t ldv, uint64_t seed, hipStream_t s);
@@ -245,6 +256,15 @@ fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *d
 fd_status copy_rows(int64_t D, int64_t row_bytes, const void *src, int64_t src_ld_bytes, void *dst,
                     int64_t dst_ld_bytes, hipStream_t s);
 fd_status stream_op(int op, int64_t n, const double *a, const double *b, double *c, double sc, hipStream_t s);
+// Lanczos building blocks; the basis vectors lie one after another (vector t
+// at Q + t D).  c[t] = Q_t . w for t < n (two-stage, nblk partial sums in P,
+// fixed summation order); w -= sum_t c[t] Q_t; w *= f; q = the seeded start
+// vector (2 U_i - 1, U_i the i-th uniform of SplitMix64(seed)).
+fd_status lz_dots(int64_t D, int n, const double *Q, const double *w, double *c, double *P, int nblk,
+                  hipStream_t s);
+fd_status lz_sub(int64_t D, int n, const double *Q, const double *c, double *w, hipStream_t s);
+fd_status lz_scale(int64_t D, double *w, double f, hipStream_t s);
+fd_status lz_start(int64_t D, double *q, uint64_t seed, hipStream_t s);
 
 // Degree-picker network (fd_mlp.hip).
 fd_status mlp_forward(const float *P, int B, const float *X, float *out, hipStream_t s);

@@ -4,7 +4,7 @@
 // vectors at once, vectors row-major so that one row of the block (n_b
 // values) is contiguous; each matrix entry is loaded once per n_b vectors.
 // Alg. 2 caption: the SpMV and the vector updates of the Chebyshev step are
-// one kernel, so that W2 is not reloaded (kappa = 5 in Sec. 3.3).
+// one kernel, so that W2 is not reloaded (kappa = 5 in Sec. 3.2, Eq. EstimateT).
 //
 // Mapping on a 64-wide wavefront: a row of the block (nb values) is split
 // over G lanes that each own VEC consecutive values (16-byte loads when the

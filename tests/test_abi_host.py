@@ -241,3 +241,48 @@ def test_pencil_order_is_the_csr_in_a_lattice_walk():
         assert np.array_equal(val[cptr[r]:cptr[r + 1]], A.val[a:b])
     with pytest.raises(fd.FDError):
         fd.build_matrix("hubbard", fmt="pencil", host_only=True, L=6, n_up=3, n_dn=3)
+
+
+@pytest.mark.parametrize("L,nu,nd,U,per", [(8, 4, 4, 4.0, True), (7, 2, 3, 2.5, True), (8, 4, 3, 1.0, False)])
+def test_hubbard_rcm_labels_are_a_relabeling(L, nu, nd, U, per):
+    """config_order 1: the library's matrix is P A P^T of the oracle's ranked
+    one, bit for bit, with P read from the exported configurations (each
+    label's spin configuration, mapped to its oracle rank); and labels one
+    hop apart are close (the bandwidth of a species' hop graph shrinks)."""
+    import math
+    m = fd.build_matrix("hubbard", host_only=True, L=L, n_up=nu, n_dn=nd, t=1.0, U=U, periodic=per,
+                        config_order=1)
+    cu, cd = math.comb(L, nu), math.comb(L, nd)
+    up, dn = m.export_configs(cu, cd)
+    rank_u = {x: i for i, x in enumerate(x for x in range(1 << L) if bin(x).count("1") == nu)}
+    rank_d = {x: i for i, x in enumerate(x for x in range(1 << L) if bin(x).count("1") == nd)}
+    pu = np.array([rank_u[int(x)] for x in up])
+    pd = np.array([rank_d[int(x)] for x in dn])
+    assert sorted(pu) == list(range(cu)) and sorted(pd) == list(range(cd))
+    P = (pu[:, None] * cd + pd[None, :]).ravel()  # label row -> oracle row
+    A = O.hubbard(L, nu, nd, 1.0, U, per)
+    rowptr, col, val = m.export_csr()
+    Ad = A.dense()
+    import scipy.sparse as sp
+    Ml = sp.csr_matrix((val, col, rowptr), shape=(m.D, m.D)).toarray()
+    assert np.array_equal(Ml.view(np.uint64), Ad[np.ix_(P, P)].view(np.uint64))
+    # canonical CSR: ascending columns, diagonal stored
+    for i in range(m.D):
+        c = col[rowptr[i]:rowptr[i + 1]]
+        assert np.all(np.diff(c.astype(np.int64)) > 0) and i in c
+    # the ranked basis exports its configurations in rank order
+    m0 = fd.build_matrix("hubbard", host_only=True, L=L, n_up=nu, n_dn=nd, t=1.0, U=U, periodic=per)
+    up0, dn0 = m0.export_configs(cu, cd)
+    assert [rank_u[int(x)] for x in up0] == list(range(cu))
+
+
+def test_hubbard14_rcm_labels_shrink_up_hop_distance():
+    """Hubbard L=14 (7+7): in the ranked basis an up hop moves up to 1,912
+    slabs of 3,432 rows; with reverse Cuthill-McKee labels at most 369."""
+    for order, bound in ((0, 1912), (1, 369)):
+        m = fd.build_matrix("hubbard", host_only=True, L=14, n_up=7, n_dn=7, t=1.0, U=8.0, config_order=order)
+        rowptr, col, _ = m.export_csr()
+        rows = np.repeat(np.arange(m.D, dtype=np.int64), np.diff(rowptr))
+        assert (np.abs(col.astype(np.int64) - rows) // 3432).max() == bound
+        del rowptr, col, rows
+        m.free()

@@ -1,0 +1,73 @@
+"""Failure paths of fd_solve and fd_orthog, forced from the host (every kernel
+still runs to its end): non-finite input -> FD_ERR_BREAKDOWN, a device
+allocation that fails -> FD_ERR_OOM with nothing written, a filter that
+cannot converge -> the stagnation stop before max_iter, and an
+ill-conditioned block under CholQR2 -> the SVQB2 fallback still returns an
+orthonormal block."""
+import numpy as np
+import pytest
+
+from fd_inputs import start_block
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2209_01974_amd as fd  # noqa: E402
+
+
+def hub8():
+    return fd.build_matrix("hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0)
+
+
+def test_nan_in_start_block_is_a_breakdown():
+    m = hub8()
+    V0 = start_block(m.D, 64, 0)
+    V0[123, 7] = np.nan
+    with pytest.raises(fd.FDError) as e:
+        fd.solve(m, -0.5, 0.5, 8, 64, 16, 60, max_iter=10, V0=V0)
+    assert e.value.status == fd.FD_ERR_BREAKDOWN
+
+
+def test_allocation_failure_is_reported_and_recoverable():
+    m = hub8()
+    V0 = start_block(m.D, 64, 0)
+    fd.debug_alloc_limit(1 << 20)  # the 4900 x 64 search block needs 2.5 MB
+    try:
+        with pytest.raises(fd.FDError) as e:
+            fd.solve(m, -0.5, 0.5, 8, 64, 16, 60, max_iter=10, V0=V0)
+        assert e.value.status == fd.FD_ERR_OOM
+    finally:
+        fd.debug_alloc_limit(0)
+    r = fd.solve(m, -0.5, 0.5, 8, 64, 16, 60, max_iter=60, V0=V0)
+    assert r.status == fd.FD_OK
+    with pytest.raises(fd.FDError) as e:
+        fd.debug_alloc_limit(-1)
+    assert e.value.status == fd.FD_ERR_INVALID
+
+
+def test_stagnation_stops_before_max_iter():
+    """1000 equidistant eigenvalues, fixed filter window [-0.5, 0.5] (500 of
+    them pass the filter alike) and N_s = 20: FD cannot converge (Fig. 2:
+    the search interval holds far more than N_s eigenvalues); the solver
+    stops once the residual stops falling, long before max_iter."""
+    lam = -1 + 2 * np.arange(1000) / 999
+    m = fd.build_matrix("diagonal", diag=lam)
+    r = fd.solve(m, -0.5, 0.5, 10, 20, 4, 60, max_iter=500, tol=1e-9, V0=start_block(1000, 20, 0))
+    assert r.status == fd.FD_ERR_NOT_CONVERGED
+    assert 10 <= r.stats["iters"] < 200
+
+
+def test_cholqr2_falls_back_on_an_ill_conditioned_block():
+    """kappa(V) = 1e10: Cholesky of V^t V (kappa 1e20) loses the small
+    directions; the relative pivot test and the near-identity test of the
+    second pass send the block to SVQB2, which returns it orthonormal with
+    the same span (up to the conditioning)."""
+    D, ns = 6000, 48
+    U, _ = np.linalg.qr(start_block(D, ns, 3))
+    V = U @ np.diag(np.logspace(0, -10, ns)) @ np.linalg.qr(start_block(ns, ns, 4))[0]
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    fd.orthog(Vd, fd.FD_ORTHO_CHOLQR2, seed=3)
+    Q = Vd.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(ns)).max() <= 1e-13
+    # the well-conditioned part of the span is kept
+    assert np.linalg.norm(U[:, :20] - Q @ (Q.T @ U[:, :20])) <= 1e-6

@@ -480,3 +480,48 @@ def test_solve_full_search_space():
     assert r.status == fd.FD_OK and r.stats["iters"] == 0
     want = np.sort(d[np.argsort(np.abs(d), kind="stable")[:4]])
     assert np.abs(r.evals - want).max() <= 1e-13
+
+
+# --------------------------------------------------------------- Lanczos ----
+@pytest.mark.parametrize("name,k", [("hub8", 40), ("and8", 40), ("diag", 60), ("hub6", 7)])
+def test_lanczos_matches_oracle(name, k):
+    """fd_lanczos against the oracle's Lanczos (same seeded start vector,
+    full reorthogonalization): same number of steps, Ritz values within
+    1e-10 ||H||, residual bounds within 1e-10 ||H|| (absolute)."""
+    if name == "hub8":
+        A, m = O.hubbard(8, 4, 4, 1.0, 4.0), fd.build_matrix("hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0)
+    elif name == "hub6":
+        A, m = O.hubbard(6, 3, 3, 1.0, 4.0), fd.build_matrix("hubbard", L=6, n_up=3, n_dn=3, t=1.0, U=4.0)
+    elif name == "and8":
+        A, m = O.anderson(8, 1.0, 8.0, 4), fd.build_matrix("anderson", L=8, t=1.0, W=8.0, seed=4)
+    else:
+        d = np.linspace(-2.0, 3.0, 45)
+        A, m = O.diagonal(d), fd.build_matrix("diagonal", diag=d)
+    th, rs = fd.lanczos(m, k, 1)
+    tho, rso, steps = O.lanczos(A, k, 1)
+    assert th.size == steps
+    normH = max(abs(tho[0]), abs(tho[-1]))
+    assert np.abs(th - tho).max() <= 1e-10 * normH
+    assert np.abs(rs - rso).max() <= 1e-10 * normH
+
+
+def test_solve_uses_lanczos_norm_and_interval():
+    """fd_solve's ||H|| is the 40-step Lanczos estimate (the oracle's), a
+    lower bound of ||H||_2; with interval = 30 the Lanczos interval scales the
+    filter and the result still matches dense diagonalization."""
+    A = O.hubbard(8, 4, 4, 1.0, 4.0)
+    lam = np.linalg.eigvalsh(A.dense())
+    m = fd.build_matrix("hubbard", L=8, n_up=4, n_dn=4, t=1.0, U=4.0)
+    V0 = start_block(A.D, 128, 0)
+    inside = lam[(lam >= -0.5) & (lam <= 0.5)]
+    want = np.sort(inside[np.argsort(np.abs(inside), kind="stable")[:16]])
+    for interval in (0, 30):
+        r = fd.solve(m, -0.5, 0.5, 16, 128, 16, 100, max_iter=80, tol=1e-9, V0=V0, interval=interval)
+        assert r.status == fd.FD_OK, r.stats
+        normH = r.stats["norm_H"]
+        assert abs(normH - O.lanczos_norm(A)) <= 1e-12 * normH
+        assert normH <= max(abs(lam[0]), abs(lam[-1]))
+        assert np.abs(r.evals - want).max() <= 1e-10 * normH
+        assert r.resid.max() <= 1e-9 * normH
+        ro = O.fd_solve(A, V0, -0.5, 0.5, 16, 100, 1e-9, max_iter=80, interval=interval)
+        assert ro.converged and np.abs(ro.evals - r.evals).max() <= 1e-10 * normH

@@ -99,7 +99,7 @@ def test_fig2_diagonal_search_interval():
         if ok:
             np.testing.assert_allclose(r.evals, lam[(lam >= -0.01) & (lam <= 0.01)], atol=1e-12)
         else:
-            assert r.status == fd.FD_ERR_NOT_CONVERGED and r.stats["iters"] == 20
+            assert r.status == fd.FD_ERR_NOT_CONVERGED and r.stats["iters"] <= 20
 
 
 def test_library_start_block_and_determinism():

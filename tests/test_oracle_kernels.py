@@ -296,3 +296,56 @@ def test_fd_lehmann_window_hubbard8_vs_dense():
     inside = ev[(ev >= -0.5) & (ev <= 0.5)]
     want = np.sort(inside[np.argsort(np.abs(inside), kind="stable")[:16]])
     assert np.abs(r.evals - want).max() <= 1e-10 * r.norm_H
+
+
+# --------------------------------------------------------------- Lanczos ----
+def test_lanczos_exact_when_krylov_space_is_whole():
+    """D <= k: the Krylov space is the whole space, so the Ritz values are the
+    eigenvalues (distinct diagonal) and the residual bounds vanish."""
+    d = np.linspace(-3.0, 5.0, 23) ** 3 / 10.0
+    A = O.diagonal(d)
+    th, rs, steps = O.lanczos(A, 40, 1)
+    assert steps == 23
+    np.testing.assert_allclose(th, np.sort(d), rtol=0, atol=1e-12)
+    assert rs.max() <= 1e-10
+
+
+def test_lanczos_stops_at_an_invariant_subspace():
+    """Three distinct levels: the start vector lies in a 3-dimensional
+    invariant subspace, so Lanczos stops after 3 steps with the 3 levels."""
+    d = np.repeat([-1.0, 0.5, 2.0], 7)
+    th, rs, steps = O.lanczos(O.diagonal(d), 40, 1)
+    assert steps == 3
+    np.testing.assert_allclose(th, [-1.0, 0.5, 2.0], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["hub8", "and8"])
+def test_lanczos_ritz_values_against_dense_spectrum(name):
+    """Cauchy interlacing: every Ritz value lies inside [lam_min, lam_max];
+    each Ritz value has an eigenvalue within its residual bound; the extreme
+    ones converge first (40 steps: within 1e-6 relative)."""
+    A = O.hubbard(8, 4, 4, 1.0, 4.0) if name == "hub8" else O.anderson(8, 1.0, 8.0, 4)
+    lam = np.linalg.eigvalsh(A.dense())
+    th, rs, steps = O.lanczos(A, 40, 1)
+    assert steps == 40
+    assert th.min() >= lam[0] - 1e-12 and th.max() <= lam[-1] + 1e-12
+    dist = np.abs(th[:, None] - lam[None, :]).min(axis=1)
+    assert np.all(dist <= rs + 1e-12)
+    normH = max(abs(lam[0]), abs(lam[-1]))
+    assert abs(th[0] - lam[0]) <= 1e-6 * normH and abs(th[-1] - lam[-1]) <= 1e-6 * normH
+    est = O.lanczos_norm(A)
+    assert est <= normH * (1 + 1e-14) and est >= normH * (1 - 1e-6)
+    lo, hi = O.lanczos_interval(A, 40)
+    assert lo <= lam[0] and hi >= lam[-1]
+
+
+def test_lanczos_norm_is_tighter_than_gershgorin():
+    """Hubbard L=8, U=4: the Gershgorin bound is 32 against ||H||_2 = 20.6;
+    the Lanczos estimate sits just below ||H||_2 (a lower bound; 40 steps
+    bring it within about 1e-8 here)."""
+    A = O.hubbard(8, 4, 4, 1.0, 4.0)
+    lam = np.linalg.eigvalsh(A.dense())
+    normH = max(abs(lam[0]), abs(lam[-1]))
+    assert max(abs(x) for x in O.gershgorin(A)) == 32.0
+    est = O.lanczos_norm(A)
+    assert est <= normH and normH - est <= 1e-6 * normH
