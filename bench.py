@@ -111,6 +111,8 @@ def fd_runs(args, fd, np):
     runs = [("hubbard8", dict(L=8, n_up=4, n_dn=4, U=4.0), -0.5, 0.5, 16, 128, 16, 100)]
     if not args.no_hub14:
         runs.append(("hubbard14", dict(L=14, n_up=7, n_dn=7, U=8.0), -1.0, 1.0, 64, 256, 32, 800))
+    # one line per FD iteration on stderr (the L=14 solves run for minutes)
+    os.environ["FD_TRACE"] = "1"
     for name, kw, lo, hi, nt, nsr, nbr, deg in runs:
         t0 = time.time()
         mh = fd.build_matrix("hubbard", fmt=args.hub_fmt, t=1.0, config_order=args.hub_order, **kw)
@@ -179,18 +181,14 @@ def batch_runs(args, fd, np, torch):
     def alg_bytes(nb):
         return sum(degree * (ns // nb) * (m.nnz * 12 + 4 * (m.D + 1) + 5 * m.D * nb * 8) for m in mats)
 
-    # nb picked by timing one application per candidate (graph captured on
-    # the first call of each shape)
+    # nb and the launch shape chosen by the library (fd_batch_autotune)
+    t = time.perf_counter()
+    nb, chunk, sh = fd.batch_autotune(b, "f64", 0)
+    t_tune = time.perf_counter() - t
+    log("batch autotune: nb %d, XCD chunk %d rows, entry loop %d (%.1fs)" % (nb, chunk, sh, t_tune))
     times = {}
-    for nb in (8, 16, 32, 64):
-        fd.batch_filter(b, V, mu, degs, alpha, beta, W1, W2, nb)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        fd.batch_filter(b, V, mu, degs, alpha, beta, W1, W2, nb)
-        torch.cuda.synchronize()
-        times[nb] = time.perf_counter() - t
-        V.div_(V.norm())
-    nb = min(times, key=times.get)
+    fd.batch_filter(b, V, mu, degs, alpha, beta, W1, W2, nb)  # graph capture
+    torch.cuda.synchronize()
     reps = 3
     t = time.perf_counter()
     for _ in range(reps):
@@ -205,13 +203,38 @@ def batch_runs(args, fd, np, torch):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t
     out["filter_full"] = {"instances": len(mats), "D_total": b.D, "n_search": ns, "degree": degree, "nb": nb,
-                          "nb_times_s": {str(k): round(v, 4) for k, v in times.items()},
+                          "autotuned": {"nb": nb, "chunk_rows": chunk, "entry_loop": sh, "tune_s": round(t_tune, 2)},
                           "batched_s": round(tb, 4), "sequential_s": round(ts, 4),
                           "batched_GBs": round(alg_bytes(nb) / tb / 1e9, 1),
                           "sequential_GBs": round(alg_bytes(nb) / ts / 1e9, 1),
                           "speedup": round(ts / tb, 2)}
     log("batch filter: %s" % out["filter_full"])
-    del V, W1, W2, b, mats
+    del V, W1, W2
+    torch.cuda.empty_cache()
+
+    # (1b) FD at the full sizes, as specified: 16 pairs nearest E = 0 per
+    # instance, the KPM rule's degree (capped), N_s = 64, nb chosen by the
+    # library, a few outer iterations; converged count and eigenpairs/s
+    nt = 16
+    t = time.perf_counter()
+    degs_full = [min(args.batch_max_degree, fd.pick_degree(m, 0.0, 0.0, nt, ns)[0]) for m in mats]
+    log("FD full size: KPM-rule degrees in [%d, %d] (cap %d), %.1fs"
+        % (min(degs_full), max(degs_full), args.batch_max_degree, time.perf_counter() - t))
+    params = [dict(tau_lo=0.0, tau_hi=0.0, n_target=nt, n_search=ns, nb=0, degree=d, max_iter=args.batch_full_iters,
+                   tol=1e-9, seed=2000 + i) for i, d in enumerate(degs_full)]
+    r = fd.solve_batch(b, params)
+    conv = [s_["iters"] <= args.batch_full_iters and s_["max_resid"] <= 1e-9 * s_["norm_H"] for s_ in r.stats]
+    tconv = sorted(s_["t_total"] for s_, c in zip(r.stats, conv) if c)
+    out["fd_full"] = {"instances": len(mats), "D_total": b.D, "n_target": nt, "n_search": ns,
+                      "nb": r.bstats["nb"], "degree_range": [min(degs_full), max(degs_full)],
+                      "max_iter": args.batch_full_iters, "converged": int(sum(conv)),
+                      "t_total_s": round(r.bstats["t_total"], 2),
+                      "eigenpairs_per_s": round(nt * sum(conv) / r.bstats["t_total"], 3),
+                      "p50_completion_s": round(float(np.percentile(tconv, 50)), 2) if tconv else None,
+                      "p99_completion_s": round(float(np.percentile(tconv, 99)), 2) if tconv else None,
+                      "max_resid_rel_median": float(np.median([s_["max_resid"] / s_["norm_H"] for s_ in r.stats]))}
+    log("FD full size: %s" % out["fd_full"])
+    del b, mats
     torch.cuda.empty_cache()
 
     # (2) FD on small instances drawn the same way, with both orthogonalizations
@@ -435,8 +458,9 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the FD eigenpairs/s runs")
     ap.add_argument("--no-hub14", action="store_true",
                     help="skip the FD runs on the Hubbard ring L=14 (the mixed-precision workload)")
-    ap.add_argument("--hub-order", type=int, choices=[0, 1], default=0,
-                    help="Hubbard basis labels of the FD runs: 0 ranked, 1 reverse Cuthill-McKee")
+    ap.add_argument("--hub-order", type=int, choices=[0, 1], default=1,
+                    help="Hubbard basis labels of the FD runs: 0 ranked, 1 reverse Cuthill-McKee (the same "
+                         "operator, P A P^T)")
     ap.add_argument("--site-compare", action="store_true",
                     help="also time a degree-20 filter with the tiled and the natural Anderson numbering")
     ap.add_argument("--fd-only", action="store_true", help="only the FD eigenpairs/s runs (no Anderson step)")
@@ -445,6 +469,10 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="only the batched workload (96 Anderson instances; filter and FD, batched vs one by one)")
     ap.add_argument("--batch-iters", type=int, default=80, help="max outer iterations per batched FD instance")
+    ap.add_argument("--batch-full-iters", type=int, default=3,
+                    help="outer iterations of the batched FD at the full instance sizes")
+    ap.add_argument("--batch-max-degree", type=int, default=12000,
+                    help="cap on the KPM-rule degree of the batched FD at the full instance sizes")
     ap.add_argument("--adapt", type=int, choices=[0, 1, 2], default=1,
                     help="filter window of the FD runs: 0 fixed, 1 tracked by the N_t-th Ritz value, "
                          "2 tracked by the Lehmann radius")
@@ -454,6 +482,10 @@ def main():
     ap.add_argument("--cpu-degree", type=int, default=6, help="filter degree of the CPU sample")
     ap.add_argument("--cpu-deadline", type=int, default=440,
                     help="skip the CPU baseline's Hubbard samples once the run has taken this many seconds")
+    ap.add_argument("--pmc-sample-hubbard14", action="store_true",
+                    help="short run for hardware counters on the mixed-precision workload's step: one 1 GiB "
+                         "STREAM copy, then one degree-12 filter on one nb=32 bundle of the Hubbard ring L=14, "
+                         "FP64 and FP32, in the --hub-fmt storage and --hub-order labels; prints the sizes")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
                          "filter on one nb=64 FP64 bundle of the workload; prints the sizes and exits")
@@ -473,6 +505,30 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
+    if args.pmc_sample_hubbard14:
+        n = 1 << 27  # 1 GiB of doubles
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        fd.stream(0, a, c, stream=stream)
+        torch.cuda.synchronize()
+        del a, c
+        mh = fd.build_matrix("hubbard", fmt=args.hub_fmt, L=14, n_up=7, n_dn=7, t=1.0, U=8.0,
+                             config_order=args.hub_order)
+        al, be = 2.0 / (mh.lam_hi - mh.lam_lo), -(mh.lam_hi + mh.lam_lo) / (mh.lam_hi - mh.lam_lo)
+        res = {"pmc_sample_hubbard14": True, "copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+               "D": mh.D, "nnz": mh.nnz, "nb": 32, "format": args.hub_fmt,
+               "labels": ["ranked", "rcm"][args.hub_order], "launches_mode5": 5, "launches_mode4": 5}
+        for dt, name, sv in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
+            res["shape_" + name] = list(fd.autotune(mh, name, 32, stream=stream))
+            V1 = torch.randn((mh.D, 32), dtype=dt, device=dev)
+            Z1, Z2 = torch.empty_like(V1), torch.empty_like(V1)
+            fd.cheb_filter(mh, V1, fd.cheb_coeffs(1, be, 0.0, 12), al, be, Z1, Z2, 32, stream=stream)
+            torch.cuda.synchronize()
+            res["algorithmic_bytes_mode5_" + name] = fused_bytes(mh.nnz, mh.D, 32, sv, 5)
+            res["algorithmic_bytes_mode4_" + name] = fused_bytes(mh.nnz, mh.D, 32, sv, 3)
+            del V1, Z1, Z2
+        print(json.dumps(res), flush=True)
+        return
     if args.fd_only:
         print(json.dumps({"fd": fd_runs(args, fd, np)}), flush=True)
         return

@@ -194,7 +194,9 @@ fd_status fd_cheb_filter(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t n_bund
 /* Chebyshev coefficients (host, FP64) of the window function, Sec. 2
  * (p(x) = sum_k mu_k T_k(x)): kind 0 = indicator of [a, b] (scaled to
  * [-1, 1]) with Jackson damping for degree+1 moments; kind 1 = Jackson-damped
- * delta at a (b unused).  mu_host has degree+1 entries.                     */
+ * delta at a (b unused); kind 2 = the indicator's plain coefficients (no
+ * damping; for moments that carry the damping already).  mu_host has
+ * degree+1 entries.                                                         */
 fd_status fd_cheb_coeffs(int32_t kind, double a, double b, int32_t degree, double *mu_host);
 
 /* G = X^T Y for device blocks X (D x m, ld ldx) and Y (D x n, ld ldy), FP64,
@@ -219,14 +221,27 @@ fd_status fd_syev(int32_t n, double *S_dev, int64_t lds, double *w_dev, double *
 
 /* Chebyshev moments of the kernel polynomial method (Sec. 4.1 computes the
  * density of states with KPM; Weisse et al. RMP 2006):
- *   mu_k = (1 / (nb D)) sum_r <r| T_k(alpha A + beta) |r>,  k = 0 .. nmom-1,
- * over the nb columns r of the device block R (D x nb, ld ldr; normalised
- * random vectors give the stochastic trace).  nmom even: nmom/2 SpMMVs with
+ *   mu_k = (1 / (ncol D)) sum_r <r| T_k(alpha A + beta) |r>,  k = 0 .. nmom-1,
+ * over the ncol >= 1 columns r of the device block R (D x ncol, ld ldr;
+ * random vectors give the stochastic trace).  The columns are taken in
+ * chunks of 64 (then 32, 16, ... for the rest), each chunk's average weighted
+ * by its width.  nmom even: nmom/2 SpMMVs per chunk with
  * T_2m = 2 T_m^2 - 1 and T_2m+1 = 2 T_m+1 T_m - T_1.  W1, W2: device
- * workspaces D x nb (ld ldw).  mu_host: nmom entries.  FP64.  Synchronizes. */
-fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R_dev, int64_t ldr, int32_t nmom,
+ * workspaces of min(ncol, 64) columns (ld ldw).  mu_host: nmom entries.
+ * FP64.  Synchronizes.                                                      */
+fd_status fd_kpm_moments(fd_matrix m, int32_t ncol, const double *R_dev, int64_t ldr, int32_t nmom,
                          double alpha, double beta, double *W1_dev, double *W2_dev, int64_t ldw,
                          double *mu_host, void *stream);
+
+/* KPM estimate of the number of eigenvalues in the scaled window [a, b]
+ * (-1 <= a <= b <= 1) from nmom moments (host): D sum_k c_k mu_k / mu_0 with
+ * c_k the window's coefficients (fd_cheb_coeffs kind 0, Jackson-damped for
+ * nmom moments, when damped == 0; kind 2, plain, when the moments already
+ * carry the damping, damped == 1).  Dividing by mu_0 (1 for an exact trace)
+ * removes the norm fluctuation of a stochastic sample.  mu_0 <= 0:
+ * FD_ERR_INVALID.                                                           */
+fd_status fd_kpm_count(const double *mu_host, int32_t nmom, int32_t damped, int64_t D, double a, double b,
+                       double *count);
 
 /* Degree picker network (a refinement of the plain rule): an MLP with FD_MLP_IN
  * inputs (64 Jackson-damped KPM moments of the scaled matrix, then the scaled
@@ -269,8 +284,10 @@ fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_ta
 /* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
  * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
  * D x nb (allocated and freed here) and keeps the fastest in the handle for
- * (dtype, nb); later calls on this matrix use it.  shape (8 ints, may be
- * NULL) receives order, xcd, iters, grid, nontemporal, wide, tile, shfl.
+ * (dtype, nb); later calls on this matrix use it.  shape (10 ints, may be
+ * NULL) receives order, xcd, iters, grid, nontemporal, wide, tile, shfl,
+ * lpr, lds (lpr > 0: one vector on CSR with lpr lanes per row; lds 1: the
+ * matrix-free Hubbard down pass with each slab's column slice in LDS).
  * Synchronizes.                                                            */
 fd_status fd_autotune(fd_matrix m, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
 
@@ -290,7 +307,7 @@ fd_status fd_stream(int32_t op, int64_t n, const double *a_dev, const double *b_
 int32_t fd_syev_last_sweeps(void);
 
 /* Launch shape of the sparse kernels, process-wide (tuning; results do not
- * depend on it).  order 0: each block walks `iters` consecutive groups of
+ * depend on it, except lpr below).  order 0: each block walks `iters` consecutive groups of
  * rows (0 = automatic); order 1: grid-stride over `grid` blocks per bundle
  * (0 = automatic).  xcd 1: every XCD owns a contiguous eighth of the rows;
  * xcd 2 (order 0 only): XCD x owns the row chunks x, x+8, x+16, ... of
@@ -305,12 +322,21 @@ int32_t fd_syev_last_sweeps(void);
  * entries at once and hand them to the row's other lanes by cross-lane
  * permute; 2 (at least 8 lanes per row, else as 1), the same with lanes
  * 0..7 and 8 entries at once.
+ * lpr (one vector, nb = 1, on CSR): 0, a lane owns a row; 4, 8 or 16 lanes
+ * share a row, lane q taking its entries q, q + lpr, ... (coalesced index
+ * and value loads) and the partial sums added by cross-lane exchanges --
+ * the same sum in another order, so results differ by rounding.
+ * lds (matrix-free Hubbard): 1 runs the down-hop pass with one block per
+ * (up configuration, 16-byte column slice) that first copies the slab's
+ * slice into LDS and takes every down hop from there (when the slab's
+ * C(L, n_dn) rows of 16 bytes fit in 160 KB and the hops fit the packed
+ * 16-bit table; otherwise the plain pass runs); same results bit for bit.
  * Default: order 0, xcd 2, iters 1, grid 1024, nontemporal 1, wide 0,
- * tile 0, shfl 2.  A shape chosen by fd_autotune for a matrix takes
- * precedence for that matrix.  tile outside [0, 2^20] or shfl outside
- * [0, 2]: FD_ERR_INVALID.                                                  */
+ * tile 0, shfl 2, lpr 0, lds 0.  A shape chosen by fd_autotune for a matrix takes
+ * precedence for that matrix.  tile outside [0, 2^20], shfl outside
+ * [0, 2], lpr not in {0, 4, 8, 16} or lds not 0 or 1: FD_ERR_INVALID.        */
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal,
-                        int32_t wide, int32_t tile, int32_t shfl);
+                        int32_t wide, int32_t tile, int32_t shfl, int32_t lpr, int32_t lds);
 
 /* Lehmann intervals (Lehmann 1963; Sec. 2 determines the target and search
  * intervals of FD from them).  V_dev: D x n block (ld >= n, linearly
@@ -412,7 +438,7 @@ fd_status fd_lanczos(fd_matrix m, int32_t k, uint64_t seed, double *theta_host, 
  * D x N_t, ld N_t) or NULL, resid_host[N_t] or NULL, stats or NULL.  Returns
  * FD_ERR_NOT_CONVERGED (outputs written) if max_iter is reached, or
  * earlier once the FP64 filter stagnates: the largest residual of the
- * targets has not fallen below 0.9 of its best value for 10 iterations.
+ * targets has not fallen below 0.9 of its best value for 30 iterations.
  * Non-finite data anywhere in the iteration (e.g. NaN in V0_host, or a
  * filter that overflowed) give FD_ERR_BREAKDOWN.                           */
 fd_status fd_solve(fd_matrix m, const fd_solve_params *params, const double *V0_host,
@@ -465,11 +491,24 @@ typedef struct {
     int32_t n_converged;   /* instances whose N_t pairs converged            */
     int64_t graph_launches;/* filter graph replays                           */
     double t_filter, t_orthog, t_rr, t_total; /* seconds, whole batch        */
+    int32_t nb;            /* bundle width used (chosen when params nb = 0)  */
 } fd_batch_stats;
+
+/* Launch-shape autotuner of the batched kernels: times the fused Chebyshev
+ * step on scratch blocks of D_total x nb (allocated and freed here) for XCD
+ * chunks of 256 .. 16384 rows and both permute entry loops, and keeps the
+ * fastest in the handle for (dtype, nb); nb = 0 also picks the bundle width
+ * among 8, 16, 32, 64 by time per vector.  shape (3 ints, may be NULL):
+ * nb, chunk rows, entry loop (1: rounds of 4 entries, 2: of 8).  Overwrites
+ * the per-instance filter parameters on the device (fd_batch_filter and
+ * fd_solve_batch set their own).  Synchronizes.                             */
+fd_status fd_batch_autotune(fd_batch b, fd_dtype dtype, int32_t nb, int32_t *shape, void *stream);
 
 /* fd_solve on every instance of the batch (FP64 only: precision must be 0,
  * else FD_ERR_UNSUPPORTED).  params[n_inst]: nb, n_search, n_target and
- * ortho must agree; the window, degree (2..100000, no picker), max_iter,
+ * ortho must agree (nb = 0: the library times the batched step and picks
+ * the bundle width among 8 .. 64 that divide N_s, and the launch shape,
+ * as fd_batch_autotune); the window, degree (2..100000, no picker), max_iter,
  * tol, seed and adapt are per instance.  Each outer iteration
  * orthogonalizes and runs Rayleigh-Ritz (one batched SpMMV for W = A V;
  * with N_s <= 64 every dense step of all instances is one launch, else they

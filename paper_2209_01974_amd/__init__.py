@@ -66,7 +66,7 @@ class SolveStats(C.Structure):
 class BatchStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_converged", C.c_int32), ("graph_launches", C.c_int64),
                 ("t_filter", C.c_double), ("t_orthog", C.c_double), ("t_rr", C.c_double),
-                ("t_total", C.c_double)]
+                ("t_total", C.c_double), ("nb", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,7 +85,9 @@ _SIGS = {
     "fd_matrix_export_sell": [_P, _P, _P, _P, _P, _P],
     "fd_matrix_export_configs": [_P, _P, _P],
     "fd_lanczos": [_P, _I32, C.c_uint64, _P, _P, C.POINTER(_I32), _P],
+    "fd_kpm_count": [_P, _I32, _I32, _I64, _D, _D, _P],
     "fd_debug_alloc_limit": [_I64],
+    "fd_batch_autotune": [_P, C.c_int, _I32, _P, _P],
     "fd_spmmv": [_P, C.c_int, _I32, _P, _I64, _P, _I64, _P],
     "fd_cheb_filter": [_P, C.c_int, _I32, _I32, _P, _I64, _P, _I32, _D, _D, _P, _P, _I64, _P],
     "fd_cheb_coeffs": [_I32, _D, _D, _I32, _P],
@@ -95,7 +97,7 @@ _SIGS = {
     "fd_orthog": [_I64, _I32, _P, _I64, _I32, C.c_uint64, C.POINTER(_I32), _P],
     "fd_rayleigh_ritz": [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P],
     "fd_solve": [_P, C.POINTER(SolveParams), _P, _P, _P, _P, C.POINTER(SolveStats)],
-    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32],
+    "fd_spmmv_tune": [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32],
     "fd_stream": [_I32, _I64, _P, _P, _P, _D, _P],
     "fd_autotune": [_P, C.c_int, _I32, _P, _P],
     "fd_kpm_moments": [_P, _I32, _P, _I64, _I32, _D, _D, _P, _P, _I64, _P, _P],
@@ -310,34 +312,27 @@ def syev(S, w, U, stream=None) -> None:
 
 
 def spmmv_tune(order: int = 0, xcd: int = 2, iters: int = 1, grid: int = 1024, nontemporal: int = 1,
-               wide: int = 0, tile: int = 0, shfl: int = 2) -> None:
-    """Launch shape of the sparse kernels (process-wide; results unchanged)."""
-    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide, tile, shfl))
+               wide: int = 0, tile: int = 0, shfl: int = 2, lpr: int = 0, lds: int = 0) -> None:
+    """Launch shape of the sparse kernels (process-wide; results unchanged,
+    except lpr > 0 for one vector, which sums a row's entries in another
+    order)."""
+    _check(lib().fd_spmmv_tune(order, xcd, iters, grid, nontemporal, wide, tile, shfl, lpr, lds))
 
 
 def kpm_moments(m: "Matrix", R, nmom: int, alpha: float, beta: float, stream=None) -> np.ndarray:
     """KPM moments mu_k = <r|T_k(alpha A + beta)|r> / D averaged over the
     columns r of the GPU block R (fd_kpm_moments)."""
     import torch
-    nr = R.shape[1]
-    total = np.zeros(nmom)
-    j = 0
-    while j < nr:  # column chunks of a width the kernels take (1, 2, 4, ..., 64)
-        w = 64
-        while w > nr - j:
-            w //= 2
-        blk = R[:, j:j + w]
-        pr, ldr, dt = _blk(blk, "R")
-        if dt != FD_F64:
-            raise ValueError("R must be float64")
-        W1 = torch.empty((R.shape[0], w), dtype=torch.float64, device=R.device)
-        W2 = torch.empty_like(W1)
-        mu = np.empty(nmom)
-        _check(lib().fd_kpm_moments(m.handle, w, pr, ldr, nmom, alpha, beta, C.c_void_p(W1.data_ptr()),
-                                    C.c_void_p(W2.data_ptr()), W1.stride(0), mu.ctypes.data, _stream(stream)))
-        total += mu * (w / nr)
-        j += w
-    return total
+    pr, ldr, dt = _blk(R, "R")
+    if dt != FD_F64:
+        raise ValueError("R must be float64")
+    w = min(R.shape[1], 64)
+    W1 = torch.empty((R.shape[0], w), dtype=torch.float64, device=R.device)
+    W2 = torch.empty_like(W1)
+    mu = np.empty(nmom)
+    _check(lib().fd_kpm_moments(m.handle, R.shape[1], pr, ldr, nmom, alpha, beta, C.c_void_p(W1.data_ptr()),
+                                C.c_void_p(W2.data_ptr()), W1.stride(0), mu.ctypes.data, _stream(stream)))
+    return mu
 
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 66, 128, 2
@@ -372,16 +367,18 @@ def mlp_adam(params, G, M, V, step: int, lr: float, wd: float = 0.0, stream=None
                              C.c_void_p(V.data_ptr()), step, lr, wd, _stream(stream)))
 
 
-def window_count(mu_kpm: np.ndarray, D: int, a: float, b: float) -> float:
-    """Estimated number of eigenvalues in the scaled window [a, b]:
-    D * sum_k c_k g_k mu_k with the Jackson-damped indicator coefficients."""
-    c = cheb_coeffs(0, a, b, mu_kpm.size - 1)
-    return float(D * np.dot(c, mu_kpm))
+def window_count(mu_kpm: np.ndarray, D: int, a: float, b: float, damped: bool = False) -> float:
+    """fd_kpm_count: estimated number of eigenvalues in the scaled window
+    [a, b] from KPM moments (damped: the moments carry the Jackson factors)."""
+    mu = np.ascontiguousarray(mu_kpm, dtype=np.float64)
+    out = _D()
+    _check(lib().fd_kpm_count(mu.ctypes.data, mu.size, int(damped), D, a, b, C.byref(out)))
+    return out.value
 
 
 def autotune(m: "Matrix", dtype: str = "f64", nb: int = 64, stream=None) -> tuple:
     """Pick the fastest launch shape of the fused step for (m, dtype, nb)."""
-    shape = (C.c_int32 * 8)()
+    shape = (C.c_int32 * 10)()
     _check(lib().fd_autotune(m.handle, FD_F64 if dtype == "f64" else FD_F32, nb, shape, _stream(stream)))
     return tuple(shape)
 
@@ -512,6 +509,13 @@ class Batch:
                 self._h = None
         except Exception:
             pass
+
+
+def batch_autotune(b: Batch, dtype: str = "f64", nb: int = 0, stream=None) -> tuple:
+    """fd_batch_autotune: (nb, chunk rows, entry loop) chosen for the batch."""
+    shape = (C.c_int32 * 3)()
+    _check(lib().fd_batch_autotune(b.handle, FD_F64 if dtype == "f64" else FD_F32, nb, shape, _stream(stream)))
+    return tuple(shape)
 
 
 def batch_spmmv(b: Batch, X, Y, stream=None) -> None:

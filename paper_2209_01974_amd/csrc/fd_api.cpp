@@ -57,6 +57,15 @@ bool overlap(const void *a, int64_t la, const void *b, int64_t lb, int64_t D, si
     return a0 < b1 && b0 < a1;
 }
 
+// the same for blocks of wa and wb columns: the last row ends after its own
+// columns, not after a full leading dimension
+bool overlap_w(const void *a, int64_t la, int64_t wa, const void *b, int64_t lb, int64_t wb, int64_t D, size_t es) {
+    if (D < 1) return false;
+    const char *a0 = (const char *)a, *a1 = a0 + (size_t)((D - 1) * la + wa) * es;
+    const char *b0 = (const char *)b, *b1 = b0 + (size_t)((D - 1) * lb + wb) * es;
+    return a0 < b1 && b0 < a1;
+}
+
 template <typename T>
 fd_status to_device(T **dst, const std::vector<T> &src) {
     FD_HIP(hipMalloc((void **)dst, std::max<size_t>(1, src.size()) * sizeof(T)));
@@ -87,6 +96,18 @@ fd_status upload_tables(fd_matrix m) {
     FD_TRY(to_device(&d.val_d64, T.val_d));
     FD_TRY(to_device(&d.val_u32, u32));
     FD_TRY(to_device(&d.val_d32, d32));
+    // packed down hops for the LDS-staged pass: 15-bit targets and one
+    // shared magnitude (the ring's hops are all +-t)
+    bool pack = T.nd <= 32767 && !T.val_d.empty();
+    const double tmag = pack ? std::fabs(T.val_d[0]) : 0.0;
+    for (size_t i = 0; pack && i < T.val_d.size(); i++) pack = std::fabs(T.val_d[i]) == tmag && T.val_d[i] != 0.0;
+    if (pack) {
+        std::vector<uint16_t> h16(T.idx_d.size());
+        for (size_t i = 0; i < h16.size(); i++)
+            h16[i] = (uint16_t)(T.idx_d[i] | (T.val_d[i] > 0.0 ? 0x8000 : 0));
+        FD_TRY(to_device(&d.hop16_d, h16));
+        d.tmag_d = tmag;
+    }
     FD_HIP(hipGetDevice(&m->device));
     return FD_OK;
 }
@@ -149,7 +170,8 @@ void free_dev(DevMatrix &d) {
     if (d.val64) (void)hipFree(d.val64);
     if (d.val32) (void)hipFree(d.val32);
     if (d.perm) (void)hipFree(d.perm);
-    void *tabs[] = {d.mu, d.md, d.off_u, d.off_d, d.idx_u, d.idx_d, d.val_u64, d.val_d64, d.val_u32, d.val_d32};
+    void *tabs[] = {d.mu, d.md, d.off_u, d.off_d, d.idx_u, d.idx_d, d.val_u64, d.val_d64, d.val_u32, d.val_d32,
+                    d.hop16_d};
     for (void *p : tabs)
         if (p) (void)hipFree(p);
     d = DevMatrix();
@@ -890,24 +912,74 @@ fd_status fd_autotune(fd_matrix m, fd_dtype dt, int32_t nb, int32_t *shape, void
         shape[5] = t.wide;
         shape[6] = t.tile;
         shape[7] = t.shfl;
+        shape[8] = t.lpr;
+        shape[9] = t.lds;
     }
     return FD_OK;
 }
 
-fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R, int64_t ldr, int32_t nmom, double alpha,
-                         double beta, double *W1, double *W2, int64_t ldw, double *mu, void *stream) {
+fd_status kpm_chunk(fd_matrix m, int32_t nb, const double *R, int64_t ldr, int32_t nmom, double alpha,
+                    double beta, double *W1, double *W2, int64_t ldw, double *mu, hipStream_t s,
+                    double *dots_ws = nullptr, double *part_ws = nullptr);
+
+// Moments over ncol columns in chunks of 64, 32, ... (weighted by width).
+// dots_ws / part_ws: device buffers for the moment dots (nmom x 64) and the
+// reduction partials (2048 x 64), or nullptr for the process workspace.
+fd_status kpm_all(fd_matrix m, int32_t ncol, const double *R, int64_t ldr, int32_t nmom, double alpha, double beta,
+                  double *W1, double *W2, int64_t ldw, double *mu, hipStream_t s, double *dots_ws,
+                  double *part_ws) {
     FD_TRY(need_device(m));
-    if (!nb_ok(nb) || nmom < 2 || (nmom & 1) || !mu) return fail(FD_ERR_INVALID, "fd_kpm_moments: bad nb or nmom");
-    FD_TRY(check_block(R, ldr, nb, FD_F64, nb, "fd_kpm_moments R"));
-    FD_TRY(check_block(W1, ldw, nb, FD_F64, nb, "fd_kpm_moments W1"));
-    FD_TRY(check_block(W2, ldw, nb, FD_F64, nb, "fd_kpm_moments W2"));
+    if (ncol < 1 || nmom < 2 || (nmom & 1) || !mu) return fail(FD_ERR_INVALID, "fd_kpm_moments: bad ncol or nmom");
+    const int wmax = std::min(ncol, 64);
+    FD_TRY(check_block(R, ldr, ncol, FD_F64, 1, "fd_kpm_moments R"));
+    FD_TRY(check_block(W1, ldw, wmax, FD_F64, 1, "fd_kpm_moments W1"));
+    FD_TRY(check_block(W2, ldw, wmax, FD_F64, 1, "fd_kpm_moments W2"));
     const int64_t D = m->dev.D;
-    if (overlap(W1, ldw, W2, ldw, D, 8) || overlap(R, ldr, W1, ldw, D, 8) || overlap(R, ldr, W2, ldw, D, 8))
+    if (overlap_w(W1, ldw, wmax, W2, ldw, wmax, D, 8) || overlap_w(R, ldr, ncol, W1, ldw, wmax, D, 8) ||
+        overlap_w(R, ldr, ncol, W2, ldw, wmax, D, 8))
         return fail(FD_ERR_INVALID, "fd_kpm_moments: R, W1, W2 overlap");
+    std::vector<double> part(nmom), total(nmom, 0.0);
+    // chunks of 64 columns, then the largest power of two that is left
+    for (int j = 0; j < ncol;) {
+        int w = 64;
+        while (w > ncol - j) w >>= 1;
+        FD_TRY(kpm_chunk(m, w, R + j, ldr, nmom, alpha, beta, W1, W2, ldw, part.data(), s, dots_ws, part_ws));
+        for (int k = 0; k < nmom; k++) total[k] += part[k] * ((double)w / (double)ncol);
+        j += w;
+    }
+    std::copy(total.begin(), total.end(), mu);
+    return FD_OK;
+}
+
+fd_status fd_kpm_moments(fd_matrix m, int32_t ncol, const double *R, int64_t ldr, int32_t nmom, double alpha,
+                         double beta, double *W1, double *W2, int64_t ldw, double *mu, void *stream) {
+    return kpm_all(m, ncol, R, ldr, nmom, alpha, beta, W1, W2, ldw, mu, (hipStream_t)stream, nullptr, nullptr);
+}
+
+fd_status fd_kpm_count(const double *mu, int32_t nmom, int32_t damped, int64_t D, double a, double b,
+                       double *count) {
+    if (!mu || !count || nmom < 1 || D < 0 || (damped != 0 && damped != 1))
+        return fail(FD_ERR_INVALID, "fd_kpm_count: bad arguments");
+    if (!(mu[0] > 0.0)) return fail(FD_ERR_INVALID, "fd_kpm_count: mu_0 must be positive");
+    std::vector<double> c(nmom);
+    FD_TRY(cheb_coeffs(damped ? 2 : 0, a, b, nmom - 1, c.data()));
+    double n = 0.0;
+    for (int k = 0; k < nmom; k++) n += c[k] * mu[k];
+    *count = (double)D * n / mu[0];
+    return FD_OK;
+}
+
+// one chunk of nb <= 64 columns (nb a power of two)
+fd_status kpm_chunk(fd_matrix m, int32_t nb, const double *R, int64_t ldr, int32_t nmom, double alpha,
+                    double beta, double *W1, double *W2, int64_t ldw, double *mu, hipStream_t stream,
+                    double *dots_ws, double *part_ws) {
+    // arguments checked by the caller (kpm_all)
+    if (!nb_ok(nb)) return fail(FD_ERR_INVALID, "fd_kpm_moments: bad chunk width");
+    const int64_t D = m->dev.D;
     hipStream_t s = (hipStream_t)stream;
     const int half = nmom / 2;
     // per column: d[2m] = <T_m|T_m>, d[2m+1] = <T_{m+1}|T_m>, m = 0 .. half-1
-    double *dots = (double *)workspace((size_t)nmom * nb * sizeof(double), 5);
+    double *dots = dots_ws ? dots_ws : (double *)workspace((size_t)nmom * nb * sizeof(double), 5);
     if (!dots) return fail(FD_ERR_OOM, "fd_kpm_moments: workspace");
     FD_TRY(copy_block(D, nb, R, ldr, W2, ldw, s));  // T_0
     SpmmvCall c;
@@ -917,8 +989,8 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R, int64_t ldr, 
     c.y = W1; c.ldy = ldw;
     c.a = alpha; c.b = beta;
     FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
-    FD_TRY(col_dots(D, nb, W2, ldw, W2, ldw, dots, s));
-    FD_TRY(col_dots(D, nb, W1, ldw, W2, ldw, dots + nb, s));
+    FD_TRY(col_dots(D, nb, W2, ldw, W2, ldw, dots, s, part_ws));
+    FD_TRY(col_dots(D, nb, W1, ldw, W2, ldw, dots + nb, s, part_ws));
     double *cur = W1, *prev = W2;  // T_m, T_{m-1}
     for (int k = 1; k < half; k++) {
         c.mode = 4;  // prev <- T_{m+1} = 2 B T_m - T_{m-1}
@@ -927,8 +999,8 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t nb, const double *R, int64_t ldr, 
         c.y = prev; c.ldy = ldw;
         c.a = 2.0 * alpha; c.b = 2.0 * beta;
         FD_TRY(launch_spmmv(m->dev, FD_F64, c, s));
-        FD_TRY(col_dots(D, nb, cur, ldw, cur, ldw, dots + (size_t)(2 * k) * nb, s));
-        FD_TRY(col_dots(D, nb, prev, ldw, cur, ldw, dots + (size_t)(2 * k + 1) * nb, s));
+        FD_TRY(col_dots(D, nb, cur, ldw, cur, ldw, dots + (size_t)(2 * k) * nb, s, part_ws));
+        FD_TRY(col_dots(D, nb, prev, ldw, cur, ldw, dots + (size_t)(2 * k + 1) * nb, s, part_ws));
         std::swap(cur, prev);
     }
     std::vector<double> h((size_t)nmom * nb);
@@ -1024,9 +1096,10 @@ fd_status fd_stream(int32_t op, int64_t n, const double *a, const double *b, dou
 }
 
 fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid, int32_t nontemporal, int32_t wide,
-                        int32_t tile, int32_t shfl) {
+                        int32_t tile, int32_t shfl, int32_t lpr, int32_t lds) {
     if (order < 0 || order > 1 || xcd < 0 || xcd > 2 || (order == 1 && xcd == 2) || iters < 0 || grid < 0 ||
-        grid > (1 << 24) || tile < 0 || tile > (1 << 20) || shfl < 0 || shfl > 2)
+        grid > (1 << 24) || tile < 0 || tile > (1 << 20) || shfl < 0 || shfl > 2 ||
+        (lpr != 0 && lpr != 4 && lpr != 8 && lpr != 16) || lds < 0 || lds > 1)
         return fail(FD_ERR_INVALID, "fd_spmmv_tune: bad arguments");
     SpmmvTune &t = spmmv_tune();
     t.order = order;
@@ -1037,6 +1110,8 @@ fd_status fd_spmmv_tune(int32_t order, int32_t xcd, int32_t iters, int32_t grid,
     t.wide = wide != 0;
     t.tile = tile;
     t.shfl = shfl;
+    t.lpr = lpr;
+    t.lds = lds;
     return FD_OK;
 }
 
@@ -1181,13 +1256,15 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     st.norm_H = normH;
     st.degree = degree;
     bool fp32 = P->precision == 1;
-    // FD_TRACE=1: one JSON line per outer iteration on stderr
+    // FD_TRACE=1: one JSON line per outer iteration on stderr; FD_TRACE_FILE:
+    // the same lines appended to that file (flushed line by line)
     const char *tr = std::getenv("FD_TRACE");
-    const bool trace = tr && tr[0] == '1';
+    const char *trf = std::getenv("FD_TRACE_FILE");
+    const bool trace = (tr && tr[0] == '1') || (trf && trf[0]);
     double prev_max = INFINITY;
     // stagnation: the largest residual of the targets has not dropped below
     // 0.9 of its best value for kStall iterations (FP64 filter)
-    constexpr int kStall = 10;
+    constexpr int kStall = 30;
     double best_max = INFINITY;
     int stall = 0;
     bool stagnated = false;
@@ -1231,13 +1308,23 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
             char mxs[32], lrs[32];
             std::snprintf(mxs, sizeof mxs, std::isfinite(mx) ? "%.3e" : "null", mx / normH);
             std::snprintf(lrs, sizeof lrs, std::isfinite(lehmann_r) ? "%.3e" : "null", lehmann_r);
-            std::fprintf(stderr,
-                         "{\"fd_iter\": %d, \"max_resid_rel\": %s, \"n_in_window\": %d, \"n_conv\": %d, "
-                         "\"next_fp32\": %d, \"spmmv\": %lld, \"t_filter\": %.3f, \"t_orthog\": %.3f, "
-                         "\"t_rr\": %.3f, \"lehmann_r\": %s, \"t\": %.3f}\n",
-                         it, mxs, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count, st.t_filter,
-                         st.t_orthog, st.t_rr, lrs, now() - t0);
-            std::fflush(stderr);
+            char line[512];
+            std::snprintf(line, sizeof line,
+                          "{\"fd_iter\": %d, \"D\": %lld, \"max_resid_rel\": %s, \"n_in_window\": %d, "
+                          "\"n_conv\": %d, \"next_fp32\": %d, \"spmmv\": %lld, \"t_filter\": %.3f, "
+                          "\"t_orthog\": %.3f, \"t_rr\": %.3f, \"lehmann_r\": %s, \"t\": %.3f}\n",
+                          it, (long long)D, mxs, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count,
+                          st.t_filter, st.t_orthog, st.t_rr, lrs, now() - t0);
+            if (tr && tr[0] == '1') {
+                std::fputs(line, stderr);
+                std::fflush(stderr);
+            }
+            if (trf && trf[0]) {
+                if (FILE *f = std::fopen(trf, "a")) {
+                    std::fputs(line, f);
+                    std::fclose(f);
+                }
+            }
         }
         if (!fp32) {
             if (mx < 0.9 * best_max) {
@@ -1307,7 +1394,7 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     st.t_total = now() - t0;
     if (stats) *stats = st;
     if (!converged)
-        return fail(FD_ERR_NOT_CONVERGED, stagnated ? "fd_solve: stagnated (no 10% progress in 10 iterations)"
+        return fail(FD_ERR_NOT_CONVERGED, stagnated ? "fd_solve: stagnated (no 10% progress in 30 iterations)"
                                                     : "fd_solve: not converged within max_iter");
     return FD_OK;
 }
@@ -1479,16 +1566,133 @@ fd_status fd_batch_filter(fd_batch b, fd_dtype dt, int32_t nb, int32_t n_bundles
                             use_graph != 0, s);
 }
 
+// Launch-shape autotuner of the batched step: the fused Chebyshev step
+// (V every other step: k = 3 and k = 4 alternately) timed on scratch blocks
+// for XCD chunks of 256 .. 16384 rows and both permute loops; the fastest is
+// kept in the handle for (dtype, nb).  nb = 0: also the bundle width among
+// 8, 16, 32, 64 that divide ns (all when ns = 0; time per vector; in
+// *nb_out).  Overwrites the per-instance
+// filter parameters on the device (every filter call sets its own).
+static fd_status batch_autotune(fd_batch b, fd_dtype dt, int nb_req, int ns, int *nb_out, int32_t *chunk_out,
+                                int32_t *sh_out, hipStream_t s) {
+    BatchDev &d = b->dev;
+    const int n = d.n_inst;
+    const size_t es = esize(dt);
+    const int di = dt == FD_F64 ? 0 : 1;
+    std::vector<int> nbs;
+    if (nb_req == 0) {
+        for (int w : {8, 16, 32, 64})
+            if (ns == 0 || ns % w == 0) nbs.push_back(w);
+        if (nbs.empty()) return fail(FD_ERR_INVALID, "batched autotune: N_s has no bundle width among 8 .. 64");
+    } else {
+        nbs = {nb_req};
+    }
+    const int nbmax = *std::max_element(nbs.begin(), nbs.end());
+    DevBuf buf;
+    FD_TRY(buf.alloc((size_t)d.D * nbmax * es * 3, "batched autotune blocks"));
+    FD_HIP(hipMemsetAsync(buf.p, 0, (size_t)d.D * nbmax * es * 3, s));
+    std::vector<double> al(n, 0.25), be(n, 0.0), mu((size_t)n * 5, 0.5);
+    std::vector<int32_t> dg(n, 4), act(n, 1);
+    FD_TRY(batch_params(b, al.data(), be.data(), dg.data(), act.data(), mu.data(), 5, s));
+    hipEvent_t e0, e1;
+    FD_HIP(hipEventCreate(&e0));
+    FD_HIP(hipEventCreate(&e1));
+    const int chunks[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
+    double best_pv = 1e300;
+    int best_nb = nbs[0];
+    fd_status st = FD_OK;
+    for (int w : nbs) {
+        const int lg = __builtin_ctz((unsigned)w);
+        const int G = std::max(1, (int)(w * es / 16));  // lanes per row (16 bytes each)
+        const int rpb = 256 / std::min(G, 256);
+        char *x = (char *)buf.p, *y = x + (size_t)d.D * w * es, *v = y + (size_t)d.D * w * es;
+        BatchCall c;
+        c.nb = w;
+        c.nbundles = 1;
+        c.mode = 5;
+        c.x = x; c.ldx = w;
+        c.z = y; c.ldz = w;
+        c.y = y; c.ldy = w;
+        c.v = v; c.ldv = w;
+        const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(20, (int64_t)4e9 / (int64_t)(d.D * w * es + 1)));
+        float best_ms = 1e30f;
+        int32_t bc = 1024, bs = 2;
+        for (int ch : chunks) {
+            if (ch < rpb) continue;
+            for (int sh = 1; sh <= 2; sh++) {
+                if (sh == 1 && G < 8) continue;  // both loops are the same below 8 lanes
+                d.chunk[di][lg] = ch;
+                d.sh[di][lg] = (int8_t)sh;
+                c.k = 3;
+                st = launch_batch(d, dt, c, s);  // warm-up
+                if (st != FD_OK) break;
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < reps && st == FD_OK; r++) {
+                    c.k = 3 + (r & 1);
+                    st = launch_batch(d, dt, c, s);
+                }
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (st == FD_OK && ms < best_ms) {
+                    best_ms = ms;
+                    bc = ch;
+                    bs = sh;
+                }
+            }
+            if (st != FD_OK) break;
+        }
+        if (st != FD_OK) break;
+        d.chunk[di][lg] = bc;
+        d.sh[di][lg] = (int8_t)bs;
+        const double per_vec = best_ms / reps / w;
+        if (per_vec < best_pv) {
+            best_pv = per_vec;
+            best_nb = w;
+            if (chunk_out) *chunk_out = bc;
+            if (sh_out) *sh_out = bs;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    if (st != FD_OK) return st;
+    if (nb_out) *nb_out = best_nb;
+    // a captured filter graph holds the old launch shape
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    return FD_OK;
+}
+
+fd_status fd_batch_autotune(fd_batch b, fd_dtype dt, int32_t nb, int32_t *shape, void *stream) {
+    if (!b) return fail(FD_ERR_INVALID, "fd_batch_autotune: null handle");
+    if ((dt != FD_F64 && dt != FD_F32) || (nb != 0 && !nb_ok(nb)) || b->dev.D == 0)
+        return fail(FD_ERR_INVALID, "fd_batch_autotune: bad dtype or nb");
+    int nbo = nb;
+    int32_t ch = 0, sh = 0;
+    FD_TRY(batch_autotune(b, dt, nb, 0, &nbo, &ch, &sh, (hipStream_t)stream));
+    if (shape) {
+        shape[0] = nbo;
+        shape[1] = ch;
+        shape[2] = sh;
+    }
+    return FD_OK;
+}
+
 fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0, double *evals, double *evecs,
                          double *resid, fd_solve_stats *stats, fd_batch_stats *bstats) {
     if (!b || !P || !evals) return fail(FD_ERR_INVALID, "fd_solve_batch: null argument");
     const int n = b->dev.n_inst;
-    const int nb = P[0].nb, ns = P[0].n_search, nt = P[0].n_target, ortho = P[0].ortho;
-    if (!nb_ok(nb) || ns < nb || ns % nb || ns > 512 || nt < 1 || nt > ns)
-        return fail(FD_ERR_INVALID, "fd_solve_batch: need nb in {1..64}, N_s a multiple of nb, N_t <= N_s <= 512");
+    int nb = P[0].nb;
+    const int ns = P[0].n_search, nt = P[0].n_target, ortho = P[0].ortho;
+    if ((nb != 0 && (!nb_ok(nb) || ns < nb || ns % nb)) || ns > 512 || nt < 1 || nt > ns)
+        return fail(FD_ERR_INVALID, "fd_solve_batch: need nb in {0, 1..64}, N_s a multiple of nb, N_t <= N_s <= 512");
     for (int i = 0; i < n; i++) {
         const fd_solve_params &p = P[i];
-        if (p.nb != nb || p.n_search != ns || p.n_target != nt || p.ortho != ortho)
+        if (p.nb != P[0].nb || p.n_search != ns || p.n_target != nt || p.ortho != ortho)
             return fail(FD_ERR_INVALID, "fd_solve_batch: nb, N_s, N_t and ortho must agree across instances");
         if (p.precision != 0) return fail(FD_ERR_UNSUPPORTED, "fd_solve_batch: FP64 only (precision 0)");
         if (p.interval != 0) return fail(FD_ERR_UNSUPPORTED, "fd_solve_batch: Gershgorin scaling only (interval 0)");
@@ -1503,6 +1707,7 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
     const double t0 = now();
     const int64_t D = b->dev.D;
     hipStream_t s = nullptr;
+    if (nb == 0) FD_TRY(batch_autotune(b, FD_F64, 0, ns, &nb, nullptr, nullptr, s));
     int max_degree = 0;
     for (int i = 0; i < n; i++) max_degree = std::max(max_degree, P[i].degree);
     const int mstride = max_degree + 1;
@@ -1755,6 +1960,7 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
     }
     bs.t_total = now() - t0;
     bs.graph_launches = b->graph_launches - launches0;
+    bs.nb = nb;
     if (stats) std::copy(st.begin(), st.end(), stats);
     if (bstats) *bstats = bs;
     if (!all) return fail(FD_ERR_NOT_CONVERGED, "fd_solve_batch: some instances did not converge within max_iter");

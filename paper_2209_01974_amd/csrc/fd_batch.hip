@@ -10,9 +10,12 @@
 // over G lanes of VEC values (16 bytes); blockIdx.y selects the bundle.
 // With 4 or more lanes per row, the row's first 4 or 8 lanes load that many
 // entries at once and pass them on by cross-lane permute.
-// Row groups are dealt to the 8 XCDs in interleaved chunks of CHUNK rows, so
+// Row groups are dealt to the 8 XCDs in interleaved chunks of rows (a power
+// of two, 1024 by default, chosen per dtype and nb by fd_batch_autotune), so
 // that the near neighbours of a row (+-1, +-L for a 3D stencil) stay in one
 // XCD's L2.
+#include <type_traits>
+
 #include "fd_internal.h"
 
 namespace fd {
@@ -25,13 +28,12 @@ template <> struct BV<float, 1> { typedef float type; };
 template <> struct BV<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
 template <> struct BV<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
 
-constexpr int CHUNK = 1024;  // rows per XCD chunk
-
 template <typename T>
 struct BArgs {
     int64_t D;
     int32_t k, mstride;
     int32_t maxlen;  // longest row of the union
+    int32_t cb_shift;  // log2(blocks per XCD chunk)
     const uint32_t *__restrict__ ptr;
     const uint32_t *__restrict__ col;
     const T *__restrict__ val;
@@ -64,23 +66,35 @@ __device__ __forceinline__ V fmab(T a, V x, V acc) { return __builtin_elementwis
 // MODE 5: as MODE 3, but V is updated every other step with two terms: at
 //   even k, v += mu_i,k-1 x + mu_ik t (x = the previous step's vector); at
 //   odd k only when k is the instance's last step (v += mu_ik t)
-template <typename T, int VEC, int G, int MODE>
+// SH: entry loop with 4 or more lanes per row; 1 permute rounds of 4
+// entries, 2 rounds of 8 (8 or more lanes per row).
+template <typename T, int VEC, int G, int MODE, int SH>
 __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     typedef typename BV<T, VEC>::type V;
     constexpr int RPB = 256 / G;
-    constexpr int64_t CB = CHUNK / RPB;  // blocks per chunk (a power of two)
     // block -> row group: XCD x = b % 8 works through chunks x, x+8, ...
+    // (a chunk is 2^cb_shift blocks)
     const int64_t b = blockIdx.x;
-    const int64_t j = b >> 3, c = j / CB;
-    const int64_t rg = ((c << 3) + (b & 7)) * CB + (j - c * CB);
+    const int64_t j = b >> 3, c = j >> p.cb_shift;
+    const int64_t rg = ((((c << 3) + (b & 7))) << p.cb_shift) + (j - (c << p.cb_shift));
     const int64_t row = rg * RPB + threadIdx.x / G;
-    if (row >= p.D) return;
-    const int i = p.inst[row];
+    bool live = row < p.D;
+    const int i = live ? p.inst[row] : 0;
     if constexpr (MODE == 0) {
-        if (!p.act[i]) return;
+        live = live && p.act[i];
     } else {
-        if (p.k > p.deg[i]) return;
+        live = live && p.k <= p.deg[i];
     }
+    const uint32_t j0 = live ? p.ptr[row] : 0, j1 = live ? p.ptr[row + 1] : 0;
+    // rounds of the permute loop: the longest live row of this wave (every
+    // lane of the wave is still here; lanes of a row share its length)
+    int32_t wl = (int32_t)(j1 - j0);
+    if constexpr (G >= 4) {
+#pragma unroll
+        for (int o = G; o < 64; o <<= 1) wl = max(wl, __shfl_xor(wl, o, 64));
+        wl = min(wl, p.maxlen);
+    }
+    if (!live) return;
     const int q = threadIdx.x % G;
     const int64_t bnd = blockIdx.y;
     const T *xq = p.x + bnd * p.bx + q * VEC;
@@ -95,18 +109,17 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     if constexpr (MODE >= 3) zi = ldn<V>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
     V xi = (V)0;
     if constexpr (MODE != 0) xi = ldg<V>(xq + row * p.ldx);
-    const uint32_t j0 = p.ptr[row], j1 = p.ptr[row + 1];
     V acc0 = (V)0, acc1 = (V)0;
     if constexpr (G >= 4) {
         // rounds of LW entries: lanes 0..LW-1 of the row load one each, the
         // row's lanes take them by permute; the rounds run to the longest
-        // row of the union, so all lanes of a live row take part in every
+        // row of the wave, so all lanes of a live row take part in every
         // permute (a row's lanes return together, and a permute reads only
         // lanes of its own row)
-        constexpr int LW = G >= 8 ? 8 : 4;
+        constexpr int LW = (G >= 8 && SH == 2) ? 8 : 4;
         const uint32_t len = j1 - j0;
         const int rbase = (int)(threadIdx.x & 63) - q;
-        for (int r0 = 0; r0 < p.maxlen; r0 += LW) {
+        for (int r0 = 0; r0 < wl; r0 += LW) {
             const uint32_t jq = (uint32_t)(r0 + q);
             uint32_t cm = 0;
             T am = (T)0;
@@ -173,6 +186,20 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     }
 }
 
+template <typename T, int VEC, int G, int SH>
+fd_status launch_bs(const BatchDev &B, const BArgs<T> &p, const BatchCall &c, const dim3 &grid, hipStream_t s) {
+    switch (c.mode) {
+        case 0: hipLaunchKernelGGL((k_batch<T, VEC, G, 0, SH>), grid, dim3(256), 0, s, p); break;
+        case 1: hipLaunchKernelGGL((k_batch<T, VEC, G, 1, SH>), grid, dim3(256), 0, s, p); break;
+        case 2: hipLaunchKernelGGL((k_batch<T, VEC, G, 2, SH>), grid, dim3(256), 0, s, p); break;
+        case 3: hipLaunchKernelGGL((k_batch<T, VEC, G, 3, SH>), grid, dim3(256), 0, s, p); break;
+        case 5: hipLaunchKernelGGL((k_batch<T, VEC, G, 5, SH>), grid, dim3(256), 0, s, p); break;
+        default: return fail(FD_ERR_INVALID, "batched SpMMV: bad mode");
+    }
+    FD_HIP(hipGetLastError());
+    return FD_OK;
+}
+
 template <typename T, int VEC, int G>
 fd_status launch_bt(const BatchDev &B, const T *val, const BatchCall &c, hipStream_t s) {
     constexpr int RPB = 256 / G;
@@ -188,24 +215,23 @@ fd_status launch_bt(const BatchDev &B, const T *val, const BatchCall &c, hipStre
     p.z = (const T *)c.z; p.ldz = c.ldz; p.bz = c.bz;
     p.v = (T *)c.v; p.ldv = c.ldv; p.bv = c.bv;
     if (B.D == 0) return FD_OK;
+    // launch shape of this dtype and nb: XCD chunk (rows) and entry loop
+    const int di = std::is_same<T, double>::value ? 0 : 1, lg = __builtin_ctz((unsigned)c.nb);
+    const int64_t chunk = B.chunk[di][lg] > 0 ? B.chunk[di][lg] : 1024;
+    const int64_t cb = std::max<int64_t>(1, chunk / RPB);  // blocks per chunk (a power of two)
+    p.cb_shift = __builtin_ctzll((unsigned long long)cb);
     // grid: whole super-chunks (8 chunks of cb blocks), so the block -> row
     // group map is a bijection; row groups past D return at once
     const int64_t ngroups = (B.D + RPB - 1) / RPB;
-    const int64_t super = 8 * (CHUNK / RPB);
+    const int64_t super = 8 * cb;
     const int64_t nblk = (ngroups + super - 1) / super * super;
     if (nblk > 0x7fffffff || c.nbundles < 1 || c.nbundles > 65535)
         return fail(FD_ERR_UNSUPPORTED, "batched SpMMV: grid too large");
     const dim3 grid((unsigned)nblk, c.nbundles);
-    switch (c.mode) {
-        case 0: hipLaunchKernelGGL((k_batch<T, VEC, G, 0>), grid, dim3(256), 0, s, p); break;
-        case 1: hipLaunchKernelGGL((k_batch<T, VEC, G, 1>), grid, dim3(256), 0, s, p); break;
-        case 2: hipLaunchKernelGGL((k_batch<T, VEC, G, 2>), grid, dim3(256), 0, s, p); break;
-        case 3: hipLaunchKernelGGL((k_batch<T, VEC, G, 3>), grid, dim3(256), 0, s, p); break;
-        case 5: hipLaunchKernelGGL((k_batch<T, VEC, G, 5>), grid, dim3(256), 0, s, p); break;
-        default: return fail(FD_ERR_INVALID, "batched SpMMV: bad mode");
+    if constexpr (G >= 8) {
+        if (B.sh[di][lg] == 1) return launch_bs<T, VEC, G, 1>(B, p, c, grid, s);
     }
-    FD_HIP(hipGetLastError());
-    return FD_OK;
+    return launch_bs<T, VEC, G, 2>(B, p, c, grid, s);
 }
 
 }  // namespace

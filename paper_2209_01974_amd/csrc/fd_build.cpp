@@ -566,14 +566,15 @@ void gershgorin(const HostCSR &A, double &lo, double &hi) {
 fd_status cheb_coeffs(int kind, double a, double b, int n, double *mu) {
     if (n < 0 || !mu) return fail(FD_ERR_INVALID, "coefficients: need degree >= 0");
     if (!(a >= -1.0 && a <= 1.0)) return fail(FD_ERR_INVALID, "coefficients: a outside [-1, 1]");
-    if (kind == 0 && !(b >= a && b <= 1.0)) return fail(FD_ERR_INVALID, "coefficients: need a <= b <= 1");
-    if (kind != 0 && kind != 1) return fail(FD_ERR_INVALID, "coefficients: kind must be 0 or 1");
+    if ((kind == 0 || kind == 2) && !(b >= a && b <= 1.0)) return fail(FD_ERR_INVALID, "coefficients: need a <= b <= 1");
+    if (kind < 0 || kind > 2) return fail(FD_ERR_INVALID, "coefficients: kind must be 0, 1 or 2");
     const double M = n + 1.0, q = M_PI / (M + 1.0), cotq = std::cos(q) / std::sin(q);
-    const double tha = std::acos(a), thb = (kind == 0) ? std::acos(b) : 0.0;
+    const double tha = std::acos(a), thb = (kind != 1) ? std::acos(b) : 0.0;
     for (int k = 0; k <= n; k++) {
-        double g = ((M - k + 1.0) * std::cos(k * q) + std::sin(k * q) * cotq) / (M + 1.0);
+        // kind 2: the indicator's plain coefficients (no damping)
+        double g = kind == 2 ? 1.0 : ((M - k + 1.0) * std::cos(k * q) + std::sin(k * q) * cotq) / (M + 1.0);
         double c;
-        if (kind == 0)
+        if (kind != 1)
             c = (k == 0) ? (tha - thb) / M_PI : 2.0 / (k * M_PI) * (std::sin(k * tha) - std::sin(k * thb));
         else
             c = (k == 0 ? 1.0 : 2.0) * std::cos(k * tha);

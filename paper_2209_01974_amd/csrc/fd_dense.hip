@@ -930,10 +930,10 @@ __global__ void k_copy_block(int64_t D, int n, const double *__restrict__ a, int
 }  // namespace
 
 fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
-                   hipStream_t s) {
+                   hipStream_t s, double *P) {
     int64_t rpb = std::max<int64_t>(64, (D + 2047) / 2048);
     int nblk = (int)((D + rpb - 1) / rpb);
-    double *P = (double *)workspace((size_t)nblk * n * sizeof(double), 2);
+    if (!P) P = (double *)workspace((size_t)nblk * n * sizeof(double), 2);
     if (!P) return fail(FD_ERR_OOM, "col_dots: workspace");
     hipLaunchKernelGGL(k_coldot_part, dim3(nblk), dim3(256), 0, s, D, n, A, lda, B, ldb, rpb, P);
     FD_HIP(hipGetLastError());

@@ -48,6 +48,8 @@ struct MfArgs {
     const int32_t *__restrict__ off_d;
     const int32_t *__restrict__ idx_d;
     const T *__restrict__ val_d;
+    const uint16_t *__restrict__ hop16_d;  // down hops packed: target | 0x8000 for +tmag
+    T tmag;                                // |element| of every down hop
     T U;
     const T *x; int64_t ldx, bx;
     T *y; int64_t ldy, by;
@@ -66,8 +68,8 @@ __device__ __forceinline__ V fmah(T e, V x, V acc) { return __builtin_elementwis
 // gathered row of hop h is xq + (base + idx * stride) * ldx.  Even hops go
 // to acc0, odd ones to acc1.  SH 1 / 2: lanes 0..LW-1 of the row (LW = 4 /
 // 8, q < LW) load one hop each per round and the row's lanes take them by
-// permute; the rounds run to maxlen, the most hops of any state, so that
-// every lane of a live row takes part in every permute.  SH 0: every lane
+// permute; the rounds run to maxlen, the most hops of any row in the wave
+// (wave_len), so that every lane of a live row takes part in every permute.  SH 0: every lane
 // loads every hop (broadcast).
 template <typename T, typename V, int G, int SH>
 __device__ __forceinline__ void hop_sum(const int32_t *__restrict__ idx, const T *__restrict__ val, int32_t j0,
@@ -124,6 +126,20 @@ __device__ __forceinline__ void hop_sum(const int32_t *__restrict__ idx, const T
             acc0 = fmah(val[j0 + h + 2], ld<V>(xq + (base + (int64_t)idx[j0 + h + 2] * stride) * ldx), acc0);
     }
 }
+// Rounds of the permute hop loop: the most hops of any row in this wave
+// (lanes of a row share len; every lane of the wave must call this).
+template <int G, int SH>
+__device__ __forceinline__ int32_t wave_len(int32_t len, int32_t maxlen) {
+    if constexpr (SH == 0) {
+        return len;
+    } else {
+        int32_t w = len;
+#pragma unroll
+        for (int o = G; o < 64; o <<= 1) w = max(w, __shfl_xor(w, o, 64));
+        return min(w, maxlen);
+    }
+}
+
 template <typename V, bool NT>
 __device__ __forceinline__ V lds(const void *p) {
     if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
@@ -157,19 +173,22 @@ __global__ __launch_bounds__(256) void k_mf_down(MfArgs<T> p) {
     constexpr int RPB = 256 / G;
     const int64_t blk = logical_block<XCD>(blockIdx.x, p.q8);
     const int64_t s = blk * RPB + threadIdx.x / G;
-    if (s >= p.D) return;
+    const bool live = s < p.D;
+    // D < 2^32 (checked at build): 32-bit division, far cheaper than 64-bit
+    const int64_t a = live ? (uint32_t)s / (uint32_t)p.nd : 0, b = live ? s - a * p.nd : 0;
+    const int32_t j0 = live ? p.off_d[b] : 0;
+    const int32_t len = live ? p.off_d[b + 1] - j0 : 0;
+    const int32_t wl = wave_len<G, SH>(len, p.maxd);
+    if (!live) return;
     const int q = threadIdx.x % G;
     const int64_t bnd = blockIdx.y;
     const T *xq = p.x + bnd * p.bx + q * VEC;
-    // D < 2^32 (checked at build): 32-bit division, far cheaper than 64-bit
-    const int64_t a = (uint32_t)s / (uint32_t)p.nd, b = s - a * p.nd;
     V zi = (V)0;
     if constexpr (MODE == 2) zi = lds<V, NT>(p.v + bnd * p.bv + s * p.ldv + q * VEC);
     if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + s * p.ldz + q * VEC);
     const V xi = ld<V>(xq + s * p.ldx);
     V acc0 = (p.U * (T)__popcll(p.mu[a] & p.md[b])) * xi, acc1 = (V)0;
-    const int32_t j0 = p.off_d[b];
-    hop_sum<T, V, G, SH>(p.idx_d, p.val_d, j0, p.off_d[b + 1] - j0, p.maxd, xq, a * p.nd, 1, p.ldx, q, acc0, acc1);
+    hop_sum<T, V, G, SH>(p.idx_d, p.val_d, j0, len, wl, xq, a * p.nd, 1, p.ldx, q, acc0, acc1);
     V r = acc0 + acc1;
     if constexpr (MODE >= 1) r = p.a * r + p.b * xi;
     if constexpr (MODE >= 2) r -= zi;
@@ -188,18 +207,23 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     constexpr int RPB = 256 / G;
     const int64_t blk = logical_block<XCD>(blockIdx.x, p.q8);
     const int64_t l = blk * RPB + threadIdx.x / G;
-    if (l >= p.nlog) return;
     const int64_t per_tile = p.nu * p.tile_b;
-    int64_t tile, a;
-    if (p.nlog < (int64_t(1) << 32)) {  // uniform branch: 32-bit divisions
-        tile = (uint32_t)l / (uint32_t)per_tile;
-        a = (uint32_t)(l - tile * per_tile) / (uint32_t)p.tile_b;
-    } else {
-        tile = l / per_tile;
-        a = (l - tile * per_tile) / p.tile_b;
+    int64_t tile = 0, a = 0;
+    if (l < p.nlog) {
+        if (p.nlog < (int64_t(1) << 32)) {  // uniform branch: 32-bit divisions
+            tile = (uint32_t)l / (uint32_t)per_tile;
+            a = (uint32_t)(l - tile * per_tile) / (uint32_t)p.tile_b;
+        } else {
+            tile = l / per_tile;
+            a = (l - tile * per_tile) / p.tile_b;
+        }
     }
     const int64_t b = tile * p.tile_b + (l - tile * per_tile - a * p.tile_b);
-    if (b >= p.nd) return;
+    const bool live = l < p.nlog && b < p.nd;
+    const int32_t j0 = live ? p.off_u[a] : 0;
+    const int32_t len = live ? p.off_u[a + 1] - j0 : 0;
+    const int32_t wl = wave_len<G, SH>(len, p.maxu);
+    if (!live) return;
     const int64_t s = a * p.nd + b;
     const int q = threadIdx.x % G;
     const int64_t bnd = blockIdx.y;
@@ -214,8 +238,7 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     if constexpr (MODE == 2 || MODE == 5) xi = ld<V>(xq + s * p.ldx);
     const V yi = lds<V, NT>(yr);
     V acc0 = (V)0, acc1 = (V)0;
-    const int32_t j0 = p.off_u[a];
-    hop_sum<T, V, G, SH>(p.idx_u, p.val_u, j0, p.off_u[a + 1] - j0, p.maxu, xq, b, p.nd, p.ldx, q, acc0, acc1);
+    hop_sum<T, V, G, SH>(p.idx_u, p.val_u, j0, len, wl, xq, b, p.nd, p.ldx, q, acc0, acc1);
     V t;
     if constexpr (MODE == 0) t = yi + (acc0 + acc1);
     else t = yi + p.a * (acc0 + acc1);
@@ -225,14 +248,93 @@ __global__ __launch_bounds__(256) void k_mf_up(MfArgs<T> p) {
     if constexpr (MODE == 5) sts<V, NT>(vr, vi + p.cx * xi + p.ct * t);
 }
 
+// pass 1 with the slab staged in LDS (the x-gather of the down hops served
+// from LDS): one block per (up configuration a, 16-byte column slice of the
+// bundle).  The block first issues its rows' streamed loads (z or v), then
+// copies the slab's slice x[a, 0..nd-1, slice] into LDS (one 16-byte load
+// per row), and after one barrier every row (a, b) of the slab takes the
+// diagonal and its down hops from LDS.  The G slices of a slab are dealt to
+// one XCD one after another, so each row of the slab comes from HBM once and
+// from L2 for the other slices.  Down-hop targets and signs come from a
+// packed 16-bit table (all down hops have the same magnitude).  Same
+// arithmetic, in the same order, as k_mf_down: bitwise equal results.
+constexpr int LDS_THREADS = 512;
+constexpr int LDS_RB = 8;  // rows per thread and round (nd <= 4096: one round)
+template <typename T, int VEC, int G, int MODE, bool NT>
+__global__ __launch_bounds__(LDS_THREADS) void k_mf_down_lds(MfArgs<T> p) {
+    typedef typename VT<T, VEC>::type V;
+    extern __shared__ unsigned char smem[];
+    V *xs = reinterpret_cast<V *>(smem);
+    const int64_t blk = blockIdx.x;
+    const int64_t j = blk >> 3;
+    const int64_t a = (j / G) * 8 + (blk & 7);
+    const int sl = (int)(j % G);
+    if (a >= p.nu) return;  // the whole block leaves before its barrier
+    const int64_t bnd = blockIdx.y;
+    const int64_t nd = p.nd, r0 = a * nd;
+    const int t = threadIdx.x;
+    const T *xq = p.x + bnd * p.bx + sl * VEC;
+    const uint64_t ma = p.mu[a];
+    for (int64_t base = 0; base < nd; base += (int64_t)LDS_THREADS * LDS_RB) {
+        V zr[LDS_RB];
+#pragma unroll
+        for (int u = 0; u < LDS_RB; u++) {
+            const int64_t b = base + (int64_t)u * LDS_THREADS + t;
+            zr[u] = (V)0;
+            if (b < nd) {
+                if constexpr (MODE == 2) zr[u] = lds<V, NT>(p.v + bnd * p.bv + (r0 + b) * p.ldv + sl * VEC);
+                if constexpr (MODE >= 3) zr[u] = lds<V, NT>(p.z + bnd * p.bz + (r0 + b) * p.ldz + sl * VEC);
+            }
+        }
+        if (base == 0) {
+            for (int64_t b = t; b < nd; b += LDS_THREADS) xs[b] = ld<V>(xq + (r0 + b) * p.ldx);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < LDS_RB; u++) {
+            const int64_t b = base + (int64_t)u * LDS_THREADS + t;
+            if (b >= nd) break;
+            const V xi = xs[b];
+            V acc0 = (p.U * (T)__popcll(ma & p.md[b])) * xi, acc1 = (V)0;
+            const int32_t h1 = p.off_d[b + 1];
+            int32_t h = p.off_d[b];
+            for (; h + 2 <= h1; h += 2) {
+                const uint32_t e0 = p.hop16_d[h], e1 = p.hop16_d[h + 1];
+                acc0 = fmah((e0 & 0x8000u) ? p.tmag : -p.tmag, xs[e0 & 0x7fffu], acc0);
+                acc1 = fmah((e1 & 0x8000u) ? p.tmag : -p.tmag, xs[e1 & 0x7fffu], acc1);
+            }
+            if (h < h1) {
+                const uint32_t e0 = p.hop16_d[h];
+                acc0 = fmah((e0 & 0x8000u) ? p.tmag : -p.tmag, xs[e0 & 0x7fffu], acc0);
+            }
+            V r = acc0 + acc1;
+            if constexpr (MODE >= 1) r = p.a * r + p.b * xi;
+            if constexpr (MODE >= 2) r -= zr[u];
+            sts<V, NT>(p.y + bnd * p.by + (r0 + b) * p.ldy + sl * VEC, r);
+        }
+    }
+}
+
 template <typename T, int VEC, int G, int MODE, bool XCD, bool NT, int SH>
-fd_status launch_mode(const MfArgs<T> &p, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+fd_status launch_mode(const MfArgs<T> &p, int nbund, int64_t g1, int64_t g2, hipStream_t s, bool lds) {
     MfArgs<T> p1 = p, p2 = p;
     p1.nblk = g1;
     p1.q8 = g1 / 8;
     p2.nblk = g2;
     p2.q8 = g2 / 8;
-    hipLaunchKernelGGL((k_mf_down<T, VEC, G, MODE, XCD, NT, SH>), dim3((unsigned)g1, nbund), dim3(256), 0, s, p1);
+    if (lds) {
+        typedef typename VT<T, VEC>::type V;
+        const size_t sh = (size_t)p.nd * sizeof(V);
+        if (sh > 65536)
+            FD_HIP(hipFuncSetAttribute((const void *)k_mf_down_lds<T, VEC, G, MODE, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+        const int64_t nb1 = (p.nu + 7) / 8 * 8 * G;
+        hipLaunchKernelGGL((k_mf_down_lds<T, VEC, G, MODE, NT>), dim3((unsigned)nb1, nbund), dim3(LDS_THREADS), sh, s,
+                           p1);
+    } else {
+        hipLaunchKernelGGL((k_mf_down<T, VEC, G, MODE, XCD, NT, SH>), dim3((unsigned)g1, nbund), dim3(256), 0, s,
+                           p1);
+    }
     FD_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_mf_up<T, VEC, G, MODE, XCD, NT, SH>), dim3((unsigned)g2, nbund), dim3(256), 0, s, p2);
     FD_HIP(hipGetLastError());
@@ -240,14 +342,14 @@ fd_status launch_mode(const MfArgs<T> &p, int nbund, int64_t g1, int64_t g2, hip
 }
 
 template <typename T, int VEC, int G, bool XCD, bool NT, int SH>
-fd_status launch_m(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+fd_status launch_m(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t g2, hipStream_t s, bool lds) {
     switch (mode) {
-        case 0: return launch_mode<T, VEC, G, 0, XCD, NT, SH>(p, nbund, g1, g2, s);
-        case 1: return launch_mode<T, VEC, G, 1, XCD, NT, SH>(p, nbund, g1, g2, s);
-        case 2: return launch_mode<T, VEC, G, 2, XCD, NT, SH>(p, nbund, g1, g2, s);
-        case 3: return launch_mode<T, VEC, G, 3, XCD, NT, SH>(p, nbund, g1, g2, s);
-        case 4: return launch_mode<T, VEC, G, 4, XCD, NT, SH>(p, nbund, g1, g2, s);
-        case 5: return launch_mode<T, VEC, G, 5, XCD, NT, SH>(p, nbund, g1, g2, s);
+        case 0: return launch_mode<T, VEC, G, 0, XCD, NT, SH>(p, nbund, g1, g2, s, lds);
+        case 1: return launch_mode<T, VEC, G, 1, XCD, NT, SH>(p, nbund, g1, g2, s, lds);
+        case 2: return launch_mode<T, VEC, G, 2, XCD, NT, SH>(p, nbund, g1, g2, s, lds);
+        case 3: return launch_mode<T, VEC, G, 3, XCD, NT, SH>(p, nbund, g1, g2, s, lds);
+        case 4: return launch_mode<T, VEC, G, 4, XCD, NT, SH>(p, nbund, g1, g2, s, lds);
+        case 5: return launch_mode<T, VEC, G, 5, XCD, NT, SH>(p, nbund, g1, g2, s, lds);
     }
     return fail(FD_ERR_INVALID, "matrix-free SpMMV: bad mode");
 }
@@ -255,14 +357,15 @@ fd_status launch_m(const MfArgs<T> &p, int mode, int nbund, int64_t g1, int64_t 
 // hop loop: permute rounds of 8 need 8 lanes per row, rounds of 4 need 4;
 // with fewer lanes the next smaller form runs
 template <typename T, int VEC, int G, bool XCD, bool NT>
-fd_status launch_x(const MfArgs<T> &p, int mode, int sh, int nbund, int64_t g1, int64_t g2, hipStream_t s) {
+fd_status launch_x(const MfArgs<T> &p, int mode, int sh, int nbund, int64_t g1, int64_t g2, hipStream_t s,
+                   bool lds) {
     if constexpr (G >= 8) {
-        if (sh >= 2) return launch_m<T, VEC, G, XCD, NT, 2>(p, mode, nbund, g1, g2, s);
+        if (sh >= 2) return launch_m<T, VEC, G, XCD, NT, 2>(p, mode, nbund, g1, g2, s, lds);
     }
     if constexpr (G >= 4) {
-        if (sh >= 1) return launch_m<T, VEC, G, XCD, NT, 1>(p, mode, nbund, g1, g2, s);
+        if (sh >= 1) return launch_m<T, VEC, G, XCD, NT, 1>(p, mode, nbund, g1, g2, s, lds);
     }
-    return launch_m<T, VEC, G, XCD, NT, 0>(p, mode, nbund, g1, g2, s);
+    return launch_m<T, VEC, G, XCD, NT, 0>(p, mode, nbund, g1, g2, s, lds);
 }
 
 template <typename T, int VEC, int G>
@@ -287,6 +390,8 @@ fd_status launch_mf_t(const DevMatrix &M, const T *val_u, const T *val_d, const 
     p.off_d = M.off_d;
     p.idx_d = M.idx_d;
     p.val_d = val_d;
+    p.hop16_d = M.hop16_d;
+    p.tmag = (T)M.tmag_d;
     p.U = (T)M.U;
     p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;
     p.y = (T *)c.y; p.ldy = c.ldy; p.by = c.by;
@@ -299,12 +404,15 @@ fd_status launch_mf_t(const DevMatrix &M, const T *val_u, const T *val_d, const 
         return fail(FD_ERR_UNSUPPORTED, "matrix-free SpMMV: grid too large");
     const bool xcd = tn.xcd == 1, nt = tn.nontemporal != 0;
     const int sh = tn.shfl;
+    // the LDS-staged down pass: packed down hops and a slab slice that fits
+    // in LDS (nd 16-byte rows, at most 160 KB)
+    const bool lds = tn.lds != 0 && M.hop16_d != nullptr && M.nd * (int64_t)(VEC * sizeof(T)) <= 160 * 1024;
     if (xcd) {
-        if (nt) return launch_x<T, VEC, G, true, true>(p, c.mode, sh, c.nbundles, g1, g2, s);
-        return launch_x<T, VEC, G, true, false>(p, c.mode, sh, c.nbundles, g1, g2, s);
+        if (nt) return launch_x<T, VEC, G, true, true>(p, c.mode, sh, c.nbundles, g1, g2, s, lds);
+        return launch_x<T, VEC, G, true, false>(p, c.mode, sh, c.nbundles, g1, g2, s, lds);
     }
-    if (nt) return launch_x<T, VEC, G, false, true>(p, c.mode, sh, c.nbundles, g1, g2, s);
-    return launch_x<T, VEC, G, false, false>(p, c.mode, sh, c.nbundles, g1, g2, s);
+    if (nt) return launch_x<T, VEC, G, false, true>(p, c.mode, sh, c.nbundles, g1, g2, s, lds);
+    return launch_x<T, VEC, G, false, false>(p, c.mode, sh, c.nbundles, g1, g2, s, lds);
 }
 
 }  // namespace

@@ -90,6 +90,8 @@ struct SpmmvTune {
     int wide = 0;         // 1: 32 bytes per lane (nb >= 16)
     int tile = 0;         // matrix-free Hubbard: down-state tile of the up pass (0: 16)
     int shfl = 2;         // entry loop: 0 plain; 1 permute rounds of 4 (>= 4 lanes per row); 2 of 8 (>= 8)
+    int lpr = 0;          // nb = 1 on CSR: lanes that share a row (4, 8, 16; 0: one lane per row)
+    int lds = 0;          // matrix-free Hubbard: 1 stages each slab's column slice in LDS for the down pass
 };
 
 // One layout serves CSR and SELL: "slot" s of the device format belongs to
@@ -120,6 +122,8 @@ struct DevMatrix {
     float *val_u32 = nullptr, *val_d32 = nullptr;
     int32_t mf_tile = 16;  // default down-state tile of the up pass
     int32_t mf_maxu = 0, mf_maxd = 0;  // most hops of an up / down state
+    uint16_t *hop16_d = nullptr;  // down hops packed (target | 0x8000 for +tmag_d), or null
+    double tmag_d = 0;            // |element| shared by every down hop
 };
 
 }  // namespace fd
@@ -171,6 +175,11 @@ struct BatchDev {
     int64_t D = 0;
     uint32_t *ptr = nullptr, *col = nullptr;  // D + 1, nnz (columns already shifted)
     int32_t maxlen = 0;                       // longest row
+    // launch shape per dtype and log2(nb) (fd_batch_autotune): rows per XCD
+    // chunk (a power of two, 0: 1024) and the entry loop (1: permute rounds
+    // of 4 entries, 2: of 8 with 8 or more lanes per row)
+    int32_t chunk[2][7] = {};
+    int8_t sh[2][7] = {{2, 2, 2, 2, 2, 2, 2}, {2, 2, 2, 2, 2, 2, 2}};
     double *val64 = nullptr;
     float *val32 = nullptr;
     uint16_t *inst = nullptr;  // row -> instance
@@ -249,9 +258,10 @@ fd_status symmetrize(int n, double *H, hipStream_t s);
 // Lehmann pencil (B, S) from the three Gram matrices of V and W = A V
 fd_status lehmann_pencil(int n, const double *G2, const double *G1, const double *G0, double rho, double *B,
                          double *S, hipStream_t s);
-// out[off + j] = sum_i A[i][j] B[i][j] for j < n (two-stage, fixed order)
+// out[off + j] = sum_i A[i][j] B[i][j] for j < n (two-stage, fixed order);
+// P: the partial sums (at most 2048 n doubles) or nullptr for the workspace
 fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
-                   hipStream_t s);
+                   hipStream_t s, double *P = nullptr);
 fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s);
 fd_status copy_rows(int64_t D, int64_t row_bytes, const void *src, int64_t src_ld_bytes, void *dst,
                     int64_t dst_ld_bytes, hipStream_t s);

@@ -78,16 +78,13 @@ __device__ __forceinline__ void sts(void *p, V x) {
     else *reinterpret_cast<V *>(p) = x;
 }
 
-template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, int SH>
-__global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
-    typedef typename VecT<T, VEC>::type V;
-    constexpr int RPB = 256 / G;
-    // Row groups of this block.  order 0: groups [b iters, (b+1) iters) of
-    // logical block b; order 1: grid-stride, so that the blocks running at a
-    // time cover one compact window of rows.  With xcd != 0 the hardware's
-    // round-robin of workgroups over the 8 XCDs is undone: XCD x owns the
-    // x-th eighth of the groups.
-    int64_t g0, g1, gstep;
+// Row groups of this block.  order 0: groups [b iters, (b+1) iters) of
+// logical block b; order 1: grid-stride, so that the blocks running at a
+// time cover one compact window of rows.  With xcd != 0 the hardware's
+// round-robin of workgroups over the 8 XCDs is undone: XCD x owns the
+// x-th eighth of the groups.  g1 <= g0 when the block has no work.
+template <typename T>
+__device__ __forceinline__ void block_groups(const KArgs<T> &p, int64_t &g0, int64_t &g1, int64_t &gstep) {
     if (p.order == 0) {
         int64_t blk = blockIdx.x;
         if (p.xcd == 1) {
@@ -99,10 +96,13 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             const int64_t j = blockIdx.x >> 3;
             blk = ((j / p.sg) * 8 + (blockIdx.x & 7)) * p.sg + (j % p.sg);
         }
-        if (blk >= p.nblk) return;
+        gstep = 1;
+        if (blk >= p.nblk) {
+            g0 = g1 = 0;
+            return;
+        }
         g0 = blk * p.iters;
         g1 = min(p.ngroups, g0 + p.iters);
-        gstep = 1;
     } else if (p.xcd) {
         const int64_t per = (p.ngroups + 7) >> 3;
         const int64_t x = blockIdx.x & 7;
@@ -114,6 +114,14 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
         g1 = p.ngroups;
         gstep = gridDim.x;
     }
+}
+
+template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, int SH>
+__global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
+    typedef typename VecT<T, VEC>::type V;
+    constexpr int RPB = 256 / G;
+    int64_t g0, g1, gstep;
+    block_groups(p, g0, g1, gstep);
     const int64_t bnd = blockIdx.y;
     const T *x = p.x + bnd * p.bx;
     T *y = p.y + bnd * p.by;
@@ -122,12 +130,28 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     const uint32_t step = 1u << p.cshift;
     for (int64_t g = g0; g < g1; g += gstep) {
         const int64_t s = g * RPB + grp;
-        if (s >= p.nslots) break;
-        const int64_t c = s >> p.cshift;
-        const uint32_t p0 = p.ptr[c];
-        const uint32_t len = (p.ptr[c + 1] - p0) >> p.cshift;
-        const uint32_t base = p0 + (uint32_t)(s & (step - 1));
-        const int64_t row = PERM ? (int64_t)p.perm[s] : s;
+        // every lane of the block reaches this point (the loop bounds are
+        // per block), so the wave can agree on its longest row below
+        const bool in = s < p.nslots;
+        uint32_t len = 0, base = 0;
+        int64_t row = -1;
+        if (in) {
+            const int64_t c = s >> p.cshift;
+            const uint32_t p0 = p.ptr[c];
+            len = (p.ptr[c + 1] - p0) >> p.cshift;
+            base = p0 + (uint32_t)(s & (step - 1));
+            row = PERM ? (int64_t)p.perm[s] : s;
+        }
+        if (row < 0) len = 0;
+        // load rounds of the permute loop: the longest row of this wave
+        // (lanes of a row share len, so only the rows are compared)
+        uint32_t wlen = len;
+        if constexpr (SH != 0) {
+#pragma unroll
+            for (int o = G; o < 64; o <<= 1) wlen = max(wlen, (uint32_t)__shfl_xor((int)wlen, o, 64));
+            wlen = min(wlen, (uint32_t)p.maxlen);
+        }
+        if (!in) break;
         if (row < 0) continue;  // padding slot past D
         // streamed operands first: their latency overlaps the gather chain
         V zi = (V)0, vi = (V)0;
@@ -150,13 +174,13 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             // lanes of the row take them by cross-lane permute, 4 at a time,
             // and the gathers go out together (the compiler issues all LW
             // gathers of a round before their FMAs).  The rounds run to the
-            // longest row of the matrix, so every lane of a row takes part in
+            // longest row of the wave, so every lane of a row takes part in
             // every permute.
             constexpr int LW = SH == 2 ? 8 : 4;
             constexpr int GW = 4;
             static_assert(G >= LW, "a load round needs LW lanes per row");
             const int rbase = (int)(threadIdx.x & 63) - q;
-            for (int j0 = 0; j0 < p.maxlen; j0 += LW) {
+            for (int j0 = 0; j0 < (int)wlen; j0 += LW) {
                 const uint32_t jj = (uint32_t)(j0 + q);
                 uint32_t cm = 0;
                 T am = (T)0;
@@ -241,7 +265,64 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     }
 }
 
-template <typename T, int VEC, int G>
+// One vector (nb = 1), CSR: LPR lanes share a row.  Lane q takes entries
+// q, q + LPR, ... of the row, so the row's column indices and values are
+// read by consecutive lanes (coalesced), and the LPR partial sums are
+// added by a butterfly of cross-lane exchanges; the row's first lane then
+// applies the step's update.  (With one lane per row, every lane reads its
+// own row's entries, scattered across memory.)
+template <typename T, int LPR, int MODE, bool NT>
+__global__ __launch_bounds__(256) void k_spmv_vec(KArgs<T> p) {
+    constexpr int RPB = 256 / LPR;
+    int64_t g0, g1, gstep;
+    block_groups(p, g0, g1, gstep);
+    const int64_t bnd = blockIdx.y;
+    const T *x = p.x + bnd * p.bx;
+    T *y = p.y + bnd * p.by;
+    const int grp = threadIdx.x / LPR;
+    const int q = threadIdx.x % LPR;
+    for (int64_t g = g0; g < g1; g += gstep) {
+        const int64_t s = g * RPB + grp;
+        // every lane of the block reaches the exchanges below (the loop
+        // bounds are per block); lanes of a row share s
+        const bool in = s < p.nslots;
+        T acc = (T)0;
+        if (in) {
+            const uint32_t k1 = p.ptr[s + 1];
+            for (uint32_t k = p.ptr[s] + q; k < k1; k += LPR) acc = fma(p.val[k], x[(int64_t)p.col[k] * p.ldx], acc);
+        }
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (!in) break;
+        if (q != 0) continue;
+        const int64_t row = s;
+        T *yr = y + row * p.ldy;
+        if constexpr (MODE == 0) {
+            sts<T, NT>(yr, acc);
+        } else {
+            const T xi = x[row * p.ldx];
+            T t = p.a * acc + p.b * xi;
+            if constexpr (MODE == 1) {
+                sts<T, NT>(yr, t);
+            } else {
+                T *vr = p.v + bnd * p.bv + row * p.ldv;
+                if constexpr (MODE == 2) {
+                    const T vi = lds<T, NT>(vr);
+                    t -= vi;
+                    sts<T, NT>(yr, t);
+                    sts<T, NT>(vr, p.cv * vi + p.cx * xi + p.ct * t);
+                } else {
+                    t -= lds<T, NT>(p.z + bnd * p.bz + row * p.ldz);
+                    sts<T, NT>(yr, t);
+                    if constexpr (MODE == 3) sts<T, NT>(vr, lds<T, NT>(vr) + p.ct * t);
+                    if constexpr (MODE == 5) sts<T, NT>(vr, lds<T, NT>(vr) + p.cx * xi + p.ct * t);
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int VEC, int G, bool VROW = false>
 fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStream_t s) {
     KArgs<T> p;
     p.ptr = M.ptr;
@@ -294,6 +375,26 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     dim3 grid((unsigned)gx, (unsigned)c.nbundles), block(256);
     const bool perm = M.perm != nullptr;
     const bool nt = tn.nontemporal != 0;
+    if constexpr (VROW) {
+        if (perm || M.cshift != 0) return fail(FD_ERR_INVALID, "SpMMV: the lane-shared row loop needs CSR");
+#define FD_V(MODE)                                                                                  \
+    do {                                                                                            \
+        if (nt) hipLaunchKernelGGL((k_spmv_vec<T, G, MODE, true>), grid, block, 0, s, p);           \
+        else hipLaunchKernelGGL((k_spmv_vec<T, G, MODE, false>), grid, block, 0, s, p);             \
+    } while (0)
+        switch (c.mode) {
+            case 0: FD_V(0); break;
+            case 1: FD_V(1); break;
+            case 2: FD_V(2); break;
+            case 3: FD_V(3); break;
+            case 4: FD_V(4); break;
+            case 5: FD_V(5); break;
+            default: return fail(FD_ERR_INVALID, "SpMMV: bad mode");
+        }
+#undef FD_V
+        FD_HIP(hipGetLastError());
+        return FD_OK;
+    }
     // entry loop: 0 plain, 1 permute rounds of 4 entries, 2 load rounds of 8;
     // each form needs its lanes per row, else the next smaller one is used
     const int sh = (tn.shfl >= 2 && G >= 8) ? 2 : (tn.shfl != 0 && G >= 4 ? 1 : 0);
@@ -354,6 +455,9 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
         {0, 2, 1, 512, 1, 0, 0, 1},  {0, 2, 1, 1024, 1, 0, 0, 1}, {0, 2, 1, 2048, 1, 0, 0, 1},
         {0, 2, 1, 8192, 1, 0, 0, 1}, {0, 2, 1, 1024, 1, 1, 0, 0}, {0, 2, 1, 4096, 1, 1, 0, 0},
         {0, 2, 1, 2048, 1, 0, 0, 0}, {0, 2, 1, 8192, 1, 0, 0, 0},
+        // one vector on CSR: 4, 8 or 16 lanes per row
+        {0, 2, 1, 1024, 1, 0, 0, 0, 4}, {0, 2, 1, 1024, 1, 0, 0, 0, 8}, {0, 2, 1, 8192, 1, 0, 0, 0, 8},
+        {0, 2, 1, 1024, 1, 0, 0, 0, 16}, {0, 2, 4, 1024, 1, 0, 0, 0, 8},
     };
     // matrix-free Hubbard: down-state tile of the up pass, XCD remap on/off
     // matrix-free Hubbard: xcd (remap), nontemporal, wide, tile (down states
@@ -364,6 +468,9 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
         {0, 1, 1, 0, 0, 0, 16, 1}, {0, 0, 1, 0, 0, 0, 64, 1},  {0, 1, 1, 0, 1, 1, 16, 1},
         {0, 0, 1, 0, 1, 0, 64, 2}, {0, 1, 1, 0, 1, 0, 16, 2},  {0, 0, 1, 0, 1, 0, 64, 0},
         {0, 1, 1, 0, 1, 0, 16, 0},
+        // the down pass with each slab's column slice staged in LDS
+        {0, 1, 1, 0, 1, 0, 16, 1, 0, 1}, {0, 1, 1, 0, 1, 0, 64, 1, 0, 1}, {0, 0, 1, 0, 1, 0, 64, 1, 0, 1},
+        {0, 1, 1, 0, 1, 0, 16, 2, 0, 1}, {0, 1, 1, 0, 1, 0, 4, 1, 0, 1},
     };
     const SpmmvTune *cb = M.matfree ? mf_cands : cands;
     const SpmmvTune *ce = M.matfree ? mf_cands + sizeof(mf_cands) / sizeof(mf_cands[0])
@@ -386,6 +493,7 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
     for (const SpmmvTune *tp = cb; tp != ce; ++tp) {
         const SpmmvTune &t = *tp;
         if (t.wide && nb < 16) continue;
+        if (t.lpr && (nb != 1 || M.cshift != 0 || M.perm)) continue;
         M.tune[di][lg] = t;
         M.tuned[di][lg] = true;
         st = launch_spmmv(M, dt, c, s);  // warm-up
@@ -427,6 +535,18 @@ fd_status launch_spmmv(const DevMatrix &M, fd_dtype dt, const SpmmvCall &c, hipS
             if (c.nb == 64) return launch_t<float, 8, 8>(M, M.val32, c, s);
             if (c.nb == 32) return launch_t<float, 8, 4>(M, M.val32, c, s);
             if (c.nb == 16) return launch_t<float, 8, 2>(M, M.val32, c, s);
+        }
+    }
+    if (c.nb == 1 && tn.lpr > 0 && M.cshift == 0 && !M.perm) {
+        // one vector: lpr lanes per row (vector-CSR loop)
+        if (dt == FD_F64) {
+            if (tn.lpr == 4) return launch_t<double, 1, 4, true>(M, M.val64, c, s);
+            if (tn.lpr == 8) return launch_t<double, 1, 8, true>(M, M.val64, c, s);
+            if (tn.lpr == 16) return launch_t<double, 1, 16, true>(M, M.val64, c, s);
+        } else {
+            if (tn.lpr == 4) return launch_t<float, 1, 4, true>(M, M.val32, c, s);
+            if (tn.lpr == 8) return launch_t<float, 1, 8, true>(M, M.val32, c, s);
+            if (tn.lpr == 16) return launch_t<float, 1, 16, true>(M, M.val32, c, s);
         }
     }
     if (dt == FD_F64) {

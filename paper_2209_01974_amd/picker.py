@@ -27,6 +27,7 @@ import time
 import numpy as np
 
 from . import FD_OK, MLP_NPARAMS, build_matrix, kpm_moments, mlp_adam, mlp_forward, mlp_grad, pick_degree, solve
+from . import window_count as kpm_count
 
 FACTORS = np.array([0.5, 0.71, 1.0, 1.41, 2.0])
 NT, NS, NB = 8, 32, 16
@@ -70,9 +71,9 @@ def instance(rng, big: bool, max_degree: int, strict: bool = False):
 
 
 def window_count(m, wl: float, wh: float, nmom: int = 1024, nvec: int = 16, seed: int = 5) -> float:
-    """KPM estimate of the number of eigenvalues in [wl, wh]: Jackson-damped
-    Chebyshev moments of nvec random N(0, 1) vectors (stochastic trace),
-    integrated against the window's indicator."""
+    """KPM estimate of the number of eigenvalues in [wl, wh]: Chebyshev
+    moments of nvec random N(0, 1) vectors (stochastic trace), integrated
+    against the window's Jackson-damped indicator (fd_kpm_count)."""
     import torch
     lo, hi = m.lam_lo, m.lam_hi
     alpha, beta = 2.0 / (hi - lo), -(hi + lo) / (hi - lo)
@@ -80,23 +81,16 @@ def window_count(m, wl: float, wh: float, nmom: int = 1024, nvec: int = 16, seed
     g.manual_seed(seed)
     R = torch.randn((m.D, nvec), generator=g, dtype=torch.float64, device="cuda")
     mu = kpm_moments(m, R, nmom, alpha, beta)
-    n1 = nmom + 1.0
-    k = np.arange(nmom)
-    q = np.pi / n1
-    jack = ((n1 - k) * np.cos(k * q) + np.sin(k * q) / np.tan(q)) / n1
-    ta, tb = np.arccos(np.clip(alpha * wl + beta, -1, 1)), np.arccos(np.clip(alpha * wh + beta, -1, 1))
-    c = np.where(k == 0, (ta - tb) / np.pi, 2.0 * (np.sin(k * ta) - np.sin(k * tb)) / (np.maximum(k, 1) * np.pi))
-    return float(m.D * np.dot(c, jack * mu) / mu[0])
+    a = min(1.0, max(-1.0, alpha * wl + beta))
+    return kpm_count(mu, m.D, a, max(a, min(1.0, alpha * wh + beta)))
 
 
 def window_count_from_features(feat, D: int) -> float:
     """KPM estimate of the eigenvalue count in the scaled window [a, b] = feat[64:66]
-    from the 64 Jackson-damped moments feat[:64] (g_k mu_k)."""
-    a, b = float(feat[64]), float(feat[65])
-    k = np.arange(64)
-    ta, tb = np.arccos(np.clip(a, -1, 1)), np.arccos(np.clip(b, -1, 1))
-    c = np.where(k == 0, (ta - tb) / np.pi, 2.0 * (np.sin(k * ta) - np.sin(k * tb)) / (np.maximum(k, 1) * np.pi))
-    return float(D * np.dot(c, feat[:64].astype(np.float64)))
+    from the 64 Jackson-damped moments feat[:64] (g_k mu_k), by fd_kpm_count."""
+    a = min(1.0, max(-1.0, float(feat[64])))
+    b = max(a, min(1.0, float(feat[65])))
+    return kpm_count(np.asarray(feat[:64], np.float64), D, a, b, damped=True)
 
 
 def run(m, win, degree, picker=None, max_iter=30):

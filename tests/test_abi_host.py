@@ -286,3 +286,28 @@ def test_hubbard14_rcm_labels_shrink_up_hop_distance():
         assert (np.abs(col.astype(np.int64) - rows) // 3432).max() == bound
         del rowptr, col, rows
         m.free()
+
+
+def test_kpm_count_host_call():
+    """fd_kpm_count on exact-trace moments (oracle, Anderson L=5): the
+    Jackson-damped count of a window matches the dense eigenvalue count to
+    within the kernel's broadening, and feeding damped moments with kind 2
+    gives the same number as plain moments with kind 0; mu_0 <= 0 is
+    rejected."""
+    A = O.anderson(5, 1.0, 4.0, 3)
+    lam = np.linalg.eigvalsh(A.dense())
+    lo, hi = O.gershgorin(A)
+    alpha, beta = O.scaling(lo, hi)
+    nmom = 600
+    mu = O.kpm_moments(A, np.sqrt(A.D) * np.eye(A.D), nmom, alpha, beta)
+    for wl, wh in ((-1.0, 1.0), (-3.0, 0.5), (2.0, 6.0)):
+        a, b = alpha * wl + beta, alpha * wh + beta
+        est = fd.window_count(mu, A.D, a, b)
+        true = np.sum((lam >= wl) & (lam <= wh))
+        assert abs(est - true) <= 2.0, (wl, wh, est, true)
+        g = np.array([O.jackson(nmom - 1, k) for k in range(nmom)])
+        est2 = fd.window_count(g * mu, A.D, a, b, damped=True)
+        assert abs(est2 - est) <= 1e-12 * A.D
+    with pytest.raises(fd.FDError) as e:
+        fd.window_count(np.zeros(8), 10, -0.5, 0.5)
+    assert e.value.status == fd.FD_ERR_INVALID

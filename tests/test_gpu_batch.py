@@ -256,3 +256,47 @@ def test_solve_batch_rank_deficient_start_block(ortho):
         pool = ev if hi <= lo else ev[(ev >= lo) & (ev <= hi)]
         want = np.sort(pool[np.argsort(np.abs(pool - tau), kind="stable")[:8]])
         assert np.abs(r.evals[i] - want).max() <= 1e-10 * r.stats[i]["norm_H"], i
+
+
+def test_batch_autotune_keeps_results_bitwise(batch):
+    """The batched autotuner only chooses the XCD chunk and the permute
+    round width, which do not change how a row is summed: the filter is
+    bitwise equal before and after tuning, and the chosen shape is one of
+    the candidates."""
+    b, As = batch
+    degrees = [23, 7, 0, 2, 40]
+    alpha, beta, mu = _filter_setup(b, As, degrees, 0)
+    V = start_block(b.D, 32, 3)
+    outs = []
+    for tune in (False, True):
+        if tune:
+            nb, chunk, sh = fd.batch_autotune(b, "f64", 16)
+            assert nb == 16 and chunk in (256, 512, 1024, 2048, 4096, 8192, 16384) and sh in (1, 2)
+        Vd = dev(V)
+        W1 = torch.empty_like(Vd)
+        W2 = torch.empty_like(Vd)
+        fd.batch_filter(b, Vd, mu, degrees, alpha, beta, W1, W2, 16)
+        torch.cuda.synchronize()
+        outs.append(Vd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    nb, _, _ = fd.batch_autotune(b, "f64", 0)
+    assert nb in (8, 16, 32, 64)
+
+
+def test_solve_batch_picks_the_bundle_width():
+    """params nb = 0: the library times the batched step for the widths
+    that divide N_s and uses the fastest; the answer is the one of nb = 16."""
+    kws = [dict(model="anderson", L=8, t=1.0, W=5.0, seed=2), dict(model="hubbard", L=6, n_up=3, n_dn=3, t=1.0,
+                                                                 U=4.0)]
+    mats = [fd.build_matrix(**kw) for kw in kws]
+    b = fd.Batch(mats)
+    V0 = start_block(b.D, 64, 11)
+    res = {}
+    for nb in (16, 0):
+        params = [dict(tau_lo=0.0, tau_hi=0.0, n_target=8, n_search=64, nb=nb, degree=300, max_iter=100, tol=1e-9)
+                  for _ in kws]
+        res[nb] = fd.solve_batch(b, params, V0=V0)
+        assert res[nb].status == fd.FD_OK
+    assert res[0].bstats["nb"] in (8, 16, 32, 64) and res[16].bstats["nb"] == 16
+    for i in range(2):
+        assert np.abs(res[0].evals[i] - res[16].evals[i]).max() <= 1e-10 * res[16].stats[i]["norm_H"]

@@ -28,6 +28,11 @@ pytestmark = pytest.mark.gpu
 import paper_2209_01974_amd as fd  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hubbard12_fd_oracle.txt")
+# one line per FD iteration appended here while the solves run, so that a
+# long test shows its progress
+_OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+os.makedirs(_OUT, exist_ok=True)
+os.environ["FD_TRACE_FILE"] = os.path.join(_OUT, "fd_trace_hubbard_tests.jsonl")
 NT, NS, NB, DEG = 64, 256, 32, 800
 
 

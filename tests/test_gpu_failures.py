@@ -29,16 +29,19 @@ def test_nan_in_start_block_is_a_breakdown():
 
 
 def test_allocation_failure_is_reported_and_recoverable():
+    """Hubbard L=8, 16 pairs in [-0.5, 0.5], N_s = 128 (the 4900 x 128 search
+    block needs 5 MB): with a 1 MB allocation limit the solve fails with
+    FD_ERR_OOM; with the limit lifted the same call converges."""
     m = hub8()
-    V0 = start_block(m.D, 64, 0)
-    fd.debug_alloc_limit(1 << 20)  # the 4900 x 64 search block needs 2.5 MB
+    V0 = start_block(m.D, 128, 0)
+    fd.debug_alloc_limit(1 << 20)
     try:
         with pytest.raises(fd.FDError) as e:
-            fd.solve(m, -0.5, 0.5, 8, 64, 16, 60, max_iter=10, V0=V0)
+            fd.solve(m, -0.5, 0.5, 16, 128, 16, 100, max_iter=10, V0=V0)
         assert e.value.status == fd.FD_ERR_OOM
     finally:
         fd.debug_alloc_limit(0)
-    r = fd.solve(m, -0.5, 0.5, 8, 64, 16, 60, max_iter=60, V0=V0)
+    r = fd.solve(m, -0.5, 0.5, 16, 128, 16, 100, max_iter=80, V0=V0)
     assert r.status == fd.FD_OK
     with pytest.raises(fd.FDError) as e:
         fd.debug_alloc_limit(-1)
@@ -54,14 +57,17 @@ def test_stagnation_stops_before_max_iter():
     m = fd.build_matrix("diagonal", diag=lam)
     r = fd.solve(m, -0.5, 0.5, 10, 20, 4, 60, max_iter=500, tol=1e-9, V0=start_block(1000, 20, 0))
     assert r.status == fd.FD_ERR_NOT_CONVERGED
-    assert 10 <= r.stats["iters"] < 200
+    assert 30 <= r.stats["iters"] < 200
 
 
 def test_cholqr2_falls_back_on_an_ill_conditioned_block():
     """kappa(V) = 1e10: Cholesky of V^t V (kappa 1e20) loses the small
     directions; the relative pivot test and the near-identity test of the
-    second pass send the block to SVQB2, which returns it orthonormal with
-    the same span (up to the conditioning)."""
+    second pass send the block to SVQB2, which returns it orthonormal.  The
+    span is kept for the directions the Gram matrix still resolves: the GPU
+    eigensolver is accurate to about 3e-13 of the Gram matrix's norm, so a
+    direction with singular value s is kept to about 3e-13 / s^2; the
+    first 10 (s >= 0.01) to 1e-6."""
     D, ns = 6000, 48
     U, _ = np.linalg.qr(start_block(D, ns, 3))
     V = U @ np.diag(np.logspace(0, -10, ns)) @ np.linalg.qr(start_block(ns, ns, 4))[0]
@@ -70,4 +76,4 @@ def test_cholqr2_falls_back_on_an_ill_conditioned_block():
     Q = Vd.cpu().numpy()
     assert np.abs(Q.T @ Q - np.eye(ns)).max() <= 1e-13
     # the well-conditioned part of the span is kept
-    assert np.linalg.norm(U[:, :20] - Q @ (Q.T @ U[:, :20])) <= 1e-6
+    assert np.linalg.norm(U[:, :10] - Q @ (Q.T @ U[:, :10])) <= 1e-6

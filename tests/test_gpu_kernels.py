@@ -525,3 +525,37 @@ def test_solve_uses_lanczos_norm_and_interval():
         assert r.resid.max() <= 1e-9 * normH
         ro = O.fd_solve(A, V0, -0.5, 0.5, 16, 100, 1e-9, max_iter=80, interval=interval)
         assert ro.converged and np.abs(ro.evals - r.evals).max() <= 1e-10 * normH
+
+
+@pytest.mark.parametrize("lpr", [4, 8, 16])
+@pytest.mark.parametrize("name", ["hub8", "and13", "and12t"])
+def test_one_vector_lane_shared_rows(lpr, name):
+    """nb = 1 on CSR with lpr lanes per row (coalesced entry loads, partial
+    sums added across lanes): SpMMV within 1e-12 of the oracle and bit-exact
+    on integer data when the matrix is integer (Hubbard); every step form of the filter (first steps, V every
+    other step, an odd last step) within 1e-12 in FP64 and at FP32 rounding
+    in FP32."""
+    m, A = build(name, "csr", 1, 1)
+    try:
+        fd.spmmv_tune(lpr=lpr)
+        X = start_block(A.D, 1, 3)
+        Y = torch.empty((A.D, 1), dtype=torch.float64, device="cuda")
+        fd.spmmv(m, dev(X), Y)
+        assert relerr(Y.cpu().numpy(), O.spmmv(A, X)) <= 1e-12
+        if np.array_equal(A.val, np.round(A.val)):  # integer matrix: every order of the sum is exact
+            Xi = int_block(A.D, 1, 4)
+            fd.spmmv(m, dev(Xi), Y)
+            assert np.array_equal(Y.cpu().numpy(), O.spmmv(A, Xi))
+        lo, hi = O.gershgorin(A)
+        alpha, beta = O.scaling(lo, hi)
+        for deg in (2, 3, 10, 11):
+            mu = O.cheb_coeffs(0, -0.3, 0.25, deg)
+            V0 = start_block(A.D, 4, 5)
+            ref = O.cheb_filter(A, V0, mu, alpha, beta)
+            for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+                V = dev(V0, dt)
+                W1, W2 = torch.empty_like(V), torch.empty_like(V)
+                fd.cheb_filter(m, V, mu, alpha, beta, W1, W2, 1)
+                assert relerr(V.cpu().double().numpy(), ref) <= tol, (deg, dt)
+    finally:
+        fd.spmmv_tune()

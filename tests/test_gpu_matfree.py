@@ -122,12 +122,15 @@ def test_matfree_filter_fp32_error():
     assert relerr(Vd.cpu().double().numpy(), ref) <= 100 * 2.0 ** -24 * 10
 
 
-@pytest.mark.parametrize("xcd,nt,tile,wide,shfl", [(1, 1, 0, 0, 2), (0, 0, 1, 0, 2), (1, 0, 5, 0, 2),
-                                                    (0, 1, 1000, 0, 2), (1, 1, 2, 0, 2), (0, 1, 64, 1, 2),
-                                                    (1, 1, 3, 1, 2), (0, 1, 16, 0, 0), (1, 0, 7, 1, 0)])
-def test_matfree_launch_shapes_bitwise_equal(xcd, nt, tile, wide, shfl):
-    """Tile, XCD remap, lane width and hop loop (permute or broadcast) only
-    change the order rows are visited in: bitwise equal results."""
+@pytest.mark.parametrize("xcd,nt,tile,wide,shfl,lds", [(1, 1, 0, 0, 2, 0), (0, 0, 1, 0, 2, 0), (1, 0, 5, 0, 2, 0),
+                                                        (0, 1, 1000, 0, 2, 0), (1, 1, 2, 0, 2, 0), (0, 1, 64, 1, 2, 0),
+                                                        (1, 1, 3, 1, 2, 0), (0, 1, 16, 0, 0, 0), (1, 0, 7, 1, 0, 0),
+                                                        (1, 1, 0, 0, 2, 1), (0, 0, 5, 0, 1, 1), (0, 1, 16, 1, 2, 1),
+                                                        (1, 1, 3, 0, 0, 1)])
+def test_matfree_launch_shapes_bitwise_equal(xcd, nt, tile, wide, shfl, lds):
+    """Tile, XCD remap, lane width, hop loop (permute or broadcast) and the
+    LDS-staged down pass only change the order rows are visited in and
+    where the gathered rows come from: bitwise equal results."""
     m, A = build("hub9")
     X = dev(start_block(A.D, 16, 1))
     Y0 = torch.empty_like(X)
@@ -140,7 +143,7 @@ def test_matfree_launch_shapes_bitwise_equal(xcd, nt, tile, wide, shfl):
     W2 = torch.empty_like(Va)
     fd.cheb_filter(m, Va, mu, alpha, beta, W1, W2, 16)
     try:
-        fd.spmmv_tune(0, xcd, 1, 1024, nt, wide, tile, shfl)
+        fd.spmmv_tune(0, xcd, 1, 1024, nt, wide, tile, shfl, 0, lds)
         Y1 = torch.empty_like(X)
         fd.spmmv(m, X, Y1)
         Vb = dev(V0)
