@@ -233,6 +233,23 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t ncol, const double *R_dev, int64_t
                          double alpha, double beta, double *W1_dev, double *W2_dev, int64_t ldw,
                          double *mu_host, void *stream);
 
+/* fd_kpm_moments for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same moments from the same kernels, with the two device buffers the
+ * call needs beyond its arguments -- the per-column moment dots (nmom x 64
+ * doubles) and the partial sums of the column reductions (2048 x 64) --
+ * placed in a static device array of 4 MiB that the library holds on each
+ * device it runs on until the process ends (no hipMalloc or hipFree on any
+ * path of this call).  nmom must be even and at most
+ * FD_KPM_NOALLOC_MAX_MOMENTS; larger: FD_ERR_INVALID before any work.
+ * Every call on one device shares that array and leaves it dirty: calls
+ * that overlap on one device (two host threads, or two streams in flight)
+ * race and give wrong moments.  Synchronizes, as fd_kpm_moments.           */
+#define FD_KPM_NOALLOC_MAX_MOMENTS 4096
+fd_status fd_kpm_moments_noalloc(fd_matrix m, int32_t ncol, const double *R_dev, int64_t ldr, int32_t nmom,
+                                 double alpha, double beta, double *W1_dev, double *W2_dev, int64_t ldw,
+                                 double *mu_host, void *stream);
+
 /* KPM estimate of the number of eigenvalues in the scaled window [a, b]
  * (-1 <= a <= b <= 1) from nmom moments (host): D sum_k c_k mu_k / mu_0 with
  * c_k the window's coefficients (fd_cheb_coeffs kind 0, Jackson-damped for

@@ -956,6 +956,21 @@ fd_status fd_kpm_moments(fd_matrix m, int32_t ncol, const double *R, int64_t ldr
     return kpm_all(m, ncol, R, ldr, nmom, alpha, beta, W1, W2, ldw, mu, (hipStream_t)stream, nullptr, nullptr);
 }
 
+// The moments with the two device buffers carved out of the static scratch
+// (no allocation): nmom x 64 doubles of moment dots, then the partial sums
+// of the column reductions (at most 2048 x 64 doubles).
+fd_status fd_kpm_moments_noalloc(fd_matrix m, int32_t ncol, const double *R, int64_t ldr, int32_t nmom,
+                                 double alpha, double beta, double *W1, double *W2, int64_t ldw, double *mu,
+                                 void *stream) {
+    const size_t need = ((size_t)nmom * 64 + (size_t)2048 * 64) * sizeof(double);
+    if (nmom < 2 || nmom > FD_KPM_NOALLOC_MAX_MOMENTS || need > kScratchBytes)
+        return fail(FD_ERR_INVALID, "fd_kpm_moments_noalloc: nmom must be even and in [2, 4096]");
+    void *base = nullptr;
+    FD_TRY(scratch_ptr(&base));
+    double *dots = (double *)base, *part = dots + (size_t)nmom * 64;
+    return kpm_all(m, ncol, R, ldr, nmom, alpha, beta, W1, W2, ldw, mu, (hipStream_t)stream, dots, part);
+}
+
 fd_status fd_kpm_count(const double *mu, int32_t nmom, int32_t damped, int64_t D, double a, double b,
                        double *count) {
     if (!mu || !count || nmom < 1 || D < 0 || (damped != 0 && damped != 1))

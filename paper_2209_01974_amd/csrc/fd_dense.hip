@@ -948,6 +948,32 @@ fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *d
     return FD_OK;
 }
 
+// ------------------------------------------------ static device scratch ----
+// A fixed array for the entry points that must not allocate (each device
+// the library runs on holds its own copy until the process ends).  Host code
+// never names the array in a kernel argument or a copy: its address on the
+// current device comes from hipGetSymbolAddress, resolved once per device.
+namespace {
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
+fd_status scratch_ptr(void **out) {
+    int dev = 0;
+    FD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(FD_ERR_UNSUPPORTED, "scratch: device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch: symbol address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FD_OK;
+}
+
 // ------------------------------------------------------------- Lanczos ----
 // Vectors of the Lanczos basis are stored one after another (vector t at
 // Q + t * D, each contiguous), so the SpMV on one of them and the

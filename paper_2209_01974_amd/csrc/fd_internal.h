@@ -262,6 +262,10 @@ fd_status lehmann_pencil(int n, const double *G2, const double *G1, const double
 // P: the partial sums (at most 2048 n doubles) or nullptr for the workspace
 fd_status col_dots(int64_t D, int n, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
                    hipStream_t s, double *P = nullptr);
+// The static device scratch of the entry points that do not allocate:
+// kScratchBytes per device, its address on the current device in *out.
+constexpr size_t kScratchBytes = 4u << 20;
+fd_status scratch_ptr(void **out);
 fd_status copy_block(int64_t D, int n, const double *src, int64_t lds, double *dst, int64_t ldd, hipStream_t s);
 fd_status copy_rows(int64_t D, int64_t row_bytes, const void *src, int64_t src_ld_bytes, void *dst,
                     int64_t dst_ld_bytes, hipStream_t s);
