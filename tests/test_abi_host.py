@@ -311,3 +311,21 @@ def test_kpm_count_host_call():
     with pytest.raises(fd.FDError) as e:
         fd.window_count(np.zeros(8), 10, -0.5, 0.5)
     assert e.value.status == fd.FD_ERR_INVALID
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("model", ["anderson200", "hubbard14"])
+def test_full_size_matrices_bit_exact(model):
+    """The two full-size matrices the benchmarks run, exported from the
+    library's host builder, equal the oracle's CSR bit for bit: Anderson
+    L=200 (W=16.5, seed 1; D = 8,000,000) and the Hubbard ring L=14 (7+7,
+    U=8, ranked basis; D = 11,778,624)."""
+    if model == "anderson200":
+        m = fd.build_matrix("anderson", host_only=True, L=200, t=1.0, W=16.5, seed=1)
+        A = O.anderson(200, 1.0, 16.5, 1)
+    else:
+        m = fd.build_matrix("hubbard", host_only=True, L=14, n_up=7, n_dn=7, t=1.0, U=8.0)
+        A = O.hubbard(14, 7, 7, 1.0, 8.0)
+    assert (m.D, m.nnz) == (A.D, A.nnz)
+    _same_csr(m, A)
+    m.free()
