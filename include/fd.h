@@ -379,7 +379,11 @@ fd_status fd_lehmann(int64_t D, int32_t n, const double *V_dev, const double *W_
  * filter; SVQB needs only the ns x ns Gram matrix V^t V).  Columns whose
  * scaled Gram eigenvalue falls below 1e-14 of the largest are replaced by
  * seeded random vectors and orthogonalized again; *rank (may be NULL)
- * receives the number of columns kept.  ns <= 512.  Synchronizes stream.  */
+ * receives the number of columns kept.  The second pass of SVQB2 takes
+ * (V^t V)^-1/2 from its series when V^t V is within 1e-5 / ns of the
+ * identity entrywise (the same span; the basis differs from SVQB's by a
+ * rotation).  ns <= 512.  FD_ERR_BREAKDOWN for a non-finite block.
+ * Synchronizes stream.                                                    */
 fd_status fd_orthog(int64_t D, int32_t ns, double *V_dev, int64_t ldv, int32_t method,
                     uint64_t seed, int32_t *rank, void *stream);
 

@@ -260,13 +260,13 @@ fd_status cheb_filter_impl(fd_matrix m, fd_dtype dt, int nb, int nbund, void *V,
 
 // ---------------------------------------------------------- small buffers --
 struct Small {
-    double *G, *Q, *work, *theta, *rho;
+    double *G, *Q, *work, *theta, *rho, *E;
     int *keep, *ints;
 };
 
 fd_status small_buffers(int n, Small &b) {
     const size_t nn = (size_t)n * n;
-    const size_t bytes = (2 * nn + (2 * n + nn) + 2 * n) * sizeof(double) + (n + 8) * sizeof(int);
+    const size_t bytes = (4 * nn + (2 * n + nn) + 2 * n) * sizeof(double) + (n + 8) * sizeof(int);
     char *p = (char *)workspace(bytes, 3);
     if (!p) return fail(FD_ERR_OOM, "small workspace");
     b.G = (double *)p;
@@ -274,7 +274,8 @@ fd_status small_buffers(int n, Small &b) {
     b.work = b.Q + nn;
     b.theta = b.work + 2 * n + nn;
     b.rho = b.theta + n;
-    b.keep = (int *)(b.rho + n);
+    b.E = b.rho + n;  // two n x n matrices
+    b.keep = (int *)(b.E + 2 * nn);
     b.ints = b.keep + n;
     return FD_OK;
 }
@@ -306,6 +307,7 @@ fd_status orthog_impl(int64_t D, int ns, double *V, int64_t ldv, int method, uin
     FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
     FD_HIP(hipMemcpyAsync(&rank, b.ints, sizeof(int), hipMemcpyDeviceToHost, s));
     FD_HIP(hipStreamSynchronize(s));
+    if (rank < 0) return fail(FD_ERR_BREAKDOWN, "orthogonalization: non-finite Gram matrix");
     if (rank < ns) {
         // replace the directions that were clipped by fresh random vectors
         FD_TRY(refill_random(D, ns, V, ldv, b.keep, seed, s));
@@ -313,8 +315,16 @@ fd_status orthog_impl(int64_t D, int ns, double *V, int64_t ldv, int method, uin
         FD_TRY(svqb_transform(ns, b.G, b.Q, b.work, b.keep, b.ints + 1, s));
         FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
     }
+    // Second pass.  One pass leaves V^t V = I + E with |E| about kappa eps;
+    // when n max|E_ij| <= 1e-5 the pass takes Q = (I + E)^-1/2 from its
+    // series (the orthonormal basis nearest V: the span, all the next
+    // Rayleigh-Ritz step or filter depends on, is SVQB's), else SVQB again.
     FD_TRY(gram(D, ns, ns, V, ldv, V, ldv, b.G, ns, true, s));
-    FD_TRY(svqb_transform(ns, b.G, b.Q, b.work, b.keep, b.ints + 2, s));
+    FD_TRY(lowdin_transform(ns, b.G, b.E, b.E + (size_t)ns * ns, b.Q, b.ints + 3, s));
+    int okl = 0;
+    FD_HIP(hipMemcpyAsync(&okl, b.ints + 3, sizeof(int), hipMemcpyDeviceToHost, s));
+    FD_HIP(hipStreamSynchronize(s));
+    if (!okl) FD_TRY(svqb_transform(ns, b.G, b.Q, b.work, b.keep, b.ints + 2, s));
     FD_TRY(rotate(D, ns, ns, V, ldv, b.Q, ns, s));
     if (rank_out) *rank_out = rank;
     return FD_OK;

@@ -245,6 +245,9 @@ fd_status svqb_transform(int n, double *G, double *Q, double *work, int *keep, i
 // on a relative pivot below 1e-14 n, or (second_pass) when G is not within
 // 0.5 of the identity entrywise.
 fd_status cholqr_transform(int n, double *G, double *Q, int *ok_dev, bool second_pass, hipStream_t s);
+// Symmetric second pass Q = G^-1/2 = I - E/2 + 3 E^2 / 8 for G = I + E
+// (E, E2: n x n scratch); *ok_dev = 0 and Q untouched when n max|E_ij| > 1e-5.
+fd_status lowdin_transform(int n, const double *G, double *E, double *E2, double *Q, int *ok_dev, hipStream_t s);
 fd_status refill_random(int64_t D, int n, double *V, int64_t ldv, const int *keep,
                         uint64_t seed, hipStream_t s);
 fd_status fill_normal(int64_t D, int n, double *V, int64_t ldv, uint64_t seed, hipStream_t s);
