@@ -4,7 +4,7 @@
 A step is one FD outer iteration on the 3D Anderson lattice L=200 (D = 8.0M,
 7-point hopping t=1, periodic, disorder W=16.5 drawn with seed 1), target
 "nearest E = 0", with N_s search vectors in bundles of nb = 64 (default
-N_s = 128, two bundles; --ns 512 for the full search space):
+N_s = 64, one bundle; --ns 512 for the full search space):
   coefficients (Jackson-damped delta at E=0, degree 500, host)
   -> Chebyshev filter (500 fused SpMMV steps per bundle)
   -> SVQB2 orthogonalization (MFMA Gram + GPU Jacobi + MFMA rotation)
@@ -146,6 +146,22 @@ def fd_runs(args, fd, np):
         res["speedup_mixed_over_fp64"] = round(res["fp64"]["t_total_s"] / res["mixed"]["t_total_s"], 3)
         log("FD %s: mixed/FP64 speedup %.3f, max |dlambda|/||H|| %.2e, E=0 found %s"
             % (name, res["speedup_mixed_over_fp64"], res["mixed_vs_fp64_max_rel_eval_diff"], res["E0_found"]))
+        if mh.D <= 100_000:
+            # the same solves with CholQR2 orthogonalization (SVQB2 where a
+            # Cholesky pass fails); eigenvalues against the SVQB2 FP64 run
+            res["cholqr2"] = {}
+            for prec, label in ((0, "fp64"), (1, "mixed")):
+                r = fd.solve(mh, lo, hi, nt, nsr, nbr, deg, max_iter=40, tol=1e-9, precision=prec, V0=V0,
+                             seed=0, want_vectors=False, adapt=args.adapt, ortho=fd.FD_ORTHO_CHOLQR2)
+                st = r.stats
+                res["cholqr2"][label] = {
+                    "converged": r.status == fd.FD_OK, "eigenpairs_per_s": round(nt / st["t_total"], 4),
+                    "t_total_s": round(st["t_total"], 3), "iters": st["iters"], "spmmv": st["spmmv_count"],
+                    "t_filter_s": round(st["t_filter"], 3), "t_orthog_s": round(st["t_orthog"], 3),
+                    "t_rr_s": round(st["t_rr"], 3), "max_resid_rel": st["max_resid"] / st["norm_H"],
+                    "max_rel_eval_diff_vs_svqb2_fp64": float(np.abs(r.evals - e64).max() / normH)
+                    if r.evals.size == e64.size else None}
+                log("FD %s %s CholQR2: %s" % (name, label, res["cholqr2"][label]))
         fdres[name] = res
         del mh
     return fdres
@@ -163,6 +179,8 @@ def batch_runs(args, fd, np, torch):
     from fd_inputs import anderson_batch
     out = {}
     ns, degree = 64, 200
+    # one line per batched FD iteration on stderr (the full-size solve runs for minutes)
+    os.environ["FD_TRACE"] = "1"
     inst = anderson_batch(range(100, 196))
     t0 = time.time()
     mats = [fd.build_matrix(**q) for q in inst]
@@ -445,7 +463,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, default=200)
     ap.add_argument("--nb", type=int, default=64)
-    ap.add_argument("--ns", type=int, default=128)
+    ap.add_argument("--ns", type=int, default=64)
     ap.add_argument("--degree", type=int, default=500)
     ap.add_argument("--fmt", choices=["csr", "sell", "pencil"], default="csr",
                     help="storage / walk of the Anderson matrix (pencil: (x, y) tiles of C x sigma over all z)")
@@ -488,7 +506,8 @@ def main():
                          "FP64 and FP32, in the --hub-fmt storage and --hub-order labels; prints the sizes")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for hardware counters: one 1 GiB STREAM copy, then one degree-12 "
-                         "filter on one nb=64 FP64 bundle of the workload; prints the sizes and exits")
+                         "filter and five plain SpMMVs on one nb=64 FP64 bundle of the workload; prints the sizes "
+                         "and exits")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -563,12 +582,15 @@ def main():
         V1 = torch.randn((D, nb), generator=g, dtype=torch.float64, device=dev)
         Z1, Z2 = torch.empty_like(V1), torch.empty_like(V1)
         fd.cheb_filter(m, V1, fd.cheb_coeffs(1, beta, 0.0, 12), alpha, beta, Z1, Z2, nb, stream=stream)
+        for _ in range(5):  # plain SpMMV (MODE 0), same launch shape
+            fd.spmmv(m, V1, Z1, stream=stream)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_sample": True, "launch_shape": list(shape), "copy_bytes_read": n * 8,
                           "copy_bytes_written": n * 8,
-                          "launches_mode5": 5, "launches_mode4": 5,
+                          "launches_mode5": 5, "launches_mode4": 5, "launches_mode0": 5,
                           "algorithmic_bytes_mode5": fused_bytes(nnz, D, nb, 8, 5),
                           "algorithmic_bytes_mode4": fused_bytes(nnz, D, nb, 8, 3),
+                          "algorithmic_bytes_mode0": spmmv_bytes(nnz, D, nb, 8),
                           "D": D, "nnz": nnz, "nb": nb}), flush=True)
         return
     shape = fd.autotune(m, "f64", nb, stream=stream)
@@ -589,7 +611,7 @@ def main():
         e1.record(stream)
         fd.orthog(V, fd.FD_ORTHO_SVQB2, seed=7, stream=stream)
         th, rho = fd.rayleigh_ritz(m, V, W, nb, stream=stream)
-        order = np.argsort(np.abs(th), kind="stable")[:128]
+        order = np.argsort(np.abs(th), kind="stable")[:min(128, ns)]
         torch.cuda.synchronize()
         if record is not None:
             record.append(e0.elapsed_time(e1) * 1e-3)
@@ -605,8 +627,8 @@ def main():
     ts = time.perf_counter()
     for i in range(args.steps):
         th, rho = step(filt_times)
-        log("step %d: filter %.3fs, min |theta| %.3e, max rho(128 nearest 0) %.3e"
-            % (i, filt_times[-1], np.abs(th).min(), rho.max()))
+        log("step %d: filter %.3fs, min |theta| %.3e, max rho(%d nearest 0) %.3e"
+            % (i, filt_times[-1], np.abs(th).min(), len(th), rho.max()))
     torch.cuda.synchronize()
     te = time.perf_counter()
     t_step = (te - ts) / args.steps
@@ -645,7 +667,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "anderson3d_L%d_W16.5_seed1" % L, "D": D, "nnz": nnz,
                       "n_search": ns, "nb": nb, "degree": degree, "format": args.fmt, "site_order": site_order,
-                      "target": "128 pairs nearest E=0 (damped delta)", "parallelism": "single GPU",
+                      "target": "%d pairs nearest E=0 (damped delta)" % min(128, ns), "parallelism": "single GPU",
                       "launch_shape": list(shape)},
            "roofline": roofline,
            "hbm_frac_of_step": round(value / HBM_PEAK_GBS, 4)}

@@ -458,10 +458,14 @@ fd_status fd_lanczos(fd_matrix m, int32_t k, uint64_t seed, double *theta_host, 
  * coefficients.  Outputs: evals_host[N_t] ascending, evecs_dev (device
  * D x N_t, ld N_t) or NULL, resid_host[N_t] or NULL, stats or NULL.  Returns
  * FD_ERR_NOT_CONVERGED (outputs written) if max_iter is reached, or
- * earlier once the FP64 filter stagnates: the largest residual of the
- * targets has not fallen below 0.9 of its best value for 30 iterations.
+ * earlier once the FP64 filter stagnates: for 60 iterations the largest
+ * residual of the targets has not fallen below 0.9 of its best value and
+ * the count of converged pairs has not risen above its best.
  * Non-finite data anywhere in the iteration (e.g. NaN in V0_host, or a
- * filter that overflowed) give FD_ERR_BREAKDOWN.                           */
+ * filter that overflowed) give FD_ERR_BREAKDOWN.  Progress: with the
+ * environment variable FD_TRACE=1 fd_solve and fd_solve_batch write one
+ * JSON line per outer iteration to stderr; FD_TRACE_FILE=path appends the
+ * same lines to that file.                                                 */
 fd_status fd_solve(fd_matrix m, const fd_solve_params *params, const double *V0_host,
                    double *evals_host, double *evecs_dev, double *resid_host,
                    fd_solve_stats *stats);

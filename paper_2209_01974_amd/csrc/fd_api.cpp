@@ -408,6 +408,30 @@ double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// FD_TRACE=1: the solvers write one JSON line per outer iteration to
+// stderr; FD_TRACE_FILE: the same lines appended to that file (flushed line
+// by line)
+bool trace_on() {
+    const char *tr = std::getenv("FD_TRACE");
+    const char *trf = std::getenv("FD_TRACE_FILE");
+    return (tr && tr[0] == '1') || (trf && trf[0]);
+}
+
+void trace_line(const char *line) {
+    const char *tr = std::getenv("FD_TRACE");
+    const char *trf = std::getenv("FD_TRACE_FILE");
+    if (tr && tr[0] == '1') {
+        std::fputs(line, stderr);
+        std::fflush(stderr);
+    }
+    if (trf && trf[0]) {
+        if (FILE *f = std::fopen(trf, "a")) {
+            std::fputs(line, f);
+            std::fclose(f);
+        }
+    }
+}
+
 // Ritz values in the window nearest tau (ties: lower value first).
 std::vector<int> select_targets(const std::vector<double> &th, double lo, double hi, int nt) {
     const double tau = 0.5 * (lo + hi);
@@ -1283,14 +1307,15 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     bool fp32 = P->precision == 1;
     // FD_TRACE=1: one JSON line per outer iteration on stderr; FD_TRACE_FILE:
     // the same lines appended to that file (flushed line by line)
-    const char *tr = std::getenv("FD_TRACE");
-    const char *trf = std::getenv("FD_TRACE_FILE");
-    const bool trace = (tr && tr[0] == '1') || (trf && trf[0]);
+    const bool trace = trace_on();
     double prev_max = INFINITY;
-    // stagnation: the largest residual of the targets has not dropped below
-    // 0.9 of its best value for kStall iterations (FP64 filter)
-    constexpr int kStall = 30;
+    // stagnation: for kStall iterations (FP64 filter) the largest residual
+    // of the targets has not dropped below 0.9 of its best value and no more
+    // pairs have converged than before (a new target entering the set can
+    // hold the largest residual up while the others converge)
+    constexpr int kStall = 60;
     double best_max = INFINITY;
+    int best_conv = 0;
     int stall = 0;
     bool stagnated = false;
     const double tol = P->tol * normH;
@@ -1340,20 +1365,12 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
                           "\"t_orthog\": %.3f, \"t_rr\": %.3f, \"lehmann_r\": %s, \"t\": %.3f}\n",
                           it, (long long)D, mxs, (int)sel.size(), st.n_conv, (int)fp32, (long long)st.spmmv_count,
                           st.t_filter, st.t_orthog, st.t_rr, lrs, now() - t0);
-            if (tr && tr[0] == '1') {
-                std::fputs(line, stderr);
-                std::fflush(stderr);
-            }
-            if (trf && trf[0]) {
-                if (FILE *f = std::fopen(trf, "a")) {
-                    std::fputs(line, f);
-                    std::fclose(f);
-                }
-            }
+            trace_line(line);
         }
         if (!fp32) {
-            if (mx < 0.9 * best_max) {
-                best_max = mx;
+            if (mx < 0.9 * best_max || st.n_conv > best_conv) {
+                best_max = std::min(best_max, mx);
+                best_conv = std::max(best_conv, (int)st.n_conv);
                 stall = 0;
             } else {
                 stall++;
@@ -1419,7 +1436,7 @@ fd_status fd_solve(fd_matrix m, const fd_solve_params *P, const double *V0, doub
     st.t_total = now() - t0;
     if (stats) *stats = st;
     if (!converged)
-        return fail(FD_ERR_NOT_CONVERGED, stagnated ? "fd_solve: stagnated (no 10% progress in 30 iterations)"
+        return fail(FD_ERR_NOT_CONVERGED, stagnated ? "fd_solve: stagnated (no 10% progress and no newly converged pair in 60 iterations)"
                                                     : "fd_solve: not converged within max_iter");
     return FD_OK;
 }
@@ -1959,6 +1976,14 @@ fd_status fd_solve_batch(fd_batch b, const fd_solve_params *P, const double *V0,
                 st[i].iters++;
             }
         bs.iters = it + 1;
+        if (trace_on()) {
+            char line[256];
+            std::snprintf(line, sizeof line,
+                          "{\"fd_batch_iter\": %d, \"instances\": %d, \"active_after\": %d, \"t_filter\": %.3f, "
+                          "\"t_orthog\": %.3f, \"t_rr\": %.3f, \"t\": %.3f}\n",
+                          it, n, n_active, bs.t_filter, bs.t_orthog, bs.t_rr, now() - t0);
+            trace_line(line);
+        }
     }
     // results: selected pairs of each instance sorted by eigenvalue
     bool all = true;

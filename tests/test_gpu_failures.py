@@ -57,7 +57,7 @@ def test_stagnation_stops_before_max_iter():
     m = fd.build_matrix("diagonal", diag=lam)
     r = fd.solve(m, -0.5, 0.5, 10, 20, 4, 60, max_iter=500, tol=1e-9, V0=start_block(1000, 20, 0))
     assert r.status == fd.FD_ERR_NOT_CONVERGED
-    assert 30 <= r.stats["iters"] < 200
+    assert 60 <= r.stats["iters"] < 200
 
 
 def test_cholqr2_falls_back_on_an_ill_conditioned_block():
