@@ -298,9 +298,11 @@ fd_status fd_pick_degree(fd_matrix m, double tau_lo, double tau_hi, int32_t n_ta
                          const float *params_dev, uint64_t seed, int32_t *degree, double *radius,
                          float *features_host, void *stream);
 
-/* Launch-shape autotuner: times the fused Chebyshev step of this matrix for
- * a handful of launch shapes (as in fd_spmmv_tune) on scratch blocks of
- * D x nb (allocated and freed here) and keeps the fastest in the handle for
+/* Launch-shape autotuner: times the fused Chebyshev steps of this matrix
+ * (a step with the V update followed by one without, as the filter
+ * alternates them; the better of two passes) for a handful of launch shapes
+ * (as in fd_spmmv_tune) on scratch blocks of D x nb (allocated and freed
+ * here) and keeps the fastest in the handle for
  * (dtype, nb); later calls on this matrix use it.  shape (10 ints, may be
  * NULL) receives order, xcd, iters, grid, nontemporal, wide, tile, shfl,
  * lpr, lds (lpr > 0: one vector on CSR with lpr lanes per row; lds 1: the

@@ -20,6 +20,7 @@
 // the streamed operands (y, v, z) use non-temporal loads and stores.  A
 // per-XCD row partition and a grid-stride order are available as tunables.
 #include <type_traits>
+#include <vector>
 
 #include "fd_internal.h"
 
@@ -476,39 +477,53 @@ fd_status autotune(DevMatrix &M, fd_dtype dt, int nb, hipStream_t s, SpmmvTune *
                                     : cands + sizeof(cands) / sizeof(cands[0]);
     const int lg = __builtin_ctz((unsigned)nb);
     const int di = dt == FD_F64 ? 0 : 1;
+    // timed on the filter's own pair of launches: the recurrence with the
+    // two-term V update (MODE 5) and the recurrence alone (MODE 4); two
+    // passes over the candidates, each keeping its better time
     SpmmvCall c;
-    c.mode = 3;
     c.nb = nb;
     c.x = buf; c.ldx = nb;
     c.z = (char *)buf + bytes; c.ldz = nb;
     c.y = (char *)buf + bytes; c.ldy = nb;
     c.v = (char *)buf + 2 * bytes; c.ldv = nb;
-    c.a = 0.5; c.b = 0.0; c.ct = 0.5;
-    // fewer repetitions for large matrices; at least 3
-    const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(20, (int64_t)4e9 / (int64_t)(bytes + 1)));
-    float best_ms = 1e30f;
-    SpmmvTune best = spmmv_tune();
+    c.a = 0.5; c.b = 0.0; c.ct = 0.5; c.cx = 0.25;
+    SpmmvCall c5 = c, c4 = c;
+    c5.mode = 5;
+    c4.mode = 4;
+    // fewer repetitions for large matrices; at least 2 pairs
+    const int reps = (int)std::max<int64_t>(2, std::min<int64_t>(10, (int64_t)2e9 / (int64_t)(bytes + 1)));
+    const int ncand = (int)(ce - cb);
+    std::vector<float> tbest(ncand, 1e30f);
     fd_status st = FD_OK;
-    for (const SpmmvTune *tp = cb; tp != ce; ++tp) {
-        const SpmmvTune &t = *tp;
-        if (t.wide && nb < 16) continue;
-        if (t.lpr && (nb != 1 || M.cshift != 0 || M.perm)) continue;
-        M.tune[di][lg] = t;
-        M.tuned[di][lg] = true;
-        st = launch_spmmv(M, dt, c, s);  // warm-up
-        if (st != FD_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(hipErrorUnknown, "autotune event"); break; }
-        for (int r = 0; r < reps && st == FD_OK; r++) st = launch_spmmv(M, dt, c, s);
-        if (st != FD_OK) break;
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = t;
+    for (int pass = 0; pass < 2 && st == FD_OK; pass++) {
+        for (int i = 0; i < ncand; i++) {
+            const SpmmvTune &t = cb[i];
+            if (t.wide && nb < 16) continue;
+            if (t.lpr && (nb != 1 || M.cshift != 0 || M.perm)) continue;
+            M.tune[di][lg] = t;
+            M.tuned[di][lg] = true;
+            st = launch_spmmv(M, dt, c5, s);  // warm-up
+            if (st != FD_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(hipErrorUnknown, "autotune event"); break; }
+            for (int r = 0; r < reps && st == FD_OK; r++) {
+                st = launch_spmmv(M, dt, c5, s);
+                if (st == FD_OK) st = launch_spmmv(M, dt, c4, s);
+            }
+            if (st != FD_OK) break;
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tbest[i] = std::min(tbest[i], ms);
         }
     }
+    SpmmvTune best = spmmv_tune();
+    float best_ms = 1e30f;
+    for (int i = 0; i < ncand; i++)
+        if (tbest[i] < best_ms) {
+            best_ms = tbest[i];
+            best = cb[i];
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
