@@ -143,8 +143,13 @@ fd_status upload(fd_matrix m) {
         std::copy(S.perm.begin(), S.perm.end(), perm.begin());
     }
     d.maxlen = 0;
-    for (size_t c = 0; c + 1 < ptr.size(); c++)
-        d.maxlen = std::max<int32_t>(d.maxlen, (int32_t)((ptr[c + 1] - ptr[c]) >> d.cshift));
+    d.minlen = INT32_MAX;
+    for (size_t c = 0; c + 1 < ptr.size(); c++) {
+        const int32_t len = (int32_t)((ptr[c + 1] - ptr[c]) >> d.cshift);
+        d.maxlen = std::max<int32_t>(d.maxlen, len);
+        d.minlen = std::min<int32_t>(d.minlen, len);
+    }
+    if (d.minlen > d.maxlen) d.minlen = d.maxlen;
     std::vector<float> v32(val->size());
     for (size_t i = 0; i < val->size(); i++) v32[i] = (float)(*val)[i];
     const size_t st = std::max<size_t>(1, (size_t)d.stored);
@@ -1490,7 +1495,12 @@ fd_status fd_batch_create(int32_t n_inst, const fd_matrix *mats, fd_batch *out) 
     BatchDev &d = b->dev;
     d.n_inst = n_inst;
     d.D = D;
-    for (int64_t row = 0; row < D; row++) d.maxlen = std::max<int32_t>(d.maxlen, (int32_t)(ptr[row + 1] - ptr[row]));
+    d.minlen = INT32_MAX;
+    for (int64_t row = 0; row < D; row++) {
+        d.maxlen = std::max<int32_t>(d.maxlen, (int32_t)(ptr[row + 1] - ptr[row]));
+        d.minlen = std::min<int32_t>(d.minlen, (int32_t)(ptr[row + 1] - ptr[row]));
+    }
+    if (d.minlen > d.maxlen) d.minlen = d.maxlen;
     fd_status st = FD_OK;
     auto put = [&](void **dst, const void *src, size_t bytes) {
         if (st != FD_OK) return;

@@ -33,6 +33,7 @@ struct BArgs {
     int64_t D;
     int32_t k, mstride;
     int32_t maxlen;  // longest row of the union
+    int32_t uniform;  // every row holds maxlen entries
     int32_t cb_shift;  // log2(blocks per XCD chunk)
     const uint32_t *__restrict__ ptr;
     const uint32_t *__restrict__ col;
@@ -90,9 +91,14 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     // lane of the wave is still here; lanes of a row share its length)
     int32_t wl = (int32_t)(j1 - j0);
     if constexpr (G >= 4) {
+        if (p.uniform) {
+            wl = p.maxlen;  // rows of one length: no exchange needed
+        } else {
 #pragma unroll
-        for (int o = G; o < 64; o <<= 1) wl = max(wl, __shfl_xor(wl, o, 64));
-        wl = min(wl, p.maxlen);
+            for (int o = G; o < 64; o <<= 1) wl = max(wl, __shfl_xor(wl, o, 64));
+            // the same value in every lane: a scalar, so the round loop is scalar
+            wl = __builtin_amdgcn_readfirstlane(min(wl, p.maxlen));
+        }
     }
     if (!live) return;
     const int q = threadIdx.x % G;
@@ -208,6 +214,7 @@ fd_status launch_bt(const BatchDev &B, const T *val, const BatchCall &c, hipStre
     p.k = c.k;
     p.mstride = B.mstride;
     p.maxlen = B.maxlen;
+    p.uniform = B.minlen == B.maxlen ? 1 : 0;
     p.ptr = B.ptr; p.col = B.col; p.val = val; p.inst = B.inst;
     p.alpha = B.alpha; p.beta = B.beta; p.deg = B.deg; p.act = B.act; p.mu = B.mu;
     p.x = (const T *)c.x; p.ldx = c.ldx; p.bx = c.bx;

@@ -136,7 +136,8 @@ __device__ __forceinline__ int32_t wave_len(int32_t len, int32_t maxlen) {
         int32_t w = len;
 #pragma unroll
         for (int o = G; o < 64; o <<= 1) w = max(w, __shfl_xor(w, o, 64));
-        return min(w, maxlen);
+        // the same value in every lane: a scalar, so the round loop is scalar
+        return __builtin_amdgcn_readfirstlane(min(w, maxlen));
     }
 }
 

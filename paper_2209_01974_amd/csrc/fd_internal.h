@@ -103,6 +103,7 @@ struct DevMatrix {
     int32_t cshift = 0;
     int64_t nslots = 0;        // D rounded up to a multiple of C
     int32_t maxlen = 0;        // longest row (C = 1) or chunk
+    int32_t minlen = 0;        // shortest row (C = 1) or chunk
     int64_t stored = 0;        // value slots incl. padding
     uint32_t *ptr = nullptr;   // nchunks + 1
     uint32_t *col = nullptr;   // stored
@@ -175,6 +176,7 @@ struct BatchDev {
     int64_t D = 0;
     uint32_t *ptr = nullptr, *col = nullptr;  // D + 1, nnz (columns already shifted)
     int32_t maxlen = 0;                       // longest row
+    int32_t minlen = 0;                       // shortest row
     // launch shape per dtype and log2(nb) (fd_batch_autotune): rows per XCD
     // chunk (a power of two, 0: 1024) and the entry loop (1: permute rounds
     // of 4 entries, 2: of 8 with 8 or more lanes per row)

@@ -51,6 +51,7 @@ struct KArgs {
     int32_t order;     // 0: a block walks `iters` consecutive groups; 1: grid-stride
     int32_t sg;        // xcd == 2: logical blocks per super-group
     int32_t maxlen;    // longest row (CSR) or chunk (SELL)
+    int32_t uniform;   // every row (chunk) holds maxlen entries
     const T *x; int64_t ldx, bx;
     T *y; int64_t ldy, by;
     const T *z; int64_t ldz, bz;
@@ -117,7 +118,8 @@ __device__ __forceinline__ void block_groups(const KArgs<T> &p, int64_t &g0, int
     }
 }
 
-template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, int SH>
+// UNI: every row (chunk) holds p.maxlen entries (no wave exchange needed)
+template <typename T, int VEC, int G, int MODE, bool PERM, bool NT, int SH, bool UNI>
 __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int RPB = 256 / G;
@@ -131,32 +133,49 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
     const uint32_t step = 1u << p.cshift;
     for (int64_t g = g0; g < g1; g += gstep) {
         const int64_t s = g * RPB + grp;
-        // every lane of the block reaches this point (the loop bounds are
-        // per block), so the wave can agree on its longest row below
-        const bool in = s < p.nslots;
-        uint32_t len = 0, base = 0;
-        int64_t row = -1;
-        if (in) {
+        uint32_t len, base, wlen;
+        int64_t row;
+        V zi = (V)0, vi = (V)0;
+        T *vr = nullptr;
+        if constexpr (SH == 0 || UNI) {
+            // no exchange between the rows of the wave (broadcast loop, or
+            // rows of one length: the permute rounds run to maxlen), so a
+            // lane may leave at once
+            if (s >= p.nslots) break;
             const int64_t c = s >> p.cshift;
             const uint32_t p0 = p.ptr[c];
             len = (p.ptr[c + 1] - p0) >> p.cshift;
             base = p0 + (uint32_t)(s & (step - 1));
             row = PERM ? (int64_t)p.perm[s] : s;
-        }
-        if (row < 0) len = 0;
-        // load rounds of the permute loop: the longest row of this wave
-        // (lanes of a row share len, so only the rows are compared)
-        uint32_t wlen = len;
-        if constexpr (SH != 0) {
+            if (row < 0) continue;  // padding slot past D
+            wlen = (uint32_t)p.maxlen;
+        } else {
+            // every lane of the block reaches this point (the loop bounds
+            // are per block), so the wave can agree on its longest row
+            const bool in = s < p.nslots;
+            len = 0;
+            base = 0;
+            row = -1;
+            if (in) {
+                const int64_t c = s >> p.cshift;
+                const uint32_t p0 = p.ptr[c];
+                len = (p.ptr[c + 1] - p0) >> p.cshift;
+                base = p0 + (uint32_t)(s & (step - 1));
+                row = PERM ? (int64_t)p.perm[s] : s;
+            }
+            if (row < 0) len = 0;
+            // load rounds of the permute loop: the longest row of this wave
+            // (lanes of a row share len, so only the rows are compared)
+            wlen = len;
 #pragma unroll
             for (int o = G; o < 64; o <<= 1) wlen = max(wlen, (uint32_t)__shfl_xor((int)wlen, o, 64));
-            wlen = min(wlen, (uint32_t)p.maxlen);
+            // the same value in every lane: make it a scalar, so that the
+            // round loop below is a scalar loop
+            wlen = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(wlen, (uint32_t)p.maxlen));
+            if (!in) break;
+            if (row < 0) continue;  // padding slot past D
         }
-        if (!in) break;
-        if (row < 0) continue;  // padding slot past D
         // streamed operands first: their latency overlaps the gather chain
-        V zi = (V)0, vi = (V)0;
-        T *vr = nullptr;
         if constexpr (MODE >= 2) {
             vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
             if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
@@ -333,6 +352,7 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     p.nslots = M.nslots;
     p.cshift = M.cshift;
     p.maxlen = M.maxlen;
+    p.uniform = M.minlen == M.maxlen ? 1 : 0;
     constexpr int RPB = 256 / G;
     const int lg = __builtin_ctz((unsigned)c.nb);
     const int di = std::is_same<T, double>::value ? 0 : 1;
@@ -400,11 +420,14 @@ fd_status launch_t(const DevMatrix &M, const T *val, const SpmmvCall &c, hipStre
     // each form needs its lanes per row, else the next smaller one is used
     const int sh = (tn.shfl >= 2 && G >= 8) ? 2 : (tn.shfl != 0 && G >= 4 ? 1 : 0);
     constexpr int S1 = G >= 4 ? 1 : 0, S2 = G >= 8 ? 2 : S1;
-#define FD_L(MODE, PERM, NT)                                                                            \
-    do {                                                                                                \
-        if (sh == 2) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S2>), grid, block, 0, s, p);  \
-        else if (sh == 1) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S1>), grid, block, 0, s, p); \
-        else hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, 0>), grid, block, 0, s, p);        \
+    const bool uni = p.uniform != 0;
+#define FD_L(MODE, PERM, NT)                                                                                  \
+    do {                                                                                                      \
+        if (sh == 2 && uni) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S2, true>), grid, block, 0, s, p); \
+        else if (sh == 2) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S2, false>), grid, block, 0, s, p); \
+        else if (sh == 1 && uni) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S1, true>), grid, block, 0, s, p); \
+        else if (sh == 1) hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, S1, false>), grid, block, 0, s, p); \
+        else hipLaunchKernelGGL((k_spmmv<T, VEC, G, MODE, PERM, NT, 0, false>), grid, block, 0, s, p);              \
     } while (0)
 #define FD_L2(MODE, PERM) \
     if (nt) FD_L(MODE, PERM, true); else FD_L(MODE, PERM, false)

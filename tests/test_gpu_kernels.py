@@ -212,7 +212,7 @@ def test_syev_parity(n):
 
 
 @pytest.mark.parametrize("method", [fd.FD_ORTHO_SVQB2, fd.FD_ORTHO_CHOLQR2])
-@pytest.mark.parametrize("D,ns", [(5000, 64), (20011, 128), (3000, 16), (40000, 256)])
+@pytest.mark.parametrize("D,ns", [(5000, 64), (20011, 128), (6000, 129), (3000, 16), (40000, 256), (2000, 1)])
 def test_orthog(method, D, ns):
     V = start_block(D, ns, 9) @ np.diag(np.logspace(0, -5, ns))
     Vd = dev(V)
