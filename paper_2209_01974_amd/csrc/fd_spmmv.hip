@@ -149,6 +149,12 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             row = PERM ? (int64_t)p.perm[s] : s;
             if (row < 0) continue;  // padding slot past D
             wlen = (uint32_t)p.maxlen;
+            // streamed operands first: their latency overlaps the gather chain
+            if constexpr (MODE >= 2) {
+                vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
+                if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+                if constexpr (MODE == 2 || MODE == 3 || MODE == 5) vi = lds<V, NT>(vr);
+            }
         } else {
             // every lane of the block reaches this point (the loop bounds
             // are per block), so the wave can agree on its longest row
@@ -162,6 +168,15 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
                 len = (p.ptr[c + 1] - p0) >> p.cshift;
                 base = p0 + (uint32_t)(s & (step - 1));
                 row = PERM ? (int64_t)p.perm[s] : s;
+                // streamed operands first: their latency overlaps the
+                // exchange below and the gather chain
+                if (row >= 0) {
+                    if constexpr (MODE >= 2) {
+                        vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
+                        if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
+                        if constexpr (MODE == 2 || MODE == 3 || MODE == 5) vi = lds<V, NT>(vr);
+                    }
+                }
             }
             if (row < 0) len = 0;
             // load rounds of the permute loop: the longest row of this wave
@@ -174,12 +189,6 @@ __global__ __launch_bounds__(256) void k_spmmv(KArgs<T> p) {
             wlen = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(wlen, (uint32_t)p.maxlen));
             if (!in) break;
             if (row < 0) continue;  // padding slot past D
-        }
-        // streamed operands first: their latency overlaps the gather chain
-        if constexpr (MODE >= 2) {
-            vr = p.v + bnd * p.bv + row * p.ldv + q * VEC;
-            if constexpr (MODE >= 3) zi = lds<V, NT>(p.z + bnd * p.bz + row * p.ldz + q * VEC);
-            if constexpr (MODE == 2 || MODE == 3 || MODE == 5) vi = lds<V, NT>(vr);
         }
         const T *xq = x + q * VEC;
         // the row's own x (the beta term): loaded with the streams, so that
