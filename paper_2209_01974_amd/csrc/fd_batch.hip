@@ -69,7 +69,8 @@ __device__ __forceinline__ V fmab(T a, V x, V acc) { return __builtin_elementwis
 //   odd k only when k is the instance's last step (v += mu_ik t)
 // SH: entry loop with 4 or more lanes per row; 1 permute rounds of 4
 // entries, 2 rounds of 8 (8 or more lanes per row).
-template <typename T, int VEC, int G, int MODE, int SH>
+// UNI: every row of the union holds p.maxlen entries (no wave exchange)
+template <typename T, int VEC, int G, int MODE, int SH, bool UNI>
 __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     typedef typename BV<T, VEC>::type V;
     constexpr int RPB = 256 / G;
@@ -86,21 +87,27 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     } else {
         live = live && p.k <= p.deg[i];
     }
-    const uint32_t j0 = live ? p.ptr[row] : 0, j1 = live ? p.ptr[row + 1] : 0;
-    // rounds of the permute loop: the longest live row of this wave (every
-    // lane of the wave is still here; lanes of a row share its length)
-    int32_t wl = (int32_t)(j1 - j0);
-    if constexpr (G >= 4) {
-        if (p.uniform) {
-            wl = p.maxlen;  // rows of one length: no exchange needed
-        } else {
+    uint32_t j0, j1;
+    int32_t wl;
+    if constexpr (G < 4 || UNI) {
+        // no exchange between the rows of the wave (no permute rounds, or
+        // rows of one length: the rounds run to maxlen)
+        if (!live) return;
+        j0 = p.ptr[row];
+        j1 = p.ptr[row + 1];
+        wl = G >= 4 ? p.maxlen : (int32_t)(j1 - j0);
+    } else {
+        j0 = live ? p.ptr[row] : 0;
+        j1 = live ? p.ptr[row + 1] : 0;
+        // rounds of the permute loop: the longest live row of this wave (every
+        // lane of the wave is still here; lanes of a row share its length)
+        wl = (int32_t)(j1 - j0);
 #pragma unroll
-            for (int o = G; o < 64; o <<= 1) wl = max(wl, __shfl_xor(wl, o, 64));
-            // the same value in every lane: a scalar, so the round loop is scalar
-            wl = __builtin_amdgcn_readfirstlane(min(wl, p.maxlen));
-        }
+        for (int o = G; o < 64; o <<= 1) wl = max(wl, __shfl_xor(wl, o, 64));
+        // the same value in every lane: a scalar, so the round loop is scalar
+        wl = __builtin_amdgcn_readfirstlane(min(wl, p.maxlen));
+        if (!live) return;
     }
-    if (!live) return;
     const int q = threadIdx.x % G;
     const int64_t bnd = blockIdx.y;
     const T *xq = p.x + bnd * p.bx + q * VEC;
@@ -192,18 +199,25 @@ __global__ __launch_bounds__(256) void k_batch(BArgs<T> p) {
     }
 }
 
-template <typename T, int VEC, int G, int SH>
-fd_status launch_bs(const BatchDev &B, const BArgs<T> &p, const BatchCall &c, const dim3 &grid, hipStream_t s) {
+template <typename T, int VEC, int G, int SH, bool UNI>
+fd_status launch_bu(const BArgs<T> &p, const BatchCall &c, const dim3 &grid, hipStream_t s) {
     switch (c.mode) {
-        case 0: hipLaunchKernelGGL((k_batch<T, VEC, G, 0, SH>), grid, dim3(256), 0, s, p); break;
-        case 1: hipLaunchKernelGGL((k_batch<T, VEC, G, 1, SH>), grid, dim3(256), 0, s, p); break;
-        case 2: hipLaunchKernelGGL((k_batch<T, VEC, G, 2, SH>), grid, dim3(256), 0, s, p); break;
-        case 3: hipLaunchKernelGGL((k_batch<T, VEC, G, 3, SH>), grid, dim3(256), 0, s, p); break;
-        case 5: hipLaunchKernelGGL((k_batch<T, VEC, G, 5, SH>), grid, dim3(256), 0, s, p); break;
+        case 0: hipLaunchKernelGGL((k_batch<T, VEC, G, 0, SH, UNI>), grid, dim3(256), 0, s, p); break;
+        case 1: hipLaunchKernelGGL((k_batch<T, VEC, G, 1, SH, UNI>), grid, dim3(256), 0, s, p); break;
+        case 2: hipLaunchKernelGGL((k_batch<T, VEC, G, 2, SH, UNI>), grid, dim3(256), 0, s, p); break;
+        case 3: hipLaunchKernelGGL((k_batch<T, VEC, G, 3, SH, UNI>), grid, dim3(256), 0, s, p); break;
+        case 5: hipLaunchKernelGGL((k_batch<T, VEC, G, 5, SH, UNI>), grid, dim3(256), 0, s, p); break;
         default: return fail(FD_ERR_INVALID, "batched SpMMV: bad mode");
     }
     FD_HIP(hipGetLastError());
     return FD_OK;
+}
+
+template <typename T, int VEC, int G, int SH>
+fd_status launch_bs(const BatchDev &B, const BArgs<T> &p, const BatchCall &c, const dim3 &grid, hipStream_t s) {
+    (void)B;
+    if (G >= 4 && p.uniform) return launch_bu<T, VEC, G, SH, true>(p, c, grid, s);
+    return launch_bu<T, VEC, G, SH, false>(p, c, grid, s);
 }
 
 template <typename T, int VEC, int G>
