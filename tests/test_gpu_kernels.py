@@ -559,3 +559,45 @@ def test_one_vector_lane_shared_rows(lpr, name):
                 assert relerr(V.cpu().double().numpy(), ref) <= tol, (deg, dt)
     finally:
         fd.spmmv_tune()
+
+
+@pytest.mark.parametrize("nb,shfl", [(8, 1), (16, 2), (64, 1), (64, 2)])
+def test_uniform_rows_variant_matches_the_wave_exchange(nb, shfl):
+    """Anderson rows all hold 7 entries, so the step kernel skips the
+    exchange of row lengths across the wave (a compile-time variant).  The
+    same matrix with one explicit zero added to row 0 has rows of two
+    lengths and takes the exchange.  The added entry contributes fma(0, x,
+    acc) = acc, so every output is bitwise equal; both agree with the
+    oracle's SpMMV and filter."""
+    A = O.anderson(12, 1.0, 5.0, 4)
+    m_u = fd.build_matrix("csr", csr=(A.rowptr, A.col, A.val))
+    # row 0: columns ascending with the diagonal; add column D-2 if absent
+    cols0 = list(A.col[A.rowptr[0]:A.rowptr[1]])
+    extra = next(c for c in range(A.D - 1, 0, -1) if c not in cols0)
+    rp = A.rowptr.copy()
+    rp[1:] += 1
+    c0 = np.array(sorted(cols0 + [extra]), np.uint32)
+    v0 = np.array([A.val[A.rowptr[0] + cols0.index(c)] if c in cols0 else 0.0 for c in c0])
+    col = np.concatenate([c0, A.col[A.rowptr[1]:]])
+    val = np.concatenate([v0, A.val[A.rowptr[1]:]])
+    m_n = fd.build_matrix("csr", csr=(rp, col, val))
+    X = dev(start_block(A.D, nb, 5))
+    Yu, Yn = torch.empty_like(X), torch.empty_like(X)
+    lo, hi = O.gershgorin(A)
+    alpha, beta = O.scaling(lo, hi)
+    mu = O.cheb_coeffs(1, beta, 0.0, 9)
+    Vu, Vn = dev(start_block(A.D, nb, 6)), dev(start_block(A.D, nb, 6))
+    W1, W2 = torch.empty_like(X), torch.empty_like(X)
+    try:
+        fd.spmmv_tune(0, 2, 1, 512, 1, 0, 0, shfl)
+        fd.spmmv(m_u, X, Yu)
+        fd.spmmv(m_n, X, Yn)
+        fd.cheb_filter(m_u, Vu, mu, alpha, beta, W1, W2, nb)
+        fd.cheb_filter(m_n, Vn, mu, alpha, beta, W1, W2, nb)
+        torch.cuda.synchronize()
+    finally:
+        fd.spmmv_tune()
+    assert torch.equal(Yu, Yn)
+    assert torch.equal(Vu, Vn)
+    assert relerr(Yu.cpu().numpy(), O.spmmv(A, start_block(A.D, nb, 5))) <= 1e-14
+    assert relerr(Vu.cpu().numpy(), O.cheb_filter(A, start_block(A.D, nb, 6), mu, alpha, beta)) <= 1e-12
