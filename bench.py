@@ -16,8 +16,9 @@ with kappa = 5 for the steps that update V and kappa = 3 for the others --
 V takes two terms every other step -- plus the dense passes) divided by the
 step's wall time.
 
-Extra fields: a SpMMV / filter bandwidth sweep over nb and precision with the
-device STREAM ceilings (copy, triad, read-only, write-only); the FD
+Extra fields: a SpMMV / filter bandwidth sweep over nb and precision, for
+the CSR matrix and the same matrix in SELL-32-1, with the device STREAM
+ceilings (copy, triad, read-only, write-only); the FD
 eigenpairs/s comparison FP64 vs mixed precision on the Hubbard ring L=8 and
 L=14 (the mixed-precision workload: 64 pairs in [-1, 1], per-pair errors of
 the mixed run against the FP64 run); the roofline of the dominant kernel
@@ -719,39 +720,50 @@ def main():
         log("STREAM copy %.0f GB/s, triad %.0f GB/s, read-only %.0f GB/s, write-only %.0f GB/s"
             % (out["stream_copy_GBs"], out["stream_triad_GBs"], out["stream_read_GBs"], out["stream_write_GBs"]))
         del a, b, c
-        for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
-            for w in (1, 4, 8, 16, 32, 64):
-                fd.autotune(m, "f64" if sv == 8 else "f32", w, stream=stream)
-                X = torch.empty((D, w), dtype=dt, device=dev).normal_()
-                Y = torch.empty_like(X)
-                for _ in range(3):
-                    fd.spmmv(m, X, Y, stream=stream)
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                reps = 20
-                e0.record(stream)
-                for _ in range(reps):
-                    fd.spmmv(m, X, Y, stream=stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ts_ = e0.elapsed_time(e1) * 1e-3 / reps
-                gbs = spmmv_bytes(nnz, D, w, sv) / ts_ / 1e9
-                # filter of degree 50 on one bundle of width w
-                Z1, Z2 = torch.empty_like(X), torch.empty_like(X)
-                mu = fd.cheb_coeffs(1, beta, 0.0, 50)
-                fd.cheb_filter(m, X, mu, alpha, beta, Z1, Z2, w, stream=stream)
-                e0.record(stream)
-                fd.cheb_filter(m, X, mu, alpha, beta, Z1, Z2, w, stream=stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                tf = e0.elapsed_time(e1) * 1e-3
-                fgbs = filter_bytes(nnz, D, w, sv, 50) / tf / 1e9
-                sweep.append({"dtype": "f64" if sv == 8 else "f32", "nb": w,
-                              "spmmv_us": round(ts_ * 1e6, 1), "spmmv_GBs": round(gbs, 1),
-                              "spmmv_frac": round(gbs / HBM_PEAK_GBS, 4),
-                              "filter_step_us": round(tf / 50 * 1e6, 1), "filter_GBs": round(fgbs, 1),
-                              "filter_frac": round(fgbs / HBM_PEAK_GBS, 4)})
-                log("sweep %s nb=%d: SpMMV %.0f GB/s, filter %.0f GB/s" % (sweep[-1]["dtype"], w, gbs, fgbs))
-                del X, Y, Z1, Z2
+        # the benchmark's matrix (CSR, tiled numbering), and the same matrix in
+        # SELL-32-1 (chunks of 32 rows, no sorting: the rows of a chunk read
+        # entry j from consecutive addresses), which serves small nb better
+        m_sell = fd.build_matrix("anderson", fmt="sell", C_=32, sigma=1, L=L, t=1.0, W=16.5, seed=1, tiles=tiles)
+        for fmt_name, mm in (("csr", m), ("sell-32-1", m_sell)):
+            for dt, sv in ((torch.float64, 8), (torch.float32, 4)):
+                for w in (1, 4, 8, 16, 32, 64):
+                    shape_w = fd.autotune(mm, "f64" if sv == 8 else "f32", w, stream=stream)
+                    X = torch.empty((D, w), dtype=dt, device=dev).normal_()
+                    Y = torch.empty_like(X)
+                    for _ in range(3):
+                        fd.spmmv(mm, X, Y, stream=stream)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    reps = 20
+                    e0.record(stream)
+                    for _ in range(reps):
+                        fd.spmmv(mm, X, Y, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ts_ = e0.elapsed_time(e1) * 1e-3 / reps
+                    # algorithmic bytes count the nnz entries (padding slots of
+                    # SELL are overhead; the lattice at L=200 has none)
+                    gbs = spmmv_bytes(nnz, D, w, sv) / ts_ / 1e9
+                    # filter of degree 50 on one bundle of width w
+                    Z1, Z2 = torch.empty_like(X), torch.empty_like(X)
+                    mu = fd.cheb_coeffs(1, beta, 0.0, 50)
+                    fd.cheb_filter(mm, X, mu, alpha, beta, Z1, Z2, w, stream=stream)
+                    e0.record(stream)
+                    fd.cheb_filter(mm, X, mu, alpha, beta, Z1, Z2, w, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    tf = e0.elapsed_time(e1) * 1e-3
+                    fgbs = filter_bytes(nnz, D, w, sv, 50) / tf / 1e9
+                    sweep.append({"format": fmt_name, "dtype": "f64" if sv == 8 else "f32", "nb": w,
+                                  "spmmv_us": round(ts_ * 1e6, 1), "spmmv_GBs": round(gbs, 1),
+                                  "spmmv_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                  "filter_step_us": round(tf / 50 * 1e6, 1), "filter_GBs": round(fgbs, 1),
+                                  "filter_frac": round(fgbs / HBM_PEAK_GBS, 4), "launch_shape": list(shape_w),
+                                  "stored_entries": mm.stored})
+                    log("sweep %s %s nb=%d: SpMMV %.0f GB/s, filter %.0f GB/s"
+                        % (fmt_name, sweep[-1]["dtype"], w, gbs, fgbs))
+                    del X, Y, Z1, Z2
+        del m_sell
+        torch.cuda.empty_cache()
         out["sweep"] = sweep
 
     # ---------------------------------------------------- FD eigenpairs/s ----
