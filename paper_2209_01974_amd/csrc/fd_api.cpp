@@ -516,11 +516,15 @@ fd_status lanczos_impl(const DevMatrix &M, int64_t xoff, int k, uint64_t seed, s
     DevBuf Q;
     FD_TRY(Q.alloc((size_t)(k + 1) * D * 8, "the Lanczos basis"));
     double *Qd = (double *)Q.p;
-    // small device buffers: c (k), partial sums (nblk k), T (k k), U (k k), w (k)
-    const size_t nsmall = (size_t)k + (size_t)nblk * k + 2 * (size_t)k * k + k;
+    // small device buffers: c (k, first Gram-Schmidt pass), c2 (k, second
+    // pass), c3 (1, squared norm) in a row, partial sums (nblk k), T (k k),
+    // U (k k), w (k)
+    const size_t nsmall = 2 * (size_t)k + 1 + (size_t)nblk * k + 2 * (size_t)k * k + k;
     double *c = (double *)workspace(nsmall * sizeof(double), 9);
     if (!c) return fail(FD_ERR_OOM, "Lanczos: workspace");
-    double *P = c + k, *T = P + (size_t)nblk * k, *U = T + (size_t)k * k, *w = U + (size_t)k * k;
+    double *c2 = c + k, *c3 = c2 + k;
+    double *P = c3 + 1, *T = P + (size_t)nblk * k, *U = T + (size_t)k * k, *w = U + (size_t)k * k;
+    std::vector<double> hb(2 * (size_t)k + 1);
     auto norm_of = [&](const double *v, double &out) -> fd_status {
         FD_TRY(lz_dots(D, 1, v, v, c, P, nblk, s));
         double h = 0.0;
@@ -546,15 +550,19 @@ fd_status lanczos_impl(const DevMatrix &M, int64_t xoff, int k, uint64_t seed, s
         call.y = wv;
         call.ldy = 1;
         FD_TRY(launch_spmmv(M, FD_F64, call, s));
-        for (int pass = 0; pass < 2; pass++) {
-            FD_TRY(lz_dots(D, j + 1, Qd, wv, c, P, nblk, s));
-            FD_TRY(lz_sub(D, j + 1, Qd, c, wv, s));
-            double cj = 0.0;
-            FD_HIP(hipMemcpyAsync(&cj, c + j, sizeof(double), hipMemcpyDeviceToHost, s));
-            FD_HIP(hipStreamSynchronize(s));
-            alpha[j] += cj;
-        }
-        FD_TRY(norm_of(wv, beta[j]));
+        // two Gram-Schmidt passes (coefficients in c, then c2) and the norm
+        // (c3); one read-back per step: c[j], c2[j] and c3 lie in one range
+        FD_TRY(lz_dots(D, j + 1, Qd, wv, c, P, nblk, s));
+        FD_TRY(lz_sub(D, j + 1, Qd, c, wv, s));
+        FD_TRY(lz_dots(D, j + 1, Qd, wv, c2, P, nblk, s));
+        FD_TRY(lz_sub(D, j + 1, Qd, c2, wv, s));
+        FD_TRY(lz_dots(D, 1, wv, wv, c3, P, nblk, s));
+        const size_t nrd = 2 * (size_t)k + 1 - (size_t)j;
+        FD_HIP(hipMemcpyAsync(hb.data() + j, c + j, nrd * sizeof(double), hipMemcpyDeviceToHost, s));
+        FD_HIP(hipStreamSynchronize(s));
+        alpha[j] += hb[j];
+        alpha[j] += hb[k + j];
+        beta[j] = std::sqrt(hb[2 * (size_t)k]);
         double amax = 0.0;
         for (int i = 0; i <= j; i++) amax = std::max(amax, std::fabs(alpha[i]));
         if (!std::isfinite(beta[j]) || !std::isfinite(alpha[j]))
